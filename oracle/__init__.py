@@ -1,0 +1,301 @@
+"""FP64 CPU oracle for the Henry ensemble solves (TEST INFRASTRUCTURE).
+
+Only `tests/`, `__graft_entry__.smoke()` and the benchmark's `cpu_baseline`
+leg may import this package.  It wraps the plain C oracle
+(`henry_oracle.c`: Newton + exact Jacobian + banded LU, FP64) with ctypes
+and adds the MLMC estimator statistics (Sec. 3 of the paper) and a Halton
+quasi-Monte Carlo rule in plain numpy.  It shares no code with the HIP
+library in `paper_2302_07804_amd/`.
+
+Parity status of each function is listed in the module docstrings of the
+tests that pin it; every function here is pinned by at least one
+`-m "not gpu"` test.
+"""
+from __future__ import annotations
+
+import concurrent.futures as _cf
+import ctypes as _ct
+import os as _os
+import subprocess as _sp
+
+import numpy as np
+
+_HERE = _os.path.dirname(_os.path.abspath(__file__))
+_SRC = _os.path.join(_HERE, "henry_oracle.c")
+_LIB_PATH = _os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not _os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        _sp.check_call(["gcc", "-O3", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+                        "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"], cwd=_HERE)
+        _os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Phys(_ct.Structure):
+    _fields_ = [(k, _ct.c_double) for k in ("rho0", "rho1", "mu", "g", "D", "phi0", "k0", "q_in", "T")]
+
+
+def phys_struct(phys: dict) -> Phys:
+    return Phys(**{name: float(phys[name]) for name, _ in Phys._fields_})
+
+
+_D = _ct.POINTER(_ct.c_double)
+_I32 = _ct.c_int32
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = _ct.CDLL(_LIB_PATH)
+    P = _ct.POINTER(Phys)
+    lib.oracle_philox4x32_10.argtypes = [_ct.POINTER(_ct.c_uint32)] * 3
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_sample_xi.argtypes = [_ct.c_uint64, _I32, _ct.c_int64, _ct.c_int64, _I32, _D]
+    lib.oracle_sample_xi.restype = None
+    lib.oracle_fields_closed.argtypes = [P, _I32, _I32, _D, _D, _D, _D]
+    lib.oracle_residual.argtypes = [P, _I32, _I32, _I32, _D, _D, _ct.c_double, _D, _D, _D, _D, _D]
+    lib.oracle_jacobian_dense.argtypes = [P, _I32, _I32, _I32, _D, _D, _ct.c_double, _D, _D, _D, _D]
+    lib.oracle_band_solve_dense.argtypes = [_I32, _I32, _I32, _D, _D, _D, _I32]
+    lib.oracle_qoi.argtypes = [P, _I32, _I32, _D, _D]
+    lib.oracle_qoi.restype = _ct.c_double
+    lib.oracle_solve.argtypes = [P, _I32, _I32, _I32, _D, _D, _ct.c_double, _D, _D, _D, _D,
+                                 _ct.POINTER(_I32), _D, _D]
+    lib.oracle_adjoint.argtypes = [P, _I32, _I32, _I32, _D, _D, _ct.c_double, _D, _D, _D, _D]
+    lib.oracle_tangent.argtypes = [P, _I32, _I32, _I32, _D, _D, _ct.c_double, _D, _D, _ct.c_double,
+                                   _D, _D]
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with code {rc}")
+
+
+# ---------------------------------------------------------------- sampling
+def philox4x32_10(ctr, key):
+    lib = _load()
+    c = (_ct.c_uint32 * 4)(*ctr)
+    k = (_ct.c_uint32 * 2)(*key)
+    o = (_ct.c_uint32 * 4)()
+    lib.oracle_philox4x32_10(c, k, o)
+    return tuple(o)
+
+
+def sample_xi(seed: int, level: int, first: int, count: int, dim: int = 3) -> np.ndarray:
+    lib = _load()
+    out = np.empty((count, dim), np.float64)
+    lib.oracle_sample_xi(seed, level, first, count, dim, _dp(out))
+    return out
+
+
+def fields_closed(phys, nx, ny, xi):
+    lib = _load()
+    phi = np.empty((ny, nx)); K = np.empty((ny, nx)); q = np.empty(1)
+    _check(lib.oracle_fields_closed(_ct.byref(phys_struct(phys)), nx, ny, _dp(_f64(xi)), _dp(phi), _dp(K),
+                                    _dp(q)), "fields")
+    return phi, K, float(q[0])
+
+
+# ---------------------------------------------------------------- discrete operator
+def residual(phys, nsteps, phi, K, q, p, c, cn):
+    lib = _load()
+    ny, nx = phi.shape
+    Rp = np.empty((ny, nx)); Rc = np.empty((ny, nx))
+    _check(lib.oracle_residual(_ct.byref(phys_struct(phys)), nx, ny, nsteps, _dp(_f64(phi)), _dp(_f64(K)),
+                               float(q), _dp(_f64(p)), _dp(_f64(c)), _dp(_f64(cn)), _dp(Rp), _dp(Rc)), "residual")
+    return Rp, Rc
+
+
+def jacobian_dense(phys, nsteps, phi, K, q, p, c, cn):
+    lib = _load()
+    ny, nx = phi.shape
+    n2 = 2 * nx * ny
+    J = np.empty((n2, n2))
+    _check(lib.oracle_jacobian_dense(_ct.byref(phys_struct(phys)), nx, ny, nsteps, _dp(_f64(phi)),
+                                     _dp(_f64(K)), float(q), _dp(_f64(p)), _dp(_f64(c)), _dp(_f64(cn)),
+                                     _dp(J)), "jacobian")
+    return J
+
+
+def band_solve_dense(A, b, kl, ku, trans=False):
+    lib = _load()
+    A = _f64(A); b = _f64(b)
+    x = np.empty_like(b)
+    _check(lib.oracle_band_solve_dense(A.shape[0], kl, ku, _dp(A), _dp(b), _dp(x), int(trans)), "band solve")
+    return x
+
+
+def qoi(phys, phi, c):
+    lib = _load()
+    ny, nx = phi.shape
+    return lib.oracle_qoi(_ct.byref(phys_struct(phys)), nx, ny, _dp(_f64(phi)), _dp(_f64(c)))
+
+
+def cell_to_band(nx, ny):
+    """Permutation: band unknown u = 2*(i*ny + j) + v  <->  field index j*nx + i."""
+    i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    return (i * ny + j)  # [ny][nx] -> band cell index
+
+
+# ---------------------------------------------------------------- solves
+def solve(phys, nsteps, phi, K, q, c0=None, trajectory=False):
+    """Run the implicit time loop; returns dict(p, c, qoi, iters[, p_traj, c_traj])."""
+    lib = _load()
+    ny, nx = phi.shape
+    p = np.empty((ny, nx)); c = np.empty((ny, nx)); Q = np.empty(1)
+    iters = np.zeros(nsteps, np.int32)
+    pt = np.empty((nsteps + 1, ny, nx)) if trajectory else None
+    ct_ = np.empty((nsteps + 1, ny, nx)) if trajectory else None
+    rc = lib.oracle_solve(_ct.byref(phys_struct(phys)), nx, ny, nsteps, _dp(_f64(phi)), _dp(_f64(K)), float(q),
+                          _dp(None if c0 is None else _f64(c0)), _dp(p), _dp(c), _dp(Q),
+                          iters.ctypes.data_as(_ct.POINTER(_I32)), _dp(pt), _dp(ct_))
+    _check(rc, "solve")
+    out = dict(p=p, c=c, qoi=float(Q[0]), iters=iters)
+    if trajectory:
+        out.update(p_traj=pt, c_traj=ct_)
+    return out
+
+
+def solve_xi(phys, nx, ny, nsteps, xi):
+    phi, K, q = fields_closed(phys, nx, ny, xi)
+    return solve(phys, nsteps, phi, K, q)
+
+
+def solve_many(phys, jobs, threads=None):
+    """jobs: list of (nx, ny, nsteps, xi).  One job per thread (ctypes drops
+    the GIL during the C call).  Returns list of result dicts."""
+    threads = threads or len(_os.sched_getaffinity(0))
+    with _cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda jb: solve_xi(phys, *jb), jobs))
+
+
+def adjoint(phys, nsteps, phi, K, q):
+    """Returns (Q, dQ/dphi [ny][nx], dQ/dK [ny][nx], dQ/dq)."""
+    lib = _load()
+    ny, nx = phi.shape
+    Q = np.empty(1); gphi = np.empty((ny, nx)); gK = np.empty((ny, nx)); gq = np.empty(1)
+    _check(lib.oracle_adjoint(_ct.byref(phys_struct(phys)), nx, ny, nsteps, _dp(_f64(phi)), _dp(_f64(K)),
+                              float(q), _dp(Q), _dp(gphi), _dp(gK), _dp(gq)), "adjoint")
+    return float(Q[0]), gphi, gK, float(gq[0])
+
+
+def tangent(phys, nsteps, phi, K, q, v_phi, v_K, v_q):
+    lib = _load()
+    ny, nx = phi.shape
+    Q = np.empty(1); dQ = np.empty(1)
+    _check(lib.oracle_tangent(_ct.byref(phys_struct(phys)), nx, ny, nsteps, _dp(_f64(phi)), _dp(_f64(K)),
+                              float(q), _dp(_f64(v_phi)), _dp(_f64(v_K)), float(v_q), _dp(Q), _dp(dQ)), "tangent")
+    return float(Q[0]), float(dQ[0])
+
+
+def field_derivs_closed(phys, nx, ny, xi):
+    """d(phi)/d(xi1) and d(K)/d(xi2) per cell, d(q)/d(xi3): the derivatives
+    of the closed-form random fields."""
+    h = 1.0 / ny
+    x = (np.arange(nx) + 0.5) * h
+    y = -1.0 + (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    dphi = phys["phi0"] * 0.2 * np.cos(np.pi * X / 2) * np.cos(np.pi * Y)
+    K = phys["k0"] * np.exp(0.5 * xi[1] * np.sin(np.pi * X / 2))
+    dK = K * 0.5 * np.sin(np.pi * X / 2)
+    dq = phys["q_in"] * 0.2
+    return dphi, dK, dq
+
+
+def adjoint_xi(phys, nx, ny, nsteps, xi):
+    """Q, dQ/dxi (3,), dQ/dlog K per cell [ny][nx] for the closed-form fields."""
+    phi, K, q = fields_closed(phys, nx, ny, xi)
+    Q, gphi, gK, gq = adjoint(phys, nsteps, phi, K, q)
+    dphi, dK, dq = field_derivs_closed(phys, nx, ny, xi)
+    g = np.array([(gphi * dphi).sum(), (gK * dK).sum(), gq * dq])
+    return Q, g, gK * K
+
+
+# ---------------------------------------------------------------- MLMC statistics (Sec. 3)
+def inject(c_coarse, factor):
+    """Piecewise-constant injection of a cell field to a grid `factor` times
+    finer in each direction: c_fine(f*i + a, f*j + b) = c_coarse(i, j)."""
+    return np.repeat(np.repeat(c_coarse, factor, axis=-2), factor, axis=-1)
+
+
+def level_stats(g_fine, g_coarse=None):
+    """Sample mean and unbiased variance of Y_l = g_l - g_{l-1} over the
+    first axis (Def. eq:Yell with g_{-1} = 0).  Field-valued coarse samples
+    are injected to the fine grid first."""
+    g_fine = np.asarray(g_fine, np.float64)
+    if g_coarse is None:
+        Y = g_fine
+    else:
+        g_coarse = np.asarray(g_coarse, np.float64)
+        if g_fine.ndim == 3:
+            Y = g_fine - inject(g_coarse, g_fine.shape[-1] // g_coarse.shape[-1])
+        else:
+            Y = g_fine - g_coarse
+    m = Y.shape[0]
+    mean = Y.sum(axis=0) / m
+    var = ((Y - mean) ** 2).sum(axis=0) / (m - 1) if m > 1 else np.zeros_like(mean)
+    return mean, var
+
+
+def mlmc_estimate(level_means, level_vars, m):
+    """Telescoped E[g_L] = sum_l mean(Y_l) (eq:A), field means injected to
+    the finest grid, and the estimator variance sum_l V_l / m_l."""
+    L = len(level_means) - 1
+    finest = np.asarray(level_means[L])
+    if finest.ndim == 2:
+        E = np.zeros_like(finest)
+        var = np.zeros_like(finest)
+        for mean, v, mm in zip(level_means, level_vars, m):
+            f = finest.shape[-1] // np.asarray(mean).shape[-1]
+            E = E + inject(np.asarray(mean), f)
+            var = var + inject(np.asarray(v), f) / mm
+    else:
+        E = sum(level_means)
+        var = sum(np.asarray(v) / mm for v, mm in zip(level_vars, m))
+    return E, var
+
+
+def optimal_samples(V, s, eps2):
+    """m_l = ceil(eps^-2 sqrt(V_l/s_l) sum_i sqrt(V_i s_i)) (eq:M_ell) and
+    the total cost S = eps^-2 (sum_l sqrt(V_l s_l))^2."""
+    V = np.asarray(V, np.float64); s = np.asarray(s, np.float64)
+    tot = np.sqrt(V * s).sum()
+    m = np.ceil(np.sqrt(V / s) * tot / eps2).astype(np.int64)
+    return m, tot * tot / eps2
+
+
+# ---------------------------------------------------------------- QMC
+def radical_inverse(k: int, base: int) -> float:
+    f, r = 1.0, 0.0
+    while k > 0:
+        f /= base
+        r += f * (k % base)
+        k //= base
+    return r
+
+
+def halton(n: int, dim: int = 3, skip: int = 1) -> np.ndarray:
+    """First n Halton points (bases 2, 3, 5, ...) starting at index `skip`."""
+    bases = [2, 3, 5, 7, 11, 13][:dim]
+    return np.array([[radical_inverse(k, b) for b in bases] for k in range(skip, skip + n)])
