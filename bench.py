@@ -1,0 +1,285 @@
+"""Benchmark: batched MLMC ensemble of Henry solves on one MI355X.
+
+One step = one pass of the whole hot path over the L = 4 MLMC workload:
+levels 0..4 on grids 16x8/50 ... 256x128/800 steps with m = 4096, 1024, 256,
+64, 16 samples (every level > 0 solves its fine and coarse grid on shared
+samples): 6816 solves, 910,950,400 cell-steps, through `henry_solve_batch`
+(mixed precision: FP32 multigrid/line relaxation inside FP64 defect
+correction), then `mlmc_level_estimate` (level means/variances, telescoped
+E[c]).  Inputs (xi) are resident in HBM before the timed region.
+
+Printed: one JSON line with the metric (cell-steps/s of the batched path),
+the plain one-solve-at-a-time FP64 GPU path on a bounded sample (its rate
+is extrapolated to the workload's composition and labelled as such), the
+error of both against the FP64 oracle on a bounded sample of the same
+solves, the roofline of the dominant kernel and the oracle's own rate on
+the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import henry_inputs as hi  # noqa: E402
+
+M_PER_LEVEL = (4096, 1024, 256, 64, 16)
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_outer(elt: int) -> float:
+    """Bytes per fine cell that one defect-correction iteration must move
+    if every phase reads its operands once and writes its results once
+    (elt = bytes of the inner type).  Hierarchy phases carry the 4/3 factor
+    of the multigrid levels below the fine grid."""
+    f64 = 8
+    residual_p = 5 * f64 + 2 * f64 + 4 * elt          # p,c,c^n,phi,K in; R^p,R^c, te,tn,b,x out
+    coarsen_p = (2 * elt + 2 * elt / 4) / 3            # te,tn -> coarse levels
+    sweep_p = 4 * elt + elt                            # x,b,te,tn in; x out (both colours)
+    vcycle_p = (4 * sweep_p + (4 * elt + elt) + (elt + elt / 2) + (elt / 4 + 2 * elt)) * 4 / 3
+    update = 2 * f64 + elt                             # p (or c) read-modify-write, correction in
+    residual_c = 5 * f64 + f64 + 7 * elt               # same inputs; R^c out; acc,mx,my,dx,dy,b,x out
+    coarsen_c = (5 * elt + 5 * elt / 4) / 3
+    sweep_c = 2 * (7 * elt + elt)                      # x-lines then y-lines: 5 coefs, b, neighbours in; x out
+    vcycle_c = (2 * sweep_c + (7 * elt + elt) + (elt + elt / 2) + (elt / 4 + 2 * elt)) * 4 / 3
+    return residual_p + coarsen_p + vcycle_p + update + residual_c + coarsen_c + vcycle_c + update
+
+
+def algorithmic_bytes_per_step() -> float:
+    """Per fine cell and time step outside the iterations: c -> c^n copy
+    and the final (converged) residual evaluation."""
+    return 2 * 8 + (5 * 8 + 2 * 8 + 4 * 4)
+
+
+def workload():
+    solves, pairs = hi.mlmc_solves(M_PER_LEVEL)
+    return solves, pairs
+
+
+def xi_for(hm, solves):
+    """xi for every solve from the library's generator, keyed (seed, level, index)."""
+    out = np.empty((len(solves), 3))
+    cache = {}
+    for k, s in enumerate(solves):
+        if s.level not in cache:
+            m = max(x.index for x in solves if x.level == s.level) + 1
+            cache[s.level] = hm.henry_sample_xi(hi.SEED, s.level, 0, m, 3)
+        out[k] = cache[s.level][s.index]
+    return out
+
+
+def cpu_baseline_sample(solves, pairs):
+    """Bounded sample of the workload for the oracle: the first fine solves
+    of level 0, fine+coarse pairs of level 1, and one level-2 pair."""
+    pick = list(pairs[0][0][:48])
+    pick += list(pairs[1][0][:8]) + list(pairs[1][1][:8])
+    pick += list(pairs[2][0][:1]) + list(pairs[2][1][:1])
+    return pick
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps-per-launch", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the ensemble shards by sample across "
+              "GPUs by design but this build measures a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2302_07804_amd as hm
+    hm.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+
+    solves, pairs = workload()
+    grids = [(s.nx, s.ny, s.nsteps) for s in solves]
+    cell_steps = sum(s.cell_steps for s in solves)
+    xi_h = xi_for(hm, solves)
+    xi = torch.tensor(xi_h, dtype=torch.float64, device=dev)
+    ctx = hm.Context(hi.PHYS, 0)
+    opts = hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60, steps_per_launch=args.steps_per_launch)
+
+    # persistent buffers (allocated once, outside the timed region)
+    cells = sum(s.cells for s in solves)
+    wsb = hm.henry_workspace_bytes(grids, opts)
+    ws_raw = torch.empty(wsb // 8 + 64, dtype=torch.float64, device=dev)
+    off = (-ws_raw.data_ptr()) % 256 // 8
+    ws = ws_raw[off:off + (wsb + 7) // 8]
+    c_out = torch.empty(cells, dtype=torch.float64, device=dev)
+    qoi = torch.empty(len(solves), dtype=torch.float64, device=dev)
+    status = torch.empty(len(solves), dtype=torch.int32, device=dev)
+    iters = torch.empty(len(solves), dtype=torch.int32, device=dev)
+    offs = np.concatenate([[0], np.cumsum([s.cells for s in solves])])
+    L = len(M_PER_LEVEL) - 1
+    fine_grids = [hi.level_grid(l) for l in range(L + 1)]
+    c_fine, c_coarse, q_fine, q_coarse = [], [], [], []
+    for l, (fi, ci) in enumerate(pairs):
+        c_fine.append(c_out[offs[fi[0]]:offs[fi[-1] + 1]])
+        q_fine.append(qoi[fi[0]:fi[-1] + 1])
+        c_coarse.append(None if ci is None else c_out[offs[ci[0]]:offs[ci[-1] + 1]])
+        q_coarse.append(None if ci is None else qoi[ci[0]:ci[-1] + 1])
+    mean_Y = [torch.empty(g[0] * g[1], dtype=torch.float64, device=dev) for g in fine_grids]
+    var_Y = [torch.empty(g[0] * g[1], dtype=torch.float64, device=dev) for g in fine_grids]
+    qstats = torch.empty(2 * (L + 1), dtype=torch.float64, device=dev)
+    Ec = torch.empty(fine_grids[-1][0] * fine_grids[-1][1], dtype=torch.float64, device=dev)
+    var_est = torch.empty(2, dtype=torch.float64, device=dev)
+
+    def step(o=opts):
+        hm.henry_solve_batch(ctx, grids, hm.FIELD_CLOSED3, xi=xi, opts=o, c_out=c_out, qoi_out=qoi, status=status,
+                             iters=iters, workspace=ws)
+        hm.mlmc_level_estimate(ctx, fine_grids, M_PER_LEVEL, c_fine, c_coarse, q_fine, q_coarse, mean_Y, var_Y,
+                               qstats, Ec, var_est)
+
+    log(f"workload: {len(solves)} solves, {cell_steps} cell-steps, workspace {wsb / 2**20:.1f} MiB")
+    for w in range(args.warmup):
+        t = time.time()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {w}: {time.time() - t:.3f} s")
+    st = status.cpu().numpy()
+    if (st != 0).any():
+        log(f"WARNING: {int((st != 0).sum())} solves reported status != 0")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    ms_per_step = 1000.0 * wall / args.steps
+    value = cell_steps * args.steps / wall
+    log(f"timed {args.steps} steps: {wall:.3f} s wall ({ev_ms / args.steps:.1f} ms/step by events)")
+    iters_h = iters.cpu().numpy().astype(np.int64)
+    status_h = status.cpu().numpy()
+
+    # ---- dominant kernel: per-group HIP-event times of the solve kernels
+    prof_opts = hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60, profile=1)
+    step(prof_opts)
+    torch.cuda.synchronize()
+    groups = hm.henry_profile_last(ctx)
+    b_outer = algorithmic_bytes_per_outer(4)
+    b_step = algorithmic_bytes_per_step()
+    per_group = []
+    for g in groups:
+        members = [k for k, s in enumerate(solves) if s.nx == g["nx"]]
+        alg = sum(solves[k].cells * (b_outer * iters_h[k] + b_step * solves[k].nsteps + 16) for k in members)
+        per_group.append(dict(g, alg_bytes=alg, gbs=alg / (g["ms"] * 1e-3) / 1e9,
+                              mean_outer_per_step=float(np.mean([iters_h[k] / solves[k].nsteps for k in members]))))
+    for g in per_group:
+        log(f"group {g['nx']}x{g['ny']}: {g['nsolves']} solves, {g['ms']:.1f} ms, outer/step "
+            f"{g['mean_outer_per_step']:.2f}, algorithmic {g['gbs']:.0f} GB/s")
+    dom = max(per_group, key=lambda g: g["ms"])
+    achieved = sum(g["alg_bytes"] for g in per_group) / (sum(g["ms"] for g in per_group) * 1e-3) / 1e9
+
+    # ---- plain path: one solve per call, FP64 inner, bounded sample
+    plain = None
+    sample_idx = cpu_baseline_sample(solves, pairs)
+    plain_opts = hm.make_opts(prec=hm.PREC_FP64, tol=args.tol, max_outer=60)
+    if not args.no_plain:
+        per_grid_t = {}
+        reps = {16: 8, 32: 4, 64: 2, 128: 1, 256: 1}
+        for nx, rep in reps.items():
+            ks = [k for k, s in enumerate(solves) if s.nx == nx][:rep]
+            ts = []
+            for k in ks:
+                x1 = xi[k:k + 1].contiguous()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                hm.solve(ctx, [grids[k]], xi=x1, opts=plain_opts)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            per_grid_t[nx] = float(np.median(ts))
+            log(f"plain {nx}x{nx // 2}: {per_grid_t[nx] * 1e3:.1f} ms per solve")
+        t_plain = sum(per_grid_t[s.nx] for s in solves)
+        plain = dict(value=cell_steps / t_plain, unit="cell-steps/s", extrapolated=True,
+                     per_solve_ms={f"{nx}x{nx // 2}": round(v * 1e3, 3) for nx, v in per_grid_t.items()},
+                     note="median time of one-solve calls per grid, summed over the workload's 6816 solves")
+
+    # ---- oracle on a bounded sample (CPU baseline) and errors of both paths
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        jobs = [(solves[k].nx, solves[k].ny, solves[k].nsteps, xi_h[k]) for k in sample_idx]
+        t = time.perf_counter()
+        refs = oracle.solve_many(hi.PHYS, jobs, threads=threads)
+        tcpu = time.perf_counter() - t
+        cs_sample = sum(solves[k].cell_steps for k in sample_idx)
+        cpu = dict(value=cs_sample / tcpu, unit="cell-steps/s", cores=threads, kind="oracle",
+                   sample=f"{len(sample_idx)} solves of the workload (48 level-0, 8 level-1 pairs, 1 level-2 "
+                          f"pair; {cs_sample} cell-steps), one solve per thread, {tcpu:.1f} s wall")
+        c_all = c_out.cpu().numpy()
+        worst = 0.0
+        for k, r in zip(sample_idx, refs):
+            c = c_all[offs[k]:offs[k + 1]].reshape(solves[k].ny, solves[k].nx)
+            worst = max(worst, np.abs(c - r["c"]).max() / np.abs(r["c"]).max())
+        errs["batched_mixed_max_rel_c_err"] = worst
+        # E[c] of level 0 over the sampled solves
+        mean_gpu = np.mean([c_all[offs[k]:offs[k + 1]] for k in sample_idx[:48]], axis=0)
+        mean_ora = np.mean([r["c"].ravel() for r in refs[:48]], axis=0)
+        errs["batched_mixed_Ec_rel_err_level0_sample"] = float(np.abs(mean_gpu - mean_ora).max() / np.abs(mean_ora).max())
+        if not args.no_plain:
+            worst_p = 0.0
+            for k, r in list(zip(sample_idx, refs))[::7]:
+                out = hm.solve(ctx, [grids[k]], xi=xi[k:k + 1].contiguous(), opts=plain_opts)
+                c = out["c"].cpu().numpy().reshape(solves[k].ny, solves[k].nx)
+                worst_p = max(worst_p, np.abs(c - r["c"]).max() / np.abs(r["c"]).max())
+            errs["plain_fp64_max_rel_c_err"] = worst_p
+        log(f"oracle: {cpu['value']:.3e} cell-steps/s on {threads} threads; errors {errs}")
+
+    res = {
+        "metric": "Henry sample solves/s (cell-steps/s) batched vs plain, same 1e-5 E[c] error",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "mlmc_L4: 16x8/50, 32x16/100, 64x32/200, 128x64/400, 256x128/800 steps, "
+                               "m=4096,1024,256,64,16 (fine+coarse pairs), 6816 solves, 910950400 cell-steps",
+                   "precision": "FP32 V-cycles inside FP64 defect correction", "tol": args.tol,
+                   "steps_per_launch": args.steps_per_launch, "parallelism": "one workgroup per solve"},
+        "solves_per_s": len(solves) * args.steps / wall,
+        "plain": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "errors_vs_oracle": errs,
+        "nonconverged_solves": int((status_h != 0).sum()),
+        "mean_outer_iters_per_step": float(iters_h.sum() / sum(s.nsteps for s in solves)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "henry_solve_kernel<float>",
+                     "per_group": [{k: v for k, v in g.items()} for g in per_group],
+                     "dominant_group": f"{dom['nx']}x{dom['ny']}"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res, default=lambda o: o.item() if hasattr(o, "item") else str(o)))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * henry.h -- C ABI of the MI355X (gfx950) library for batched Henry
+ * saltwater-intrusion solves, the deterministic kernel that the multilevel
+ * Monte Carlo method of Litvinenko, Logashenko, Tempone, Vasilyeva and
+ * Wittum (arXiv 2302.07804) runs once per random sample and per level.
+ *
+ * Problem (Sec. 2.1 of the paper): on D = [0,2] x [-1,0] m, fluid mass
+ * conservation (e_cont_eq) and salt transport (e_tran_eq) with Darcy's law
+ * (e_Darcy_vel), rho(c) = rho0 + (rho1 - rho0) c (e_lin_density), diffusion
+ * phi D I (e_mol_diff); c = 0 at t = 0; right side x = 2: c = 1 and
+ * p = -rho1 g y; left side x = 0: fresh-water inflow rho q . e_x = rho0 q;
+ * top and bottom impermeable.  Porosity phi, permeability K and recharge q
+ * are the uncertain inputs (Sec. 2.2).  Discretisation: cell-centred finite
+ * volumes with donor-cell upwinding, harmonic face K and phi, arithmetic
+ * face density, implicit Euler with fixed tau = T / nsteps (Sec. 2.3).
+ *
+ * Conventions for every call:
+ *   - All array arguments marked "device" are device pointers on the
+ *     context's GPU, owned and allocated by the caller; nothing here frees
+ *     them.  Calls are asynchronous on `stream` (a hipStream_t; NULL = the
+ *     null stream) and validate every host-side argument before anything is
+ *     enqueued: on an error return nothing has been launched.
+ *   - A cell field is [ny][nx] row-major (x fastest), row 0 at the bottom
+ *     (y = -1 + h/2).  "Packed" per-solve fields are concatenated in solve
+ *     order: solve k starts at element sum_{m<k} nx_m * ny_m.
+ *   - Grids must satisfy nx == 2 * ny (square cells, h = 1/ny), ny a power
+ *     of two with 1 <= ny <= 512, nsteps >= 1.
+ *   - Return codes are the HENRY_* values below; no exception crosses the
+ *     ABI.  A context is not thread-safe; use one per host thread.
+ */
+#ifndef HENRY_H
+#define HENRY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HENRY_OK 0
+#define HENRY_EINVAL (-1)      /* invalid argument; nothing launched          */
+#define HENRY_ENOMEM (-2)      /* workspace too small / host allocation failed */
+#define HENRY_EHIP (-3)        /* a HIP runtime call failed                    */
+#define HENRY_ENOCONV (-4)     /* reported through status[]: see below         */
+#define HENRY_ENONFINITE (-5)  /* reported through status[]                    */
+
+/* Per-solve status values written to the device status[] array. */
+#define HENRY_STATUS_OK 0
+#define HENRY_STATUS_NOCONV 1      /* some step hit max_outer; integration went on */
+#define HENRY_STATUS_NONFINITE 2   /* a residual became NaN/Inf; the solve stopped */
+
+/* Physical constants, SI units (Table 1 of the paper lists rho0, mu, D,
+ * E[phi]; the workload fixes rho1, g, k0, q_in and T). */
+typedef struct {
+    double rho0, rho1, mu, g, D, phi0, k0, q_in, T;
+} henry_phys_t;
+
+/* One deterministic solve: grid and number of implicit Euler steps. */
+typedef struct {
+    int32_t nx, ny, nsteps, reserved; /* reserved must be 0 */
+} henry_grid_t;
+
+/* How the random inputs reach a solve (Sec. 2.2: porosity, permeability
+ * and recharge are uncertain).
+ *   CLOSED3:  xi[k][3] ~ U[-1,1]^3 per solve,
+ *             phi = phi0 (1 + 0.2 xi1 cos(pi x/2) cos(pi y)),
+ *             K = k0 exp(0.5 xi2 sin(pi x/2)), q = q_in (1 + 0.2 xi3),
+ *             evaluated at cell centres.
+ *   EXPLICIT: the caller passes packed per-cell phi and log K and a
+ *             per-solve recharge q[k] (m/s). */
+#define HENRY_FIELD_CLOSED3 0
+#define HENRY_FIELD_EXPLICIT 2
+
+/* Inner precision of the multigrid / line-relaxation preconditioner.  The
+ * outer nonlinear residual, the state, the buoyancy term and every
+ * reduction are FP64 in both modes. */
+#define HENRY_PREC_FP64 0
+#define HENRY_PREC_MIXED 1
+
+typedef struct {
+    int32_t prec;             /* HENRY_PREC_*                                   */
+    int32_t max_outer;        /* defect-correction iterations per step (>= 1)   */
+    double tol;               /* stop a step when max_P |R_P| tau/(h^2 phi_P rho0)
+                                 <= tol for both the fluid and the salt equation */
+    int32_t threads;          /* threads per solve-workgroup; 0 = tuned choice  */
+    int32_t steps_per_launch; /* 0 = whole time loop in one launch per grid
+                                 group; k > 0 = launches of k global steps, all
+                                 captured into one hipGraph and replayed        */
+    int32_t profile;          /* 1 = time each grid group's launches with HIP
+                                 events on the stream they run on; read with
+                                 henry_profile_last                              */
+    int32_t serial_groups;    /* 1 = run grid groups one after another on one
+                                 stream instead of concurrently                  */
+} henry_opts_t;
+
+/* Timing of one grid group of the last henry_solve_batch call made with
+ * opts.profile = 1 (complete once that call's work has finished). */
+typedef struct {
+    int32_t nx, ny, nsolves, launches;
+    int64_t cell_steps;      /* sum over the group's solves of nx*ny*nsteps */
+    double ms;               /* HIP-event time of the group's solve launches */
+} henry_group_time_t;
+
+typedef struct henry_ctx henry_ctx;
+
+const char* henry_strerror(int code);
+
+/* Create a context bound to HIP device `device` (the current device is
+ * restored on return).  `phys` is copied. */
+int henry_ctx_create(henry_ctx** out, const henry_phys_t* phys, int device);
+void henry_ctx_destroy(henry_ctx* ctx);
+
+/* Default options: mixed precision, max_outer 40, tol 1e-10, tuned threads,
+ * one launch per grid group. */
+void henry_opts_default(henry_opts_t* opts);
+
+/* Counter-based sample generator (Philox4x32-10, Salmon et al. SC'11).
+ * Host-side, writes count*dim doubles to out_host: component d of sample
+ * `first + s` of stream (seed, level) is built from Philox block
+ * counter = (d/2, level, index lo, index hi), key = (seed lo, seed hi):
+ * words (2e, 2e+1), e = d mod 2, form a 64-bit integer whose top 53 bits x
+ * give x * 2^-52 - 1 in [-1, 1).  Fine and coarse solves of one MLMC pair
+ * share the key, so they see the same xi (eq:A, Sec. 3). */
+int henry_sample_xi(uint64_t seed, int32_t level, int64_t first, int64_t count, int32_t dim,
+                    double* out_host);
+
+/* Workspace (device bytes) that henry_solve_batch needs for these solves. */
+int henry_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
+                          const henry_opts_t* opts, size_t* bytes_out);
+
+/* Batched forward solves.  Every solve k integrates its own grid for
+ * solves[k].nsteps implicit Euler steps to T; solves of different grids
+ * and step counts share one call.
+ *   solves   host [nsolves]
+ *   field    HENRY_FIELD_*
+ *   xi       device [nsolves][3] (CLOSED3) else ignored
+ *   phi,logk device packed per-cell fields (EXPLICIT) else ignored
+ *   qin      device [nsolves] recharge in m/s (EXPLICIT) else ignored
+ *   c0       device packed initial salt mass fraction, or NULL for c = 0
+ *   c_out    device packed c at T (FP64)
+ *   p_out    device packed p at T (FP64), or NULL
+ *   qoi_out  device [nsolves]: salt mass in x < 1 at T,
+ *            Q = h^2 sum_{x_i < 1} phi rho(c) c  (kg per m of depth)
+ *   status   device [nsolves] HENRY_STATUS_*
+ *   iters    device [nsolves] total outer iterations over all steps, or NULL
+ *   workspace, ws_bytes: device scratch of at least henry_workspace_bytes.
+ * Errors: HENRY_EINVAL (bad grid, NULL required pointer, opts out of range),
+ * HENRY_ENOMEM (ws_bytes too small), HENRY_EHIP. */
+int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                      const double* xi, const double* phi, const double* logk, const double* qin,
+                      const double* c0, const henry_opts_t* opts, double* c_out, double* p_out,
+                      double* qoi_out, int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes,
+                      void* stream);
+
+/* Per-group timings of the last profiled henry_solve_batch call: writes up
+ * to `cap` entries, returns the group count through *ngroups.  Synchronises
+ * with the recorded events (blocks the host until that work is done). */
+int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int32_t* ngroups);
+
+/* MLMC level-difference statistics (Sec. 3: eq:EgL / eq:A, Def. eq:Yell).
+ * For each level l = 0..L with m[l] samples on grid fine[l]:
+ *   Y_l = c_l - I c_{l-1}   (field; I = piecewise-constant injection from
+ *                            the coarse grid, which has half the cells per
+ *                            direction; Y_0 = c_0)
+ *   and Q_l - Q_{l-1} for the scalar QoI.
+ * Outputs (device, caller-owned):
+ *   mean_Y[l], var_Y[l]: [cells_l] sample mean and unbiased (m-1) variance
+ *   qstats: [L+1][2] mean and unbiased variance of the QoI difference
+ *   Ec_finest: [cells_L] telescoped E[c] = sum_l I_{l->L} mean_Y[l]
+ *   var_est: [2] sum_l V_l/m_l for the QoI, and max over cells of the
+ *            same sum for the field.
+ * c_fine[l] is [m_l][cells_l], c_coarse[l] is [m_l][cells_l / 4] (NULL at
+ * l = 0); q_fine[l], q_coarse[l] are [m_l] (q_coarse[0] NULL).  The pointer
+ * arrays themselves are host arrays of device pointers.  Sums run in a
+ * fixed order (deterministic); m[l] >= 2. */
+int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, const int32_t* m,
+                        const double* const* c_fine, const double* const* c_coarse,
+                        const double* const* q_fine, const double* const* q_coarse,
+                        double* const* mean_Y, double* const* var_Y, double* qstats, double* Ec_finest,
+                        double* var_est, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HENRY_H */

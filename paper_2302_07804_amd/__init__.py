@@ -1,0 +1,257 @@
+"""Python binding of the MI355X Henry-solve library (`libhenry.so`).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels
+behind the C ABI declared in `include/henry.h`.  PyTorch provides device
+memory and streams.  If the shared library is missing, importing works but
+every call raises `HenryLibraryMissing`: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libhenry.so")
+_SOURCES = [os.path.join(_HERE, "csrc", "henry_api.hip")]
+_DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlmc.hpp")] + \
+    [os.path.join(_ROOT, "include", "henry.h")]
+
+HENRY_OK, HENRY_EINVAL, HENRY_ENOMEM, HENRY_EHIP, HENRY_ENOCONV, HENRY_ENONFINITE = 0, -1, -2, -3, -4, -5
+STATUS_OK, STATUS_NOCONV, STATUS_NONFINITE = 0, 1, 2
+FIELD_CLOSED3, FIELD_EXPLICIT = 0, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+# every symbol the header declares
+EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opts_default", "henry_sample_xi",
+           "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "mlmc_level_estimate")
+
+
+class HenryLibraryMissing(RuntimeError):
+    pass
+
+
+class HenryError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {code} ({strerror(code) if _lib else 'library not loaded'})")
+        self.code = code
+
+
+def hipcc_command(out=LIB_PATH):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    return [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-command-line-argument",
+            "-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc"),
+            "-o", out] + _SOURCES
+
+
+def build() -> str:
+    """Compile libhenry.so for gfx950 (always recompiles)."""
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call(hipcc_command(tmp), cwd=_HERE)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Phys(ct.Structure):
+    _fields_ = [(k, ct.c_double) for k in ("rho0", "rho1", "mu", "g", "D", "phi0", "k0", "q_in", "T")]
+
+
+class Grid(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nsteps", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+class Opts(ct.Structure):
+    _fields_ = [("prec", ct.c_int32), ("max_outer", ct.c_int32), ("tol", ct.c_double), ("threads", ct.c_int32),
+                ("steps_per_launch", ct.c_int32), ("profile", ct.c_int32), ("serial_groups", ct.c_int32)]
+
+
+class GroupTime(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nsolves", ct.c_int32), ("launches", ct.c_int32),
+                ("cell_steps", ct.c_int64), ("ms", ct.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhenry.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HenryLibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime torch uses)
+    except ImportError:
+        pass
+    L = ct.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_double
+    L.henry_strerror.argtypes = [ct.c_int]
+    L.henry_strerror.restype = ct.c_char_p
+    L.henry_ctx_create.argtypes = [ct.POINTER(vp), ct.POINTER(Phys), ct.c_int]
+    L.henry_ctx_destroy.argtypes = [vp]
+    L.henry_ctx_destroy.restype = None
+    L.henry_opts_default.argtypes = [ct.POINTER(Opts)]
+    L.henry_opts_default.restype = None
+    L.henry_sample_xi.argtypes = [ct.c_uint64, i32, i64, i64, i32, ct.POINTER(ct.c_double)]
+    L.henry_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), ct.POINTER(ct.c_size_t)]
+    L.henry_solve_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), vp, vp,
+                                    vp, vp, vp, vp, ct.c_size_t, vp]
+    L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
+    L.mlmc_level_estimate.argtypes = [vp, i32, ct.POINTER(Grid), ct.POINTER(i32), ct.POINTER(vp), ct.POINTER(vp),
+                                      ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), vp, vp, vp, vp]
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().henry_strerror(code).decode()
+
+
+def _chk(rc, what):
+    if rc != HENRY_OK:
+        raise HenryError(rc, what)
+
+
+def grids(solves) -> ct.Array:
+    """[(nx, ny, nsteps), ...] -> henry_grid_t array."""
+    arr = (Grid * len(solves))()
+    for k, s in enumerate(solves):
+        arr[k].nx, arr[k].ny, arr[k].nsteps, arr[k].reserved = int(s[0]), int(s[1]), int(s[2]), 0
+    return arr
+
+
+def opts_default() -> Opts:
+    o = Opts()
+    lib().henry_opts_default(ct.byref(o))
+    return o
+
+
+def make_opts(**kw) -> Opts:
+    o = opts_default()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def henry_sample_xi(seed: int, level: int, first: int, count: int, dim: int = 3):
+    import numpy as np
+    out = np.empty((count, dim), np.float64)
+    _chk(lib().henry_sample_xi(seed, level, first, count, dim, out.ctypes.data_as(ct.POINTER(ct.c_double))),
+         "henry_sample_xi")
+    return out
+
+
+def henry_workspace_bytes(solves, opts: Opts | None = None, ctx=None) -> int:
+    g = grids(solves)
+    n = ct.c_size_t()
+    _chk(lib().henry_workspace_bytes(ctx, g, len(solves), ct.byref(opts) if opts else None, ct.byref(n)),
+         "henry_workspace_bytes")
+    return n.value
+
+
+class Context:
+    """Owns a henry_ctx (plans, tuned choices) bound to one device."""
+
+    def __init__(self, phys: dict, device: int = 0):
+        self.handle = ct.c_void_p()
+        p = Phys(**{name: float(phys[name]) for name, _ in Phys._fields_})
+        _chk(lib().henry_ctx_create(ct.byref(self.handle), ct.byref(p), device), "henry_ctx_create")
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().henry_ctx_destroy(self.handle)
+            self.handle = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _stream_of(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def henry_solve_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, c0=None,
+                      opts: Opts | None = None, c_out=None, p_out=None, qoi_out=None, status=None, iters=None,
+                      workspace=None, stream=None):
+    """Thin wrapper: tensors are device tensors owned by the caller."""
+    g = grids(solves)
+    rc = lib().henry_solve_batch(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk), _ptr(qin),
+                                 _ptr(c0), ct.byref(opts) if opts else None, _ptr(c_out), _ptr(p_out),
+                                 _ptr(qoi_out), _ptr(status), _ptr(iters), _ptr(workspace),
+                                 workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                 _stream_of(stream))
+    _chk(rc, "henry_solve_batch")
+
+
+def henry_profile_last(ctx: Context):
+    """Per-grid-group HIP-event timings of the last profiled batch."""
+    cap = 64
+    arr = (GroupTime * cap)()
+    n = ct.c_int32()
+    _chk(lib().henry_profile_last(ctx.handle, arr, cap, ct.byref(n)), "henry_profile_last")
+    return [dict(nx=g.nx, ny=g.ny, nsolves=g.nsolves, launches=g.launches, cell_steps=g.cell_steps, ms=g.ms)
+            for g in arr[:n.value]]
+
+
+def mlmc_level_estimate(ctx: Context, fine_grids, m, c_fine, c_coarse, q_fine, q_coarse, mean_Y, var_Y, qstats,
+                        Ec_finest, var_est, stream=None):
+    L = len(fine_grids) - 1
+    g = grids(fine_grids)
+    mm = (ct.c_int32 * (L + 1))(*[int(x) for x in m])
+    P = ct.c_void_p * (L + 1)
+    arr = lambda ts: P(*[(t.data_ptr() if t is not None else None) for t in ts])
+    rc = lib().mlmc_level_estimate(ctx.handle, L, g, mm, arr(c_fine), arr(c_coarse), arr(q_fine), arr(q_coarse),
+                                   arr(mean_Y), arr(var_Y), _ptr(qstats), _ptr(Ec_finest), _ptr(var_est),
+                                   _stream_of(stream))
+    _chk(rc, "mlmc_level_estimate")
+
+
+# ------------------------------------------------------------------ convenience layer
+def solve(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, c0=None, opts: Opts | None = None,
+          want_p=False, stream=None):
+    """Allocate outputs/workspace with torch and run one batch.
+    solves: list of (nx, ny, nsteps).  Returns dict of device tensors."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    opts = opts or opts_default()
+    cells = sum(int(s[0]) * int(s[1]) for s in solves)
+    ws_bytes = henry_workspace_bytes(solves, opts)
+    ws = torch.empty((ws_bytes + 255) // 256 * 256 // 8 + 32, dtype=torch.float64, device=dev)
+    # 256-byte aligned view
+    off = (-ws.data_ptr()) % 256 // 8
+    ws = ws[off:off + (ws_bytes + 7) // 8]
+    out = dict(c=torch.empty(cells, dtype=torch.float64, device=dev),
+               qoi=torch.empty(len(solves), dtype=torch.float64, device=dev),
+               status=torch.empty(len(solves), dtype=torch.int32, device=dev),
+               iters=torch.empty(len(solves), dtype=torch.int32, device=dev))
+    out["p"] = torch.empty(cells, dtype=torch.float64, device=dev) if want_p else None
+    field = FIELD_CLOSED3 if xi is not None else FIELD_EXPLICIT
+    henry_solve_batch(ctx, solves, field, xi=xi, phi=phi, logk=logk, qin=qin, c0=c0, opts=opts, c_out=out["c"],
+                      p_out=out["p"], qoi_out=out["qoi"], status=out["status"], iters=out["iters"], workspace=ws,
+                      stream=stream)
+    out["workspace"] = ws
+    return out
+
+
+def unpack(flat, solves):
+    """Split a packed per-solve field into a list of [ny][nx] views."""
+    res, off = [], 0
+    for s in solves:
+        n = int(s[0]) * int(s[1])
+        res.append(flat[off:off + n].view(int(s[1]), int(s[0])))
+        off += n
+    return res

@@ -1,0 +1,531 @@
+// henry_api.hip -- host side of the C ABI declared in include/henry.h.
+//
+// Validates every host argument before anything is enqueued, plans the
+// batch (groups of solves sharing a grid, largest work first), places each
+// solve's state in the caller's workspace, and launches the field and
+// solve kernels.  Groups run concurrently on the context's internal
+// streams, forked from and joined back into the caller's stream with
+// events; with steps_per_launch > 0 the whole lockstep time loop is
+// captured once into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "henry.h"
+#include "henry_device.hpp"
+#include "henry_mlmc.hpp"
+
+namespace {
+
+constexpr int kStreams = 4;
+constexpr size_t kLdsBudget = 96 * 1024;
+
+struct Group {
+    int nx, ny, threads;
+    std::vector<int> members;  // indices into the solve list
+    double cost;
+};
+
+struct PlanKey {
+    std::vector<int64_t> words;
+    bool operator==(const PlanKey& o) const { return words == o.words; }
+};
+
+}  // namespace
+
+struct henry_ctx {
+    int device = 0;
+    henry::Phys ph{};
+    hipStream_t streams[kStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t joins[kStreams] = {};
+    void* pinned = nullptr;      // host staging for descriptor tables
+    size_t pinned_bytes = 0;
+    hipEvent_t staging_done = nullptr;
+    std::map<long, int> tuned_threads;  // (nx, prec) -> threads
+    size_t lds_budget = 64 * 1024;
+    // profiling of the last batch
+    std::vector<henry_group_time_t> prof;
+    std::vector<hipEvent_t> prof_ev;  // 2 per group
+    // cached executable graph of the last chunked (lockstep) batch
+    hipGraphExec_t graph_exec = nullptr;
+    PlanKey graph_key;
+    // graphs are captured and launched on this stream (the caller's stream
+    // may be the legacy null stream, which cannot be captured)
+    hipStream_t cap_stream = nullptr;
+    hipEvent_t cap_in = nullptr, cap_out = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_grid(const henry_grid_t& g) {
+    if (g.reserved != 0) return HENRY_EINVAL;
+    if (g.ny < 1 || g.ny > 512 || !pow2(g.ny) || g.nx != 2 * g.ny) return HENRY_EINVAL;
+    if (g.nsteps < 1) return HENRY_EINVAL;
+    return HENRY_OK;
+}
+
+int check_opts(const henry_opts_t* o) {
+    if (!o) return HENRY_EINVAL;
+    if (o->prec != HENRY_PREC_FP64 && o->prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
+    if (o->max_outer < 1 || o->max_outer > 100000) return HENRY_EINVAL;
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return HENRY_EINVAL;
+    if (o->threads != 0 && (o->threads < 64 || o->threads > 1024 || !pow2(o->threads))) return HENRY_EINVAL;
+    if (o->steps_per_launch < 0) return HENRY_EINVAL;
+    if (o->profile != 0 && o->profile != 1) return HENRY_EINVAL;
+    if (o->serial_groups != 0 && o->serial_groups != 1) return HENRY_EINVAL;
+    return HENRY_OK;
+}
+
+int64_t solve_bytes(int nx, int ny, int prec) {
+    return prec == HENRY_PREC_MIXED ? henry::solve_bytes<float>(nx, ny) : henry::solve_bytes<double>(nx, ny);
+}
+
+int default_threads(int nx, int ny) {
+    const int cells = nx * ny;
+    if (cells <= 128) return 64;
+    if (cells <= 512) return 128;
+    if (cells <= 2048) return 256;
+    if (cells <= 8192) return 512;
+    return 1024;
+}
+
+int64_t desc_bytes(int nsolves) { return henry::align256((int64_t)nsolves * (int64_t)sizeof(henry::SolveDesc)); }
+
+
+// Fork from `s0`, launch every group (fields kernel, then the solve kernel
+// over lockstep chunks of `steps_per_launch` global steps, or one launch),
+// join back into `s0`.  Groups run concurrently on the context's streams
+// unless `serial`.
+int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::vector<int>& gstart,
+                   const henry_grid_t* solves, const henry_opts_t* o, const henry::Launch& lp,
+                   henry::SolveDesc* dtable, int rmax, hipStream_t s0, bool serial, bool profile) {
+    const int ng = (int)order.size();
+    const int nstreams = serial ? 0 : std::min(kStreams, ng);
+    const int prec = o->prec;
+    const int spl = o->steps_per_launch;
+    if (hipEventRecord(ctx->fork, s0) != hipSuccess) return HENRY_EHIP;
+    for (int k = 0; k < nstreams; ++k)
+        if (hipStreamWaitEvent(ctx->streams[k], ctx->fork, 0) != hipSuccess) return HENRY_EHIP;
+    for (int gi = 0; gi < ng; ++gi) {
+        const Group& G = order[gi];
+        hipStream_t st = serial ? s0 : ctx->streams[gi % kStreams];
+        henry::Launch l = lp;
+        l.descs = dtable + gstart[gi];
+        const int nb = (int)G.members.size();
+        hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
+        const size_t esz = prec == HENRY_PREC_MIXED ? sizeof(float) : sizeof(double);
+        const int cap = G.nx;  // longest line of the finest level
+        const int nw = G.threads / henry::kWave;
+        int lw = (int)std::min<size_t>((size_t)nw, ctx->lds_budget / (8 * (size_t)cap * esz));
+        if (lw < 1) lw = 1;
+        l.line_waves = lw;
+        l.line_cap = cap;
+        const size_t lds = (size_t)lw * 8 * cap * esz;
+        // lockstep time chunks: local step s of a solve with r steps runs in
+        // global step s * rmax / r; one chunk when steps_per_launch == 0
+        const int chunk = spl > 0 ? spl : rmax;
+        if (profile) {
+            henry_group_time_t& pt = ctx->prof[gi];
+            pt.nx = G.nx; pt.ny = G.ny; pt.nsolves = nb; pt.launches = 0; pt.cell_steps = 0;
+            for (int k : G.members) pt.cell_steps += (int64_t)solves[k].nx * solves[k].ny * solves[k].nsteps;
+            if (hipEventRecord(ctx->prof_ev[2 * gi], st) != hipSuccess) return HENRY_EHIP;
+        }
+        for (int g0 = 0; g0 < rmax; g0 += chunk) {
+            if (profile) ctx->prof[gi].launches++;
+            l.g_begin = g0;
+            l.g_end = std::min(rmax, g0 + chunk);
+            l.g_total = rmax;
+            if (prec == HENRY_PREC_MIXED)
+                hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nb), dim3(G.threads), lds, st, l);
+            else
+                hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nb), dim3(G.threads), lds, st, l);
+        }
+        if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+        if (profile && hipEventRecord(ctx->prof_ev[2 * gi + 1], st) != hipSuccess) return HENRY_EHIP;
+    }
+    for (int k = 0; k < nstreams; ++k) {
+        if (hipEventRecord(ctx->joins[k], ctx->streams[k]) != hipSuccess) return HENRY_EHIP;
+        if (hipStreamWaitEvent(s0, ctx->joins[k], 0) != hipSuccess) return HENRY_EHIP;
+    }
+    return HENRY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* henry_strerror(int code) {
+    switch (code) {
+        case HENRY_OK: return "ok";
+        case HENRY_EINVAL: return "invalid argument";
+        case HENRY_ENOMEM: return "workspace too small or out of host memory";
+        case HENRY_EHIP: return "HIP runtime error";
+        case HENRY_ENOCONV: return "a solve did not converge";
+        case HENRY_ENONFINITE: return "non-finite residual";
+        default: return "unknown error";
+    }
+}
+
+void henry_opts_default(henry_opts_t* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->prec = HENRY_PREC_MIXED;
+    o->max_outer = 40;
+    o->tol = 1e-10;
+    o->threads = 0;
+    o->steps_per_launch = 0;
+}
+
+int henry_ctx_create(henry_ctx** out, const henry_phys_t* phys, int device) {
+    if (!out || !phys) return HENRY_EINVAL;
+    *out = nullptr;
+    const double* v = &phys->rho0;
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(v[k])) return HENRY_EINVAL;
+    if (!(phys->rho0 > 0) || !(phys->rho1 > 0) || !(phys->mu > 0) || phys->D < 0 || !(phys->T > 0))
+        return HENRY_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HENRY_EINVAL;
+    henry_ctx* c = new (std::nothrow) henry_ctx();
+    if (!c) return HENRY_ENOMEM;
+    c->device = device;
+    std::memcpy(&c->ph, phys, sizeof(c->ph));
+    DeviceGuard g(device);
+    bool ok = true;
+    for (int k = 0; k < kStreams; ++k) {
+        ok &= hipStreamCreateWithFlags(&c->streams[k], hipStreamNonBlocking) == hipSuccess;
+        ok &= hipEventCreateWithFlags(&c->joins[k], hipEventDisableTiming) == hipSuccess;
+    }
+    ok &= hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+    ok &= hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&c->cap_in, hipEventDisableTiming) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&c->cap_out, hipEventDisableTiming) == hipSuccess;
+    // line systems are staged in up to kLdsBudget bytes of dynamic LDS; if
+    // the runtime refuses more than the 64 KiB default, stay below it
+    c->lds_budget = kLdsBudget;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&henry::henry_solve_kernel<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&henry::henry_solve_kernel<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget) != hipSuccess) {
+        (void)hipGetLastError();
+        c->lds_budget = 64 * 1024;
+    }
+    ok &= hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        henry_ctx_destroy(c);
+        return HENRY_EHIP;
+    }
+    *out = c;
+    return HENRY_OK;
+}
+
+void henry_ctx_destroy(henry_ctx* c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    for (int k = 0; k < kStreams; ++k) {
+        if (c->streams[k]) (void)hipStreamSynchronize(c->streams[k]);
+        if (c->streams[k]) (void)hipStreamDestroy(c->streams[k]);
+        if (c->joins[k]) (void)hipEventDestroy(c->joins[k]);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->staging_done) {
+        (void)hipEventSynchronize(c->staging_done);
+        (void)hipEventDestroy(c->staging_done);
+    }
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->cap_stream) {
+        (void)hipStreamSynchronize(c->cap_stream);
+        (void)hipStreamDestroy(c->cap_stream);
+    }
+    if (c->cap_in) (void)hipEventDestroy(c->cap_in);
+    if (c->cap_out) (void)hipEventDestroy(c->cap_out);
+    delete c;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications with Weyl-sequence key increments.
+static void philox10(uint32_t x[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x[2];
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x[1] ^ k0;
+        const uint32_t y1 = (uint32_t)p1;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x[3] ^ k1;
+        const uint32_t y3 = (uint32_t)p0;
+        x[0] = y0; x[1] = y1; x[2] = y2; x[3] = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+int henry_sample_xi(uint64_t seed, int32_t level, int64_t first, int64_t count, int32_t dim, double* out) {
+    if (!out || count < 0 || first < 0 || dim < 1 || level < 0) return HENRY_EINVAL;
+    for (int64_t s = 0; s < count; ++s) {
+        const uint64_t index = (uint64_t)(first + s);
+        for (int32_t blk = 0; 2 * blk < dim; ++blk) {
+            uint32_t x[4] = {(uint32_t)blk, (uint32_t)level, (uint32_t)(index & 0xffffffffu), (uint32_t)(index >> 32)};
+            philox10(x, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+            for (int half = 0; half < 2; ++half) {
+                const int d = 2 * blk + half;
+                if (d >= dim) break;
+                const uint64_t bits = ((uint64_t)x[2 * half + 1] << 32) | x[2 * half];
+                out[s * dim + d] = std::ldexp((double)(bits >> 11), -52) - 1.0;
+            }
+        }
+    }
+    return HENRY_OK;
+}
+
+int henry_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, const henry_opts_t* opts,
+                          size_t* bytes_out) {
+    (void)ctx;  // host-only computation; a context is not needed
+    if (!bytes_out || nsolves < 0 || (nsolves > 0 && !solves)) return HENRY_EINVAL;
+    henry_opts_t def;
+    henry_opts_default(&def);
+    const henry_opts_t* o = opts ? opts : &def;
+    if (int rc = check_opts(o)) return rc;
+    int64_t total = desc_bytes(nsolves);
+    for (int k = 0; k < nsolves; ++k) {
+        if (int rc = check_grid(solves[k])) return rc;
+        total += solve_bytes(solves[k].nx, solves[k].ny, o->prec);
+    }
+    *bytes_out = (size_t)total;
+    return HENRY_OK;
+}
+
+int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field, const double* xi,
+                      const double* phi, const double* logk, const double* qin, const double* c0,
+                      const henry_opts_t* opts, double* c_out, double* p_out, double* qoi_out, int32_t* status,
+                      int32_t* iters, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx || nsolves < 0) return HENRY_EINVAL;
+    if (nsolves == 0) return HENRY_OK;
+    if (!solves) return HENRY_EINVAL;
+    henry_opts_t def;
+    henry_opts_default(&def);
+    const henry_opts_t* o = opts ? opts : &def;
+    if (int rc = check_opts(o)) return rc;
+    if (field == HENRY_FIELD_CLOSED3) {
+        if (!xi) return HENRY_EINVAL;
+    } else if (field == HENRY_FIELD_EXPLICIT) {
+        if (!phi || !logk || !qin) return HENRY_EINVAL;
+    } else {
+        return HENRY_EINVAL;
+    }
+    if (!c_out || !qoi_out || !status || !workspace) return HENRY_EINVAL;
+    size_t need = 0;
+    if (int rc = henry_workspace_bytes(ctx, solves, nsolves, o, &need)) return rc;
+    if (ws_bytes < need) return HENRY_ENOMEM;
+    if (((uintptr_t)workspace & 255) != 0) return HENRY_EINVAL;
+
+    // ---- plan: descriptors, groups by grid, largest work first
+    const int prec = o->prec;
+    std::vector<henry::SolveDesc> desc(nsolves);
+    int64_t off = desc_bytes(nsolves), foff = 0;
+    int32_t rmax = 0;
+    for (int k = 0; k < nsolves; ++k) rmax = std::max(rmax, solves[k].nsteps);
+    std::map<long, Group> groups;
+    for (int k = 0; k < nsolves; ++k) {
+        const henry_grid_t& g = solves[k];
+        henry::SolveDesc& d = desc[k];
+        d.nx = g.nx; d.ny = g.ny; d.nsteps = g.nsteps; d.nlev = henry::num_levels(g.ny);
+        d.reserved = 0; d.index = k; d.ws_off = off; d.field_off = foff;
+        off += solve_bytes(g.nx, g.ny, prec);
+        foff += (int64_t)g.nx * g.ny;
+        Group& G = groups[(long)g.nx];
+        G.nx = g.nx; G.ny = g.ny;
+        G.members.push_back(k);
+        G.cost += (double)g.nx * g.ny * g.nsteps;
+    }
+    std::vector<Group> order;
+    for (auto& kv : groups) order.push_back(kv.second);
+    std::sort(order.begin(), order.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
+    // the table is laid out group by group so each launch sees a contiguous slice
+    std::vector<henry::SolveDesc> table;
+    table.reserve(nsolves);
+    std::vector<int> gstart;
+    for (auto& G : order) {
+        gstart.push_back((int)table.size());
+        for (int k : G.members) table.push_back(desc[k]);
+        int t = o->threads;
+        if (t == 0) {
+            auto it = ctx->tuned_threads.find((long)G.nx * 4 + prec);
+            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny);
+        }
+        G.threads = t;
+    }
+
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    const size_t tbytes = sizeof(henry::SolveDesc) * (size_t)nsolves;
+    if (ctx->pinned) {
+        if (hipEventSynchronize(ctx->staging_done) != hipSuccess) return HENRY_EHIP;
+    }
+    if (ctx->pinned_bytes < tbytes) {
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+        if (hipHostMalloc(&ctx->pinned, tbytes, hipHostMallocDefault) != hipSuccess) return HENRY_ENOMEM;
+        ctx->pinned_bytes = tbytes;
+    }
+    std::memcpy(ctx->pinned, table.data(), tbytes);
+    uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
+    henry::SolveDesc* dtable = reinterpret_cast<henry::SolveDesc*>(ws);
+    if (hipMemcpyAsync(dtable, ctx->pinned, tbytes, hipMemcpyHostToDevice, s0) != hipSuccess) return HENRY_EHIP;
+    if (hipEventRecord(ctx->staging_done, s0) != hipSuccess) return HENRY_EHIP;
+
+    henry::Launch lp{};
+    lp.ws = ws;
+    lp.xi = xi; lp.phi_in = phi; lp.logk_in = logk; lp.qin_in = qin; lp.c0 = c0;
+    lp.c_out = c_out; lp.p_out = p_out; lp.qoi_out = qoi_out; lp.status = status; lp.iters = iters;
+    std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
+    lp.tol = o->tol;
+    lp.max_outer = o->max_outer;
+    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : 1;
+
+    const int ng = (int)order.size();
+    const bool serial = o->serial_groups != 0;
+    const int spl = o->steps_per_launch;
+    const bool graph = spl > 0;
+    // per-group event timing only outside graph capture; a replayed graph is
+    // timed as one unit (entry 0)
+    if (o->profile) {
+        while ((int)ctx->prof_ev.size() < 2 * std::max(ng, 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return HENRY_EHIP;
+            ctx->prof_ev.push_back(e);
+        }
+        ctx->prof.assign(graph ? 1 : ng, henry_group_time_t{});
+    } else {
+        ctx->prof.clear();
+    }
+    if (!graph) return enqueue_groups(ctx, order, gstart, solves, o, lp, dtable, rmax, s0, serial, o->profile != 0);
+
+    // Lockstep chunks of `spl` global steps: capture the whole sequence once
+    // and replay it; the cached executable is reused while the plan and every
+    // pointer argument are unchanged.
+    PlanKey key;
+    key.words.reserve(4 * nsolves + 32);
+    for (int k = 0; k < nsolves; ++k) {
+        key.words.push_back(solves[k].nx);
+        key.words.push_back(solves[k].nsteps);
+    }
+    const uintptr_t ptrs[] = {(uintptr_t)xi, (uintptr_t)phi, (uintptr_t)logk, (uintptr_t)qin, (uintptr_t)c0,
+                              (uintptr_t)c_out, (uintptr_t)p_out, (uintptr_t)qoi_out, (uintptr_t)status,
+                              (uintptr_t)iters, (uintptr_t)workspace, (uintptr_t)s0};
+    for (uintptr_t v : ptrs) { key.words.push_back((int64_t)v); }
+    int64_t tolbits;
+    std::memcpy(&tolbits, &o->tol, 8);
+    for (int64_t v : {(int64_t)o->prec, (int64_t)o->max_outer, tolbits, (int64_t)o->threads, (int64_t)spl,
+                      (int64_t)o->serial_groups, (int64_t)field})
+        key.words.push_back(v);
+    hipStream_t cs = ctx->cap_stream;
+    if (hipEventRecord(ctx->cap_in, s0) != hipSuccess) return HENRY_EHIP;
+    if (hipStreamWaitEvent(cs, ctx->cap_in, 0) != hipSuccess) return HENRY_EHIP;
+    if (!ctx->graph_exec || !(key == ctx->graph_key)) {
+        if (ctx->graph_exec) { (void)hipGraphExecDestroy(ctx->graph_exec); ctx->graph_exec = nullptr; }
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return HENRY_EHIP;
+        int rc = enqueue_groups(ctx, order, gstart, solves, o, lp, dtable, rmax, cs, serial, false);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &g);
+        if (rc != HENRY_OK || ec != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != HENRY_OK ? rc : HENRY_EHIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return HENRY_EHIP;
+        ctx->graph_exec = ex;
+        ctx->graph_key = key;
+    }
+    if (o->profile) {
+        henry_group_time_t& pt = ctx->prof[0];
+        pt.nx = 0; pt.ny = 0; pt.nsolves = nsolves; pt.launches = 0; pt.cell_steps = 0;
+        for (int k = 0; k < nsolves; ++k) pt.cell_steps += (int64_t)solves[k].nx * solves[k].ny * solves[k].nsteps;
+        for (int gi = 0; gi < ng; ++gi) pt.launches += (rmax + spl - 1) / spl;
+        if (hipEventRecord(ctx->prof_ev[0], cs) != hipSuccess) return HENRY_EHIP;
+    }
+    if (hipGraphLaunch(ctx->graph_exec, cs) != hipSuccess) return HENRY_EHIP;
+    if (o->profile && hipEventRecord(ctx->prof_ev[1], cs) != hipSuccess) return HENRY_EHIP;
+    if (hipEventRecord(ctx->cap_out, cs) != hipSuccess) return HENRY_EHIP;
+    if (hipStreamWaitEvent(s0, ctx->cap_out, 0) != hipSuccess) return HENRY_EHIP;
+    return HENRY_OK;
+}
+
+int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int32_t* ngroups) {
+    if (!ctx || !ngroups || cap < 0 || (cap > 0 && !out)) return HENRY_EINVAL;
+    DeviceGuard dg(ctx->device);
+    const int ng = (int)ctx->prof.size();
+    *ngroups = ng;
+    for (int g = 0; g < ng && g < cap; ++g) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(ctx->prof_ev[2 * g + 1]) != hipSuccess) return HENRY_EHIP;
+        if (hipEventElapsedTime(&ms, ctx->prof_ev[2 * g], ctx->prof_ev[2 * g + 1]) != hipSuccess) return HENRY_EHIP;
+        ctx->prof[g].ms = ms;
+        out[g] = ctx->prof[g];
+    }
+    return HENRY_OK;
+}
+
+int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, const int32_t* m,
+                        const double* const* c_fine, const double* const* c_coarse, const double* const* q_fine,
+                        const double* const* q_coarse, double* const* mean_Y, double* const* var_Y, double* qstats,
+                        double* Ec_finest, double* var_est, void* stream) {
+    if (!ctx || L < 0 || L > 15 || !fine || !m || !c_fine || !q_fine || !mean_Y || !var_Y || !qstats ||
+        !Ec_finest || !var_est)
+        return HENRY_EINVAL;
+    for (int l = 0; l <= L; ++l) {
+        if (check_grid(fine[l]) != HENRY_OK || m[l] < 2 || !c_fine[l] || !q_fine[l] || !mean_Y[l] || !var_Y[l])
+            return HENRY_EINVAL;
+        if (l > 0) {
+            if (!c_coarse || !q_coarse || !c_coarse[l] || !q_coarse[l]) return HENRY_EINVAL;
+            if (fine[l].nx != 2 * fine[l - 1].nx) return HENRY_EINVAL;
+        }
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    henry::LevelPtrs lp{};
+    for (int l = 0; l <= L; ++l) {
+        const int nx = fine[l].nx, ny = fine[l].ny;
+        const double* cc = l > 0 ? c_coarse[l] : nullptr;
+        const double* qc = l > 0 ? q_coarse[l] : nullptr;
+        const int cells = nx * ny;
+        const int blocks = (cells * 64 + 255) / 256;
+        hipLaunchKernelGGL(henry::mlmc_field_stats_kernel, dim3(blocks), dim3(256), 0, s0, c_fine[l], cc, m[l], nx,
+                           ny, mean_Y[l], var_Y[l]);
+        hipLaunchKernelGGL(henry::mlmc_qoi_stats_kernel, dim3(1), dim3(64), 0, s0, q_fine[l], qc, m[l],
+                           qstats + 2 * l);
+        lp.mean[l] = mean_Y[l];
+        lp.var[l] = var_Y[l];
+        lp.m[l] = m[l];
+        lp.nx[l] = nx;
+    }
+    hipLaunchKernelGGL(henry::mlmc_combine_kernel, dim3(1), dim3(1024), 0, s0, lp, L, fine[L].nx, fine[L].ny,
+                       qstats, Ec_finest, var_est);
+    if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    return HENRY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,756 @@
+// henry_device.hpp -- gfx950 device code for batched Henry solves.
+//
+// One workgroup owns one solve (one random sample on one grid) and runs its
+// whole implicit time loop (Sec. 2.3: implicit Euler, fixed tau).  Each step
+// is a defect correction on the FP64 nonlinear residual of the cell-centred
+// discretisation of e_cont_eq / e_tran_eq / e_Darcy_vel (Sec. 2.1):
+//
+//   repeat
+//     R = R(p, c)                                   FP64, scaled max norms
+//     (A_pp) dp = -R^p    one V(2,2) cycle, red-black Gauss-Seidel   inner T
+//     p += dp                                                         FP64
+//     S = R^c(p, c) - c R^p(p, c)                                     FP64
+//     (A_cc) dc = -S      one V(1,1) cycle, zebra x/y line relaxation inner T
+//     c += dc                                                         FP64
+//   until both scaled residual norms <= tol
+//
+// A_pp = -div(rho K / mu grad .) with the seawater Dirichlet face.  The salt
+// block is driven by S = R^c - c R^p, an exact recombination of the two
+// equations (same discrete solution): S is the non-conservative upwind form
+// of e_tran_eq, in which a mass-flux error of an inexact pressure solve no
+// longer appears as a salt source.  A_cc, its frozen-flux derivative, is an
+// M-matrix with the stored-mass term (h^2/tau) phi rho(c^n) on the diagonal
+// and upwind inflow plus diffusion couplings.  The inner precision T is float (the
+// mixed path) or double (the plain FP64 path): one code path, two
+// instantiations.  Memory: per-solve FP64 state and per-level inner arrays
+// in a caller-provided workspace (L2 / Infinity-Cache resident for the
+// grid sizes of an MLMC hierarchy); line systems are staged in LDS and
+// solved by parallel cyclic reduction, one wavefront per line.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace henry {
+
+constexpr int kMaxLevels = 12;  // ny <= 512 -> at most 10 multigrid levels
+constexpr int kWave = 64;
+
+struct Phys {
+    double rho0, rho1, mu, g, D, phi0, k0, q_in, T;
+};
+
+// One solve of a batch.  Offsets are in bytes from the workspace base
+// (ws_off) or in elements of the packed field arrays (field_off).
+struct SolveDesc {
+    int32_t nx, ny, nsteps, nlev;
+    int32_t reserved;
+    int32_t index;       // position in the caller's solve list
+    int64_t ws_off;
+    int64_t field_off;
+};
+
+struct Launch {
+    const SolveDesc* descs;
+    uint8_t* ws;
+    const double* xi;    // [nsolves][3] or null
+    const double* phi_in;
+    const double* logk_in;
+    const double* qin_in;
+    const double* c0;
+    double* c_out;
+    double* p_out;
+    double* qoi_out;
+    int32_t* status;
+    int32_t* iters;
+    Phys ph;
+    double tol;
+    int32_t max_outer;
+    int32_t field_kind;
+    int32_t g_begin, g_end;  // global step range of this launch
+    int32_t g_total;         // global steps of the whole batch (max nsteps)
+    int32_t line_waves;      // waves that take part in line solves (LDS budget)
+    int32_t line_cap;        // LDS elements reserved per line array
+};
+
+// ------------------------------------------------------------------ layout
+__host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+__host__ __device__ inline int num_levels(int ny) {
+    int L = 1;
+    while (ny > 1) { ny >>= 1; ++L; }
+    return L;
+}
+
+// Per-level inner arrays, in this order, each nx_l*ny_l elements of T:
+//   x, b, r, te, tn, acc, mx, my, dx, dy
+// followed by four row arrays of ny_l elements: dl, dr, mr, ml
+// (left diffusion, right diffusion, right mass flux, left inflow).
+constexpr int kLevelArrays = 10;
+constexpr int kRowArrays = 4;
+
+template <typename T>
+__host__ __device__ inline int64_t level_bytes(int nx, int ny) {
+    return align256((int64_t)(kLevelArrays * nx * ny + kRowArrays * ny) * (int64_t)sizeof(T));
+}
+
+// FP64 arrays: p, c, cn, phi, K, Rp, Rc, then 8 doubles of scratch.
+constexpr int kF64Arrays = 7;
+
+template <typename T>
+__host__ __device__ inline int64_t solve_bytes(int nx, int ny) {
+    int64_t b = align256((int64_t)kF64Arrays * nx * ny * 8 + 64);
+    int lx = nx, ly = ny;
+    const int L = num_levels(ny);
+    for (int l = 0; l < L; ++l) {
+        b += level_bytes<T>(lx, ly);
+        lx >>= 1; ly >>= 1;
+    }
+    return b;
+}
+
+template <typename T>
+struct Level {
+    int nx, ny;
+    T *x, *b, *r, *te, *tn, *acc, *mx, *my, *dx, *dy, *dl, *dr, *mr, *ml;
+};
+
+template <typename T>
+struct Solve {
+    int nx, ny, n, nsteps, L;
+    double h, tau;
+    double q;  // recharge (m/s)
+    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *scratch;
+    Level<T> lv[kMaxLevels];
+};
+
+template <typename T>
+__device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny) {
+    S.nx = nx; S.ny = ny; S.n = nx * ny; S.L = num_levels(ny);
+    S.h = 1.0 / ny;
+    double* f = reinterpret_cast<double*>(base);
+    const int n = nx * ny;
+    S.p = f; S.c = f + n; S.cn = f + 2 * n; S.phi = f + 3 * n; S.K = f + 4 * n; S.Rp = f + 5 * n;
+    S.Rc = f + 6 * n; S.scratch = f + 7 * n;
+    uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + 64);
+    int lx = nx, ly = ny;
+    for (int l = 0; l < S.L; ++l) {
+        T* a = reinterpret_cast<T*>(q);
+        const int m = lx * ly;
+        Level<T>& v = S.lv[l];
+        v.nx = lx; v.ny = ly;
+        v.x = a; v.b = a + m; v.r = a + 2 * m; v.te = a + 3 * m; v.tn = a + 4 * m; v.acc = a + 5 * m;
+        v.mx = a + 6 * m; v.my = a + 7 * m; v.dx = a + 8 * m; v.dy = a + 9 * m;
+        v.dl = a + 10 * m; v.dr = a + 10 * m + ly; v.mr = a + 10 * m + 2 * ly; v.ml = a + 10 * m + 3 * ly;
+        q += level_bytes<T>(lx, ly);
+        lx >>= 1; ly >>= 1;
+    }
+}
+
+// ------------------------------------------------------------------ reductions
+// max that propagates NaN (fmax would drop it)
+__device__ inline double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+
+__device__ inline double wave_max(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = nanmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline double wave_sum(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Block-wide max / sum in a fixed order; `red` holds >= nwaves doubles.
+// Ends with every thread holding the result.
+__device__ inline double block_max(double v, double* red) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int k = 1; k < nw; ++k) r = nanmax(r, red[k]);
+    return r;
+}
+__device__ inline double block_sum(double v, double* red) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int k = 1; k < nw; ++k) r += red[k];
+    return r;
+}
+
+// ------------------------------------------------------------------ physics (FP64)
+__device__ inline double rho_of(const Phys& ph, double c) { return ph.rho0 + (ph.rho1 - ph.rho0) * c; }
+
+// Mass and salt flux from cell (i,j) to its east neighbour (i+1,j), per metre
+// of depth: harmonic K and phi, arithmetic rho on the face; donor cell.
+struct FaceFlux { double M, F, lam, dif; };
+
+__device__ inline FaceFlux flux_x(const Phys& ph, const double* p, const double* c, const double* phi,
+                                  const double* K, int a, int b) {
+    FaceFlux f;
+    const double ca = c[a], cb = c[b];
+    const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
+    const double Ka = K[a], Kb = K[b], pa = phi[a], pb = phi[b];
+    const double Kf = 2.0 * Ka * Kb / (Ka + Kb);
+    const double phf = 2.0 * pa * pb / (pa + pb);
+    f.lam = rf * Kf / ph.mu;
+    f.dif = rf * phf * ph.D;
+    f.M = -f.lam * (p[b] - p[a]);
+    f.F = f.M * (f.M >= 0.0 ? ca : cb) - f.dif * (cb - ca);
+    return f;
+}
+
+// North neighbour: Darcy's law with gravity (0,-g) adds rho_f g h.
+__device__ inline FaceFlux flux_y(const Phys& ph, double h, const double* p, const double* c, const double* phi,
+                                  const double* K, int a, int b) {
+    FaceFlux f;
+    const double ca = c[a], cb = c[b];
+    const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
+    const double Ka = K[a], Kb = K[b], pa = phi[a], pb = phi[b];
+    const double Kf = 2.0 * Ka * Kb / (Ka + Kb);
+    const double phf = 2.0 * pa * pb / (pa + pb);
+    f.lam = rf * Kf / ph.mu;
+    f.dif = rf * phf * ph.D;
+    f.M = -f.lam * ((p[b] - p[a]) + rf * ph.g * h);
+    f.F = f.M * (f.M >= 0.0 ? ca : cb) - f.dif * (cb - ca);
+    return f;
+}
+
+// Seawater face at x = 2 (half-cell distance): p_B = -rho1 g y, c_B = 1.
+__device__ inline FaceFlux flux_right(const Phys& ph, double y, double pP, double cP, double phiP, double KP) {
+    FaceFlux f;
+    const double rB = 0.5 * (rho_of(ph, cP) + ph.rho1);
+    f.lam = 2.0 * rB * KP / ph.mu;
+    f.dif = 2.0 * rB * phiP * ph.D;
+    f.M = -f.lam * (-ph.rho1 * ph.g * y - pP);
+    f.F = f.M * (f.M >= 0.0 ? cP : 1.0) - f.dif * (1.0 - cP);
+    return f;
+}
+
+// Recharge face at x = 0: inflow rho0 q h of fresh water (c_B = 0).
+__device__ inline FaceFlux flux_left(const Phys& ph, double h, double q, double cP, double phiP) {
+    FaceFlux f;
+    const double rB = 0.5 * (rho_of(ph, cP) + ph.rho0);
+    f.lam = 0.0;
+    f.dif = 2.0 * rB * phiP * ph.D;
+    f.M = -ph.rho0 * q * h;
+    f.F = f.dif * cP;
+    return f;
+}
+
+// ------------------------------------------------------------------ FP64 residual
+// mode 0: R^p and R^c, pressure coefficients te/tn at level 0, and the
+//         scaled max norms (returned through red-based block max).
+// mode 1: the salt defect S = R^c - c R^p with the transport coefficients
+//         at level 0.
+template <typename T>
+__device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out) {
+    const int nx = S.nx, ny = S.ny, n = S.n;
+    const double h = S.h, h2t = h * h / S.tau;
+    Level<T>& L0 = S.lv[0];
+    double mp = 0.0, mc = 0.0;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const int i = idx % nx, j = idx / nx;
+        const double cP = S.c[idx], cnP = S.cn[idx], phiP = S.phi[idx];
+        const double rP = rho_of(ph, cP), rN = rho_of(ph, cnP);
+        double Rp = h2t * phiP * (rP - rN);
+        double Rc = h2t * phiP * (rP * cP - rN * cnP);
+        // east face
+        if (i + 1 < nx) {
+            FaceFlux f = flux_x(ph, S.p, S.c, S.phi, S.K, idx, idx + 1);
+            Rp += f.M; Rc += f.F;
+            if (mode == 0) L0.te[idx] = (T)f.lam;
+            else { L0.mx[idx] = (T)f.M; L0.dx[idx] = (T)f.dif; }
+        } else {
+            const double y = -1.0 + (j + 0.5) * h;
+            FaceFlux f = flux_right(ph, y, S.p[idx], cP, phiP, S.K[idx]);
+            Rp += f.M; Rc += f.F;
+            if (mode == 0) L0.te[idx] = (T)f.lam;
+            else { L0.mx[idx] = (T)0; L0.dx[idx] = (T)0; L0.dr[j] = (T)f.dif; L0.mr[j] = (T)f.M; }
+        }
+        // west face
+        if (i > 0) {
+            FaceFlux f = flux_x(ph, S.p, S.c, S.phi, S.K, idx - 1, idx);
+            Rp -= f.M; Rc -= f.F;
+        } else {
+            FaceFlux f = flux_left(ph, h, S.q, cP, phiP);
+            Rp += f.M; Rc += f.F;
+            if (mode == 1) { L0.dl[j] = (T)f.dif; L0.ml[j] = (T)(-f.M); }
+        }
+        // north face (top is impermeable)
+        if (j + 1 < ny) {
+            FaceFlux f = flux_y(ph, h, S.p, S.c, S.phi, S.K, idx, idx + nx);
+            Rp += f.M; Rc += f.F;
+            if (mode == 0) L0.tn[idx] = (T)f.lam;
+            else { L0.my[idx] = (T)f.M; L0.dy[idx] = (T)f.dif; }
+        } else {
+            if (mode == 0) L0.tn[idx] = (T)0;
+            else { L0.my[idx] = (T)0; L0.dy[idx] = (T)0; }
+        }
+        // south face (bottom is impermeable)
+        if (j > 0) {
+            FaceFlux f = flux_y(ph, h, S.p, S.c, S.phi, S.K, idx - nx, idx);
+            Rp -= f.M; Rc -= f.F;
+        }
+        if (mode == 1) L0.acc[idx] = (T)(h2t * phiP * rN);
+        const double sc = S.tau / (h * h * phiP * ph.rho0);
+        if (mode == 0) {
+            S.Rp[idx] = Rp;
+            L0.b[idx] = (T)(-Rp);
+            L0.x[idx] = (T)0;
+            mp = nanmax(mp, fabs(Rp * sc));
+        } else {
+            L0.b[idx] = (T)(-(Rc - cP * Rp));
+            L0.x[idx] = (T)0;
+        }
+        S.Rc[idx] = Rc;
+        mc = nanmax(mc, fabs(Rc * sc));
+    }
+    np_out = block_max(mp, red);
+    nc_out = block_max(mc, red);
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ coefficient coarsening
+template <typename T>
+__device__ void coarsen_pressure(Solve<T>& S) {
+    for (int l = 1; l < S.L; ++l) {
+        const Level<T>& F = S.lv[l - 1];
+        Level<T>& C = S.lv[l];
+        const int nc = C.nx * C.ny;
+        for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
+            const int I = idx % C.nx, J = idx / C.nx;
+            const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
+            C.te[idx] = (T)0.5 * (F.te[f0 + 1] + F.te[f1 + 1]);
+            C.tn[idx] = (T)0.5 * (F.tn[f1] + F.tn[f1 + 1]);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ void coarsen_transport(Solve<T>& S) {
+    for (int l = 1; l < S.L; ++l) {
+        const Level<T>& F = S.lv[l - 1];
+        Level<T>& C = S.lv[l];
+        const int nc = C.nx * C.ny;
+        for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
+            const int I = idx % C.nx, J = idx / C.nx;
+            const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
+            C.acc[idx] = (F.acc[f0] + F.acc[f0 + 1]) + (F.acc[f1] + F.acc[f1 + 1]);
+            // mass fluxes through the two fine faces add; diffusion
+            // transmissibilities (length/distance = 1 on every level) average
+            C.mx[idx] = (I + 1 < C.nx) ? F.mx[f0 + 1] + F.mx[f1 + 1] : (T)0;
+            C.dx[idx] = (I + 1 < C.nx) ? (T)0.5 * (F.dx[f0 + 1] + F.dx[f1 + 1]) : (T)0;
+            C.my[idx] = (J + 1 < C.ny) ? F.my[f1] + F.my[f1 + 1] : (T)0;
+            C.dy[idx] = (J + 1 < C.ny) ? (T)0.5 * (F.dy[f1] + F.dy[f1 + 1]) : (T)0;
+        }
+        for (int J = threadIdx.x; J < C.ny; J += blockDim.x) {
+            C.dl[J] = (T)0.5 * (F.dl[2 * J] + F.dl[2 * J + 1]);
+            C.dr[J] = (T)0.5 * (F.dr[2 * J] + F.dr[2 * J + 1]);
+            C.mr[J] = F.mr[2 * J] + F.mr[2 * J + 1];
+            C.ml[J] = F.ml[2 * J] + F.ml[2 * J + 1];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ stencils
+// Pressure: (A x)_P = diag x_P - sum_nb t_nb x_nb; te of the last column is
+// the seawater Dirichlet coefficient (diagonal only); tn of the top row is 0.
+template <typename T>
+struct Stencil { T d, w, e, s, n; };
+
+template <typename T>
+__device__ inline Stencil<T> pstencil(const Level<T>& v, int i, int j) {
+    const int idx = j * v.nx + i;
+    Stencil<T> st;
+    const T te = v.te[idx];
+    st.e = (i + 1 < v.nx) ? te : (T)0;
+    st.w = (i > 0) ? v.te[idx - 1] : (T)0;
+    st.n = v.tn[idx];
+    st.s = (j > 0) ? v.tn[idx - v.nx] : (T)0;
+    st.d = te + st.w + st.n + st.s;
+    return st;
+}
+
+// Transport (non-conservative upwind form): a neighbour couples only
+// through inflow across the shared face plus diffusion; the diagonal is
+// the stored mass plus the sum of the couplings and the boundary inflow /
+// diffusion terms.  mx/my are the mass fluxes leaving (i,j) east/north.
+template <typename T>
+__device__ inline T pos(T a) { return a > (T)0 ? a : (T)0; }
+
+template <typename T>
+__device__ inline Stencil<T> cstencil(const Level<T>& v, int i, int j) {
+    const int idx = j * v.nx + i;
+    Stencil<T> st;
+    T d = v.acc[idx];
+    if (i + 1 < v.nx) {
+        st.e = pos(-v.mx[idx]) + v.dx[idx];
+        d += st.e;
+    } else {
+        st.e = (T)0;
+        d += pos(-v.mr[j]) + v.dr[j];
+    }
+    if (i > 0) {
+        st.w = pos(v.mx[idx - 1]) + v.dx[idx - 1];
+        d += st.w;
+    } else {
+        st.w = (T)0;
+        d += v.dl[j] + v.ml[j];
+    }
+    if (j + 1 < v.ny) {
+        st.n = pos(-v.my[idx]) + v.dy[idx];
+        d += st.n;
+    } else st.n = (T)0;
+    if (j > 0) {
+        st.s = pos(v.my[idx - v.nx]) + v.dy[idx - v.nx];
+        d += st.s;
+    } else st.s = (T)0;
+    st.d = d;
+    return st;
+}
+
+template <typename T, bool kTransport>
+__device__ inline Stencil<T> stencil(const Level<T>& v, int i, int j) {
+    if constexpr (kTransport) return cstencil(v, i, j);
+    else return pstencil(v, i, j);
+}
+
+// ------------------------------------------------------------------ grid transfer
+// Prolongation: bilinear with constant extrapolation at the boundary,
+// x_f += P x_c.  Restriction is its exact transpose (full weighting with
+// weights (1,3,3,1)/4 per direction, boundary weights folded in).
+template <typename T>
+__device__ void prolong_add(const Level<T>& C, Level<T>& F) {
+    const int n = F.nx * F.ny;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const int i = idx % F.nx, j = idx / F.nx;
+        const int I = i >> 1, J = j >> 1;
+        const int In = (i & 1) ? min(I + 1, C.nx - 1) : max(I - 1, 0);
+        const int Jn = (j & 1) ? min(J + 1, C.ny - 1) : max(J - 1, 0);
+        const T v = (T)0.5625 * C.x[J * C.nx + I] + (T)0.1875 * (C.x[J * C.nx + In] + C.x[Jn * C.nx + I]) +
+                    (T)0.0625 * C.x[Jn * C.nx + In];
+        F.x[idx] += v;
+    }
+}
+
+__device__ inline int rweights(int I, int n, int* idx, float* w) {
+    int k = 0;
+    if (I > 0) { idx[k] = 2 * I - 1; w[k++] = 0.25f; }
+    idx[k] = 2 * I; w[k++] = (I == 0) ? 1.0f : 0.75f;
+    idx[k] = 2 * I + 1; w[k++] = (I == n - 1) ? 1.0f : 0.75f;
+    if (I < n - 1) { idx[k] = 2 * I + 2; w[k++] = 0.25f; }
+    return k;
+}
+
+template <typename T>
+__device__ void restrict_residual(const Level<T>& F, Level<T>& C) {
+    const int n = C.nx * C.ny;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const int I = idx % C.nx, J = idx / C.nx;
+        int ix[4], iy[4];
+        float wx[4], wy[4];
+        const int kx = rweights(I, C.nx, ix, wx), ky = rweights(J, C.ny, iy, wy);
+        T s = (T)0;
+        for (int b = 0; b < ky; ++b) {
+            T row = (T)0;
+            for (int a = 0; a < kx; ++a) row += (T)wx[a] * F.r[iy[b] * F.nx + ix[a]];
+            s += (T)wy[b] * row;
+        }
+        C.b[idx] = s;
+        C.x[idx] = (T)0;
+    }
+}
+
+// r = b - A x on one level.
+template <typename T, bool kTransport>
+__device__ void level_residual(Level<T>& v) {
+    const int n = v.nx * v.ny;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const int i = idx % v.nx, j = idx / v.nx;
+        const Stencil<T> st = stencil<T, kTransport>(v, i, j);
+        T ax = st.d * v.x[idx];
+        if (i > 0) ax -= st.w * v.x[idx - 1];
+        if (i + 1 < v.nx) ax -= st.e * v.x[idx + 1];
+        if (j > 0) ax -= st.s * v.x[idx - v.nx];
+        if (j + 1 < v.ny) ax -= st.n * v.x[idx + v.nx];
+        v.r[idx] = v.b[idx] - ax;
+    }
+}
+
+// ------------------------------------------------------------------ smoothers
+// Red-black Gauss-Seidel (pressure): colour (i + j) & 1.
+template <typename T>
+__device__ void rbgs(Level<T>& v, int sweeps) {
+    const int half = v.nx >> 1;  // nx is even on every level
+    const int m = half * v.ny;
+    for (int s = 0; s < sweeps; ++s)
+        for (int col = 0; col < 2; ++col) {
+            for (int k = threadIdx.x; k < m; k += blockDim.x) {
+                const int j = k / half;
+                const int i = 2 * (k - j * half) + ((j + col) & 1);
+                const int idx = j * v.nx + i;
+                const Stencil<T> st = pstencil(v, i, j);
+                T acc = v.b[idx];
+                if (i > 0) acc += st.w * v.x[idx - 1];
+                if (i + 1 < v.nx) acc += st.e * v.x[idx + 1];
+                if (j > 0) acc += st.s * v.x[idx - v.nx];
+                if (j + 1 < v.ny) acc += st.n * v.x[idx + v.nx];
+                v.x[idx] = acc / st.d;
+            }
+            __syncthreads();
+        }
+}
+
+// Parallel cyclic reduction of one tridiagonal system per wavefront, in LDS.
+// Every wave of the block runs the same number of rounds (so that block
+// barriers line up); waves with no line in a round only take the barriers.
+// Line `li` of a colour: x-lines are rows j = col + 2 li, y-lines columns.
+template <typename T, bool kXLine>
+__device__ void line_sweep(Level<T>& v, int col, T* lds, int line_waves, int cap) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int len = kXLine ? v.nx : v.ny;
+    const int other = kXLine ? v.ny : v.nx;
+    const int nlines = (other - col + 1) >> 1;
+    const int rounds = (nlines + line_waves - 1) / line_waves;
+    T* base = lds + (size_t)w * 8 * cap;
+    T *A = base, *B = base + cap, *C = base + 2 * cap, *D = base + 3 * cap;
+    T *A2 = base + 4 * cap, *B2 = base + 5 * cap, *C2 = base + 6 * cap, *D2 = base + 7 * cap;
+    for (int r = 0; r < rounds; ++r) {
+        const int li = r * line_waves + w;
+        const bool active = (w < line_waves) && (li < nlines);
+        const int fixed = col + 2 * li;
+        if (active) {
+            for (int k = lane; k < len; k += kWave) {
+                const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
+                const int idx = j * v.nx + i;
+                const Stencil<T> st = cstencil(v, i, j);
+                T rhs = v.b[idx];
+                if (kXLine) {
+                    if (j > 0) rhs += st.s * v.x[idx - v.nx];
+                    if (j + 1 < v.ny) rhs += st.n * v.x[idx + v.nx];
+                    A[k] = -st.w; C[k] = -st.e;
+                } else {
+                    if (i > 0) rhs += st.w * v.x[idx - 1];
+                    if (i + 1 < v.nx) rhs += st.e * v.x[idx + 1];
+                    A[k] = -st.s; C[k] = -st.n;
+                }
+                B[k] = st.d; D[k] = rhs;
+            }
+        }
+        __syncthreads();
+        for (int s = 1; s < len; s <<= 1) {
+            if (active) {
+                for (int k = lane; k < len; k += kWave) {
+                    const T a = A[k], b = B[k], c = C[k], d = D[k];
+                    T na = (T)0, nb = b, nc = (T)0, nd = d;
+                    if (k - s >= 0) {
+                        const T k1 = a / B[k - s];
+                        na = -A[k - s] * k1;
+                        nb -= C[k - s] * k1;
+                        nd -= D[k - s] * k1;
+                    }
+                    if (k + s < len) {
+                        const T k2 = c / B[k + s];
+                        nc = -C[k + s] * k2;
+                        nb -= A[k + s] * k2;
+                        nd -= D[k + s] * k2;
+                    }
+                    A2[k] = na; B2[k] = nb; C2[k] = nc; D2[k] = nd;
+                }
+            }
+            __syncthreads();
+            T* t;
+            t = A; A = A2; A2 = t;
+            t = B; B = B2; B2 = t;
+            t = C; C = C2; C2 = t;
+            t = D; D = D2; D2 = t;
+        }
+        if (active) {
+            for (int k = lane; k < len; k += kWave) {
+                const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
+                v.x[j * v.nx + i] = D[k] / B[k];
+            }
+        }
+        __syncthreads();
+        // restore buffer roles for the next round (pointer parity)
+        A = base; B = base + cap; C = base + 2 * cap; D = base + 3 * cap;
+        A2 = base + 4 * cap; B2 = base + 5 * cap; C2 = base + 6 * cap; D2 = base + 7 * cap;
+    }
+}
+
+// One zebra sweep: x-lines (even rows, odd rows), then y-lines.
+template <typename T>
+__device__ void line_smooth(Level<T>& v, T* lds, int line_waves, int cap, int sweeps) {
+    for (int s = 0; s < sweeps; ++s) {
+        line_sweep<T, true>(v, 0, lds, line_waves, cap);
+        line_sweep<T, true>(v, 1, lds, line_waves, cap);
+        if (v.ny > 1) {
+            line_sweep<T, false>(v, 0, lds, line_waves, cap);
+            line_sweep<T, false>(v, 1, lds, line_waves, cap);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ V-cycles
+// The coarsest level of every hierarchy has one row (ny = 1, nx = 2): the
+// system is a single x-line, solved exactly.
+template <typename T, bool kTransport>
+__device__ void vcycle(Solve<T>& S, T* lds, int line_waves, int cap) {
+    const int L = S.L;
+    for (int l = 0; l < L - 1; ++l) {
+        Level<T>& v = S.lv[l];
+        if constexpr (kTransport) line_smooth(v, lds, line_waves, cap, 1);
+        else rbgs(v, 2);
+        level_residual<T, kTransport>(v);
+        __syncthreads();
+        restrict_residual(v, S.lv[l + 1]);
+        __syncthreads();
+    }
+    {
+        Level<T>& v = S.lv[L - 1];
+        if constexpr (kTransport) line_sweep<T, true>(v, 0, lds, line_waves, cap);
+        else {
+            // pressure coarsest (2 x 1 cells): direct Thomas solve in one thread
+            if (threadIdx.x == 0) {
+                T cp[2], dp[2];
+                const int n = v.nx;  // == 2 by construction
+                for (int i = 0; i < n; ++i) {
+                    const Stencil<T> st = pstencil(v, i, 0);
+                    const T a = -st.w, b = st.d, c = -st.e, d = v.b[i];
+                    const T den = (i > 0) ? b - a * cp[i - 1] : b;
+                    cp[i] = c / den;
+                    dp[i] = (i > 0) ? (d - a * dp[i - 1]) / den : d / den;
+                }
+                v.x[n - 1] = dp[n - 1];
+                for (int i = n - 2; i >= 0; --i) v.x[i] = dp[i] - cp[i] * v.x[i + 1];
+            }
+            __syncthreads();
+        }
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        Level<T>& v = S.lv[l];
+        prolong_add(S.lv[l + 1], v);
+        __syncthreads();
+        if constexpr (kTransport) line_smooth(v, lds, line_waves, cap, 1);
+        else rbgs(v, 2);
+    }
+}
+
+// ------------------------------------------------------------------ the solve kernel
+template <typename T>
+__global__ void __launch_bounds__(1024) henry_solve_kernel(Launch lp) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Solve<T> S;
+    __shared__ double red[16];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const SolveDesc d = lp.descs[blockIdx.x];
+    const Phys& ph = lp.ph;
+    if (threadIdx.x == 0) {
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny);
+        S.nsteps = d.nsteps;
+        S.tau = ph.T / d.nsteps;
+    }
+    __syncthreads();
+    const int n = S.n;
+    // local steps of this launch: a solve with r steps advances r/g_total
+    // local steps per global step (lockstep schedule across grids)
+    const int s_begin = (int)(((int64_t)lp.g_begin * d.nsteps) / lp.g_total);
+    const int s_end = (int)(((int64_t)lp.g_end * d.nsteps) / lp.g_total);
+    if (s_begin >= s_end) return;
+    double* sp = S.scratch;  // [0] = q, [1] = status, [2] = iterations
+    if (s_begin == 0) {
+        // initial state: c = c0 (or 0, Sec. 2.1); p only seeds the
+        // iteration: the cell's own hydrostatic value -rho(c) g y
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            const int j = idx / S.nx;
+            const double c0 = lp.c0 ? lp.c0[d.field_off + idx] : 0.0;
+            S.c[idx] = c0;
+            S.p[idx] = -rho_of(ph, c0) * ph.g * (-1.0 + (j + 0.5) * S.h);
+        }
+        if (threadIdx.x == 0) { sp[1] = 0.0; sp[2] = 0.0; }
+    }
+    if (threadIdx.x == 0) S.q = sp[0];
+    __syncthreads();
+    int status = (int)sp[1];
+    double iters = sp[2];
+    for (int s = s_begin; s < s_end && status != 2; ++s) {
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.cn[idx] = S.c[idx];
+        __syncthreads();
+        bool conv = false;
+        for (int it = 0; it < lp.max_outer; ++it) {
+            double np, nc;
+            residual_pass(ph, S, 0, red, np, nc);
+            if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) { status = 2; break; }
+            if (np <= lp.tol && nc <= lp.tol) { conv = true; break; }
+            iters += 1.0;
+            coarsen_pressure(S);
+            vcycle<T, false>(S, lds, lp.line_waves, lp.line_cap);
+            for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.p[idx] += (double)S.lv[0].x[idx];
+            __syncthreads();
+            residual_pass(ph, S, 1, red, np, nc);
+            coarsen_transport(S);
+            vcycle<T, true>(S, lds, lp.line_waves, lp.line_cap);
+            for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.c[idx] += (double)S.lv[0].x[idx];
+            __syncthreads();
+        }
+        if (!conv && status == 0) status = 1;
+    }
+    if (threadIdx.x == 0) { sp[1] = (double)status; sp[2] = iters; }
+    if (s_end == d.nsteps) {
+        // outputs: c, p at T and the QoI Q = h^2 sum_{x<1} phi rho(c) c (FP64)
+        double part = 0.0;
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            const double cP = S.c[idx];
+            lp.c_out[d.field_off + idx] = cP;
+            if (lp.p_out) lp.p_out[d.field_off + idx] = S.p[idx];
+            if ((idx % S.nx) < S.nx / 2) part += S.phi[idx] * rho_of(ph, cP) * cP;
+        }
+        const double Q = block_sum(part, red);
+        if (threadIdx.x == 0) {
+            lp.qoi_out[d.index] = Q * S.h * S.h;
+            lp.status[d.index] = status;
+            if (lp.iters) lp.iters[d.index] = (int32_t)iters;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ random fields
+// Point values at cell centres of the closed-form fields, or the caller's
+// explicit fields; FP64.  One block per solve.
+__global__ void henry_fields_kernel(Launch lp) {
+    const SolveDesc d = lp.descs[blockIdx.x];
+    const Phys& ph = lp.ph;
+    uint8_t* base = lp.ws + d.ws_off;
+    double* f = reinterpret_cast<double*>(base);
+    const int nx = d.nx, ny = d.ny, n = nx * ny;
+    double* phi = f + 3 * n;
+    double* K = f + 4 * n;
+    double* sp = f + 7 * n;
+    const double h = 1.0 / ny;
+    if (lp.field_kind == 0) {
+        const double x1 = lp.xi[3 * d.index], x2 = lp.xi[3 * d.index + 1], x3 = lp.xi[3 * d.index + 2];
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            const int i = idx % nx, j = idx / nx;
+            const double x = (i + 0.5) * h, y = -1.0 + (j + 0.5) * h;
+            phi[idx] = ph.phi0 * (1.0 + 0.2 * x1 * cos(M_PI * x / 2.0) * cos(M_PI * y));
+            K[idx] = ph.k0 * exp(0.5 * x2 * sin(M_PI * x / 2.0));
+        }
+        if (threadIdx.x == 0) sp[0] = ph.q_in * (1.0 + 0.2 * x3);
+    } else {
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            phi[idx] = lp.phi_in[d.field_off + idx];
+            K[idx] = exp(lp.logk_in[d.field_off + idx]);
+        }
+        if (threadIdx.x == 0) sp[0] = lp.qin_in[d.index];
+    }
+}
+
+}  // namespace henry

@@ -1,0 +1,99 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol `include/henry.h` declares, its sample generator is bit-exact
+with the oracle's and with a Python integer reference of Philox4x32-10, and
+argument validation rejects bad grids and options before any launch."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2302_07804_amd as hm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(hm.LIB_PATH):
+        pytest.fail("libhenry.so is not built (run __graft_entry__.build())")
+    return hm.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "henry.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", hdr, re.M))
+    assert declared == set(hm.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def philox_ref(ctr, key):
+    """Philox4x32-10 from its published definition, Python integers."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    x = list(ctr)
+    k0, k1 = key
+    for _ in range(10):
+        p0, p1 = M0 * x[0], M1 * x[2]
+        x = [((p1 >> 32) ^ x[1] ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF, ((p0 >> 32) ^ x[3] ^ k1) & 0xFFFFFFFF,
+             p0 & 0xFFFFFFFF]
+        k0, k1 = (k0 + W0) & 0xFFFFFFFF, (k1 + W1) & 0xFFFFFFFF
+    return x
+
+
+def test_python_philox_matches_known_answers():
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "philox4x32_10_kat.txt"))
+            if not l.startswith("#")]
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert philox_ref(v[0:4], v[4:6]) == v[6:10]
+
+
+@pytest.mark.parametrize("seed,level,first,count,dim", [(0, 0, 0, 64, 3), (0, 4, 1000, 17, 3), (123456789012, 6, 5,
+                                                                                                   9, 41)])
+def test_sample_xi_bit_exact(L, seed, level, first, count, dim):
+    import oracle
+    a = hm.henry_sample_xi(seed, level, first, count, dim)
+    b = oracle.sample_xi(seed, level, first, count, dim)
+    assert np.array_equal(a, b)
+    # Python integer reference
+    for s in range(count):
+        idx = first + s
+        for d in range(dim):
+            w = philox_ref([d // 2, level, idx & 0xFFFFFFFF, idx >> 32], [seed & 0xFFFFFFFF, seed >> 32])
+            e = d % 2
+            x = ((w[2 * e + 1] << 32) | w[2 * e]) >> 11
+            assert a[s, d] == x * 2.0 ** -52 - 1.0
+
+
+def test_workspace_validation(L):
+    ok = [(16, 8, 50), (256, 128, 800)]
+    assert hm.henry_workspace_bytes(ok) > 0
+    mixed = hm.make_opts(prec=hm.PREC_MIXED)
+    fp64 = hm.make_opts(prec=hm.PREC_FP64)
+    assert hm.henry_workspace_bytes(ok, fp64) > hm.henry_workspace_bytes(ok, mixed)
+    for bad in [[(16, 16, 50)], [(24, 12, 50)], [(16, 8, 0)], [(2048, 1024, 10)], [(0, 0, 5)]]:
+        with pytest.raises(hm.HenryError) as e:
+            hm.henry_workspace_bytes(bad)
+        assert e.value.code == hm.HENRY_EINVAL
+    for kw in [dict(prec=7), dict(max_outer=0), dict(tol=0.0), dict(tol=float("nan")), dict(threads=96),
+               dict(steps_per_launch=-1)]:
+        with pytest.raises(hm.HenryError):
+            hm.henry_workspace_bytes(ok, hm.make_opts(**kw))
+    assert hm.henry_workspace_bytes([]) >= 0
+
+
+def test_sample_xi_rejects_bad_arguments(L):
+    out = (ct.c_double * 3)()
+    assert L.henry_sample_xi(0, -1, 0, 1, 3, out) == hm.HENRY_EINVAL
+    assert L.henry_sample_xi(0, 0, 0, 1, 0, out) == hm.HENRY_EINVAL
+    assert L.henry_sample_xi(0, 0, 0, 1, 3, None) == hm.HENRY_EINVAL
+
+
+def test_solve_batch_rejects_null_context(L):
+    g = hm.grids([(16, 8, 50)])
+    rc = L.henry_solve_batch(None, g, 1, 0, None, None, None, None, None, None, None, None, None, None, None, None,
+                             0, None)
+    assert rc == hm.HENRY_EINVAL
+    assert hm.strerror(hm.HENRY_EINVAL) == "invalid argument"

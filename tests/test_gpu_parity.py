@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (element by element on the same seeded inputs):
+  * FP64 inner path: max |c_gpu - c_oracle| <= 1e-8 * max |c_oracle|, and
+    the QoI within 1e-8 relative;
+  * mixed path (FP32 V-cycles inside FP64 defect correction): 1e-5.
+Both paths stop a step when the scaled FP64 residual max norms fall below
+tol = 1e-10; the prototype study of this iteration gave c errors of about
+1e-11 at that tolerance, so the bars leave three orders of headroom.
+"""
+import numpy as np
+import pytest
+
+import henry_inputs as hi
+import oracle
+import paper_2302_07804_amd as hm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible for a gpu-marked test")
+    hm.lib()  # raises if the native library is missing
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    c = hm.Context(hi.PHYS, 0)
+    yield c
+    c.close()
+
+
+def run(torch, ctx, solves, xi=None, prec=hm.PREC_FP64, **kw):
+    opts = hm.make_opts(prec=prec, tol=kw.pop("tol", 1e-10), max_outer=kw.pop("max_outer", 60), **kw)
+    xi_d = None if xi is None else torch.tensor(np.asarray(xi), dtype=torch.float64, device="cuda")
+    out = hm.solve(ctx, solves, xi=xi_d, opts=opts, want_p=True)
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle_jobs(solves, xis):
+    return oracle.solve_many(hi.PHYS, [(s[0], s[1], s[2], x) for s, x in zip(solves, xis)])
+
+
+def check_against(out, solves, refs, bar):
+    cs = hm.unpack(out["c"], solves)
+    q = out["qoi"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    worst = 0.0
+    for k, (s, r) in enumerate(zip(solves, refs)):
+        assert st[k] == hm.STATUS_OK, f"solve {k} {s}: status {st[k]}"
+        c = cs[k].cpu().numpy()
+        err = np.abs(c - r["c"]).max() / np.abs(r["c"]).max()
+        qerr = abs(q[k] - r["qoi"]) / abs(r["qoi"])
+        worst = max(worst, err, qerr)
+        assert err <= bar, f"solve {k} {s}: c rel err {err:.3e}"
+        assert qerr <= bar, f"solve {k} {s}: Q rel err {qerr:.3e}"
+    return worst
+
+
+@pytest.mark.parametrize("prec,bar", [(hm.PREC_FP64, 1e-8), (hm.PREC_MIXED, 1e-5)])
+def test_single_level0_solve(torch_cuda, ctx, prec, bar):
+    solves = [(16, 8, 50)]
+    xi = hm.henry_sample_xi(0, 0, 0, 1, 3)
+    out = run(torch_cuda, ctx, solves, xi, prec)
+    refs = oracle_jobs(solves, xi)
+    worst = check_against(out, solves, refs, bar)
+    print(f"16x8/50 prec={prec}: worst rel err {worst:.3e}, iterations {out['iters'].cpu().numpy()}")
+
+
+@pytest.mark.parametrize("prec,bar", [(hm.PREC_FP64, 1e-8), (hm.PREC_MIXED, 1e-5)])
+def test_ragged_batch_several_grids(torch_cuda, ctx, prec, bar):
+    """Solves of three grids and step counts share one call (several tiles
+    per line at 64x32, odd sample counts per grid)."""
+    solves = [(16, 8, 50)] * 3 + [(32, 16, 100)] * 2 + [(64, 32, 200)]
+    xi = hm.henry_sample_xi(0, 1, 0, len(solves), 3)
+    out = run(torch_cuda, ctx, solves, xi, prec)
+    refs = oracle_jobs(solves, xi)
+    worst = check_against(out, solves, refs, bar)
+    print(f"ragged prec={prec}: worst rel err {worst:.3e}, iterations {out['iters'].cpu().numpy()}")
+
+
+def test_mixed_and_fp64_agree_closely(torch_cuda, ctx):
+    solves = [(32, 16, 100)] * 4
+    xi = hm.henry_sample_xi(0, 2, 0, 4, 3)
+    a = run(torch_cuda, ctx, solves, xi, hm.PREC_FP64)
+    b = run(torch_cuda, ctx, solves, xi, hm.PREC_MIXED)
+    assert (a["c"] - b["c"]).abs().max().item() < 1e-8
+
+
+def test_explicit_fields_match_oracle(torch_cuda, ctx):
+    """Caller-provided per-cell porosity and log-permeability."""
+    torch = torch_cuda
+    nx, ny, r = 32, 16, 60
+    rng = np.random.default_rng(3)
+    x = (np.arange(nx) + 0.5) / ny
+    y = -1 + (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    phi = 0.35 * (1 + 0.15 * np.sin(2 * X + rng.uniform()) * np.cos(3 * Y))
+    logk = np.log(hi.PHYS["k0"]) + 0.4 * np.cos(X + 2 * Y + rng.uniform())
+    q = hi.PHYS["q_in"] * 1.1
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64, device="cuda")
+    opts = hm.make_opts(prec=hm.PREC_FP64, tol=1e-10, max_outer=60)
+    out = hm.solve(ctx, [(nx, ny, r)], phi=dev(phi), logk=dev(logk), qin=dev([q]), opts=opts)
+    torch.cuda.synchronize()
+    ref = oracle.solve(hi.PHYS, r, phi, np.exp(logk), q)
+    c = out["c"].cpu().numpy().reshape(ny, nx)
+    assert np.abs(c - ref["c"]).max() <= 1e-8 * np.abs(ref["c"]).max()
+    assert abs(out["qoi"].item() - ref["qoi"]) <= 1e-8 * ref["qoi"]
+
+
+def test_chunked_launches_match_single_launch(torch_cuda, ctx):
+    solves = [(16, 8, 50)] * 2 + [(32, 16, 100)]
+    xi = hm.henry_sample_xi(0, 1, 0, 3, 3)
+    a = run(torch_cuda, ctx, solves, xi, hm.PREC_MIXED)
+    b = run(torch_cuda, ctx, solves, xi, hm.PREC_MIXED, steps_per_launch=7)
+    assert torch_cuda.equal(a["c"], b["c"]) and torch_cuda.equal(a["qoi"], b["qoi"])
+
+
+def test_repeat_is_bitwise_deterministic(torch_cuda, ctx):
+    solves = [(32, 16, 100)] * 3
+    xi = hm.henry_sample_xi(0, 5, 0, 3, 3)
+    a = run(torch_cuda, ctx, solves, xi, hm.PREC_MIXED)
+    b = run(torch_cuda, ctx, solves, xi, hm.PREC_MIXED)
+    assert torch_cuda.equal(a["c"], b["c"]) and torch_cuda.equal(a["qoi"], b["qoi"])
+
+
+def test_no_convergence_is_reported_per_solve(torch_cuda, ctx):
+    solves = [(16, 8, 50)] * 2
+    xi = hm.henry_sample_xi(0, 0, 0, 2, 3)
+    out = run(torch_cuda, ctx, solves, xi, hm.PREC_MIXED, max_outer=1)
+    assert list(out["status"].cpu().numpy()) == [hm.STATUS_NOCONV] * 2
+
+
+def test_hydrostatic_seawater_on_gpu(torch_cuda):
+    """c0 = 1, no recharge, no diffusion: p = -rho1 g y, zero Darcy flux."""
+    torch = torch_cuda
+    ph = dict(hi.PHYS, D=0.0, q_in=0.0)
+    c = hm.Context(ph, 0)
+    nx, ny, r = 32, 16, 10
+    rng = np.random.default_rng(1)
+    phi = 0.35 * (1 + 0.2 * rng.uniform(-1, 1, (ny, nx)))
+    logk = np.log(ph["k0"]) + 0.5 * rng.uniform(-1, 1, (ny, nx))
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64, device="cuda")
+    out = hm.solve(c, [(nx, ny, r)], phi=dev(phi), logk=dev(logk), qin=dev([0.0]), c0=dev(np.ones((ny, nx))),
+                   opts=hm.make_opts(prec=hm.PREC_FP64, tol=1e-12, max_outer=60), want_p=True)
+    torch.cuda.synchronize()
+    y = -1 + (np.arange(ny) + 0.5) / ny
+    p_exact = np.repeat((-ph["rho1"] * ph["g"] * y)[:, None], nx, 1)
+    assert np.abs(out["c"].cpu().numpy() - 1.0).max() <= 1e-14
+    np.testing.assert_allclose(out["p"].cpu().numpy().reshape(ny, nx), p_exact, rtol=1e-12)
+    c.close()
+
+
+def test_empty_batch_is_a_no_op(torch_cuda, ctx):
+    L = hm.lib()
+    assert L.henry_solve_batch(ctx.handle, None, 0, 0, None, None, None, None, None, None, None, None, None, None,
+                               None, None, 0, None) == hm.HENRY_OK
+
+
+def test_workspace_too_small_is_enomem(torch_cuda, ctx):
+    torch = torch_cuda
+    solves = [(16, 8, 50)]
+    ws = torch.empty(1024, dtype=torch.float64, device="cuda")
+    xi = torch.zeros(3, dtype=torch.float64, device="cuda")
+    o = torch.empty(128, dtype=torch.float64, device="cuda")
+    q = torch.empty(1, dtype=torch.float64, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(hm.HenryError) as e:
+        hm.henry_solve_batch(ctx, solves, hm.FIELD_CLOSED3, xi=xi, c_out=o, qoi_out=q, status=st, workspace=ws)
+    assert e.value.code == hm.HENRY_ENOMEM
+
+
+def test_mlmc_level_estimate_matches_oracle_stats(torch_cuda, ctx):
+    torch = torch_cuda
+    rng = np.random.default_rng(11)
+    m = [37, 9, 5]
+    grids = [(16, 8, 50), (32, 16, 100), (64, 32, 200)]
+    cf = [rng.uniform(size=(m[l], grids[l][1], grids[l][0])) for l in range(3)]
+    cc = [None] + [rng.uniform(size=(m[l], grids[l - 1][1], grids[l - 1][0])) for l in range(1, 3)]
+    qf = [rng.uniform(size=m[l]) for l in range(3)]
+    qc = [None] + [rng.uniform(size=m[l]) for l in range(1, 3)]
+    dev = lambda a: None if a is None else torch.tensor(a.reshape(a.shape[0], -1), dtype=torch.float64,
+                                                        device="cuda")
+    mean = [torch.empty(g[0] * g[1], dtype=torch.float64, device="cuda") for g in grids]
+    var = [torch.empty(g[0] * g[1], dtype=torch.float64, device="cuda") for g in grids]
+    qs = torch.empty(6, dtype=torch.float64, device="cuda")
+    E = torch.empty(64 * 32, dtype=torch.float64, device="cuda")
+    ve = torch.empty(2, dtype=torch.float64, device="cuda")
+    qdev = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device="cuda")
+    hm.mlmc_level_estimate(ctx, grids, m, [dev(x) for x in cf], [dev(x) for x in cc], [qdev(x) for x in qf],
+                           [qdev(x) for x in qc], mean, var, qs, E, ve)
+    torch.cuda.synchronize()
+    means, vars_, qm, qv = [], [], [], []
+    for l in range(3):
+        mu, v = oracle.level_stats(cf[l], cc[l])
+        np.testing.assert_allclose(mean[l].cpu().numpy().reshape(mu.shape), mu, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(var[l].cpu().numpy().reshape(v.shape), v, rtol=1e-12, atol=1e-15)
+        a, b = oracle.level_stats(qf[l], qc[l])
+        assert qs[2 * l].item() == pytest.approx(float(a), rel=1e-13)
+        assert qs[2 * l + 1].item() == pytest.approx(float(b), rel=1e-12)
+        means.append(mu); vars_.append(v); qm.append(a); qv.append(b)
+    Eo, vo = oracle.mlmc_estimate(means, vars_, m)
+    np.testing.assert_allclose(E.cpu().numpy().reshape(Eo.shape), Eo, rtol=1e-13, atol=1e-15)
+    _, vq = oracle.mlmc_estimate(qm, qv, m)
+    assert ve[0].item() == pytest.approx(float(vq), rel=1e-13)
+    assert ve[1].item() == pytest.approx(float(vo.max()), rel=1e-13)
+
+
+def test_graph_replays_match_eager(torch_cuda, ctx):
+    """steps_per_launch > 0 captures the lockstep time loop once into a
+    hipGraph; replays on the same buffers, with eager work in between, must
+    all give the eager result."""
+    torch = torch_cuda
+    solves = [(16, 8, 50)] * 3 + [(32, 16, 100)] * 2
+    xi = torch.tensor(hm.henry_sample_xi(0, 2, 0, len(solves), 3), dtype=torch.float64, device="cuda")
+    eager = hm.solve(ctx, solves, xi=xi, opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60))
+    torch.cuda.synchronize()
+    gopts = hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60, steps_per_launch=5)
+    cells = sum(s[0] * s[1] for s in solves)
+    ws_b = hm.henry_workspace_bytes(solves, gopts)
+    raw = torch.empty(ws_b // 8 + 64, dtype=torch.float64, device="cuda")
+    off = (-raw.data_ptr()) % 256 // 8
+    ws = raw[off:off + (ws_b + 7) // 8]
+    c = torch.empty(cells, dtype=torch.float64, device="cuda")
+    q = torch.empty(len(solves), dtype=torch.float64, device="cuda")
+    st = torch.empty(len(solves), dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        c.fill_(-1.0)
+        q.fill_(-1.0)
+        hm.henry_solve_batch(ctx, solves, hm.FIELD_CLOSED3, xi=xi, opts=gopts, c_out=c, qoi_out=q, status=st,
+                             workspace=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(c, eager["c"]), f"replay {rep}"
+        assert torch.equal(q, eager["qoi"]), f"replay {rep}"
+        _ = (torch.randn(1000, device="cuda") ** 2).sum().item()  # eager work between replays
