@@ -83,7 +83,8 @@ typedef struct {
     int32_t max_outer;        /* defect-correction iterations per step (>= 1)   */
     double tol;               /* stop a step when max_P |R_P| tau/(h^2 phi_P rho0)
                                  <= tol for both the fluid and the salt equation */
-    int32_t threads;          /* threads per solve-workgroup; 0 = tuned choice  */
+    int32_t threads;          /* threads per solve-workgroup (64..512, power of
+                                 two); 0 = tuned choice                          */
     int32_t steps_per_launch; /* 0 = whole time loop in one launch per grid
                                  group; k > 0 = launches of k global steps, all
                                  captured into one hipGraph and replayed        */

@@ -24,7 +24,6 @@
 namespace {
 
 constexpr int kStreams = 4;
-constexpr size_t kLdsBudget = 96 * 1024;
 
 struct Group {
     int nx, ny, threads;
@@ -49,7 +48,6 @@ struct henry_ctx {
     size_t pinned_bytes = 0;
     hipEvent_t staging_done = nullptr;
     std::map<long, int> tuned_threads;  // (nx, prec) -> threads
-    size_t lds_budget = 64 * 1024;
     // profiling of the last batch
     std::vector<henry_group_time_t> prof;
     std::vector<hipEvent_t> prof_ev;  // 2 per group
@@ -89,7 +87,7 @@ int check_opts(const henry_opts_t* o) {
     if (o->prec != HENRY_PREC_FP64 && o->prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
     if (o->max_outer < 1 || o->max_outer > 100000) return HENRY_EINVAL;
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return HENRY_EINVAL;
-    if (o->threads != 0 && (o->threads < 64 || o->threads > 1024 || !pow2(o->threads))) return HENRY_EINVAL;
+    if (o->threads != 0 && (o->threads < 64 || o->threads > 512 || !pow2(o->threads))) return HENRY_EINVAL;
     if (o->steps_per_launch < 0) return HENRY_EINVAL;
     if (o->profile != 0 && o->profile != 1) return HENRY_EINVAL;
     if (o->serial_groups != 0 && o->serial_groups != 1) return HENRY_EINVAL;
@@ -105,8 +103,7 @@ int default_threads(int nx, int ny) {
     if (cells <= 128) return 64;
     if (cells <= 512) return 128;
     if (cells <= 2048) return 256;
-    if (cells <= 8192) return 512;
-    return 1024;
+    return 512;
 }
 
 int64_t desc_bytes(int nsolves) { return henry::align256((int64_t)nsolves * (int64_t)sizeof(henry::SolveDesc)); }
@@ -133,14 +130,6 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
         hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
-        const size_t esz = prec == HENRY_PREC_MIXED ? sizeof(float) : sizeof(double);
-        const int cap = G.nx;  // longest line of the finest level
-        const int nw = G.threads / henry::kWave;
-        int lw = (int)std::min<size_t>((size_t)nw, ctx->lds_budget / (8 * (size_t)cap * esz));
-        if (lw < 1) lw = 1;
-        l.line_waves = lw;
-        l.line_cap = cap;
-        const size_t lds = (size_t)lw * 8 * cap * esz;
         // lockstep time chunks: local step s of a solve with r steps runs in
         // global step s * rmax / r; one chunk when steps_per_launch == 0
         const int chunk = spl > 0 ? spl : rmax;
@@ -156,9 +145,9 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
             l.g_end = std::min(rmax, g0 + chunk);
             l.g_total = rmax;
             if (prec == HENRY_PREC_MIXED)
-                hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nb), dim3(G.threads), lds, st, l);
+                hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nb), dim3(G.threads), 0, st, l);
             else
-                hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nb), dim3(G.threads), lds, st, l);
+                hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nb), dim3(G.threads), 0, st, l);
         }
         if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
         if (profile && hipEventRecord(ctx->prof_ev[2 * gi + 1], st) != hipSuccess) return HENRY_EHIP;
@@ -220,16 +209,6 @@ int henry_ctx_create(henry_ctx** out, const henry_phys_t* phys, int device) {
     ok &= hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
     ok &= hipEventCreateWithFlags(&c->cap_in, hipEventDisableTiming) == hipSuccess;
     ok &= hipEventCreateWithFlags(&c->cap_out, hipEventDisableTiming) == hipSuccess;
-    // line systems are staged in up to kLdsBudget bytes of dynamic LDS; if
-    // the runtime refuses more than the 64 KiB default, stay below it
-    c->lds_budget = kLdsBudget;
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&henry::henry_solve_kernel<float>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget) != hipSuccess ||
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&henry::henry_solve_kernel<double>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget) != hipSuccess) {
-        (void)hipGetLastError();
-        c->lds_budget = 64 * 1024;
-    }
     ok &= hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         henry_ctx_destroy(c);

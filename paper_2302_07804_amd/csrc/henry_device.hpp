@@ -24,8 +24,9 @@
 // mixed path) or double (the plain FP64 path): one code path, two
 // instantiations.  Memory: per-solve FP64 state and per-level inner arrays
 // in a caller-provided workspace (L2 / Infinity-Cache resident for the
-// grid sizes of an MLMC hierarchy); line systems are staged in LDS and
-// solved by parallel cyclic reduction, one wavefront per line.
+// grid sizes of an MLMC hierarchy); line systems are solved in registers by
+// segmented elimination with a cyclic-reduction interface solve across the
+// lanes of a wavefront.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,8 +70,6 @@ struct Launch {
     int32_t field_kind;
     int32_t g_begin, g_end;  // global step range of this launch
     int32_t g_total;         // global steps of the whole batch (max nsteps)
-    int32_t line_waves;      // waves that take part in line solves (LDS budget)
-    int32_t line_cap;        // LDS elements reserved per line array
 };
 
 // ------------------------------------------------------------------ layout
@@ -94,12 +93,15 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
     return align256((int64_t)(kLevelArrays * nx * ny + kRowArrays * ny) * (int64_t)sizeof(T));
 }
 
-// FP64 arrays: p, c, cn, phi, K, Rp, Rc, then 8 doubles of scratch.
+// FP64 arrays: p, c, cn, phi, K, Rp, Rc, then kScratch doubles of scratch
+// ([0] recharge, [1] status, [2] outer iterations, [8..] phase timers of
+// builds with HENRY_PHASE_TIMERS).
 constexpr int kF64Arrays = 7;
+constexpr int kScratch = 32;
 
 template <typename T>
 __host__ __device__ inline int64_t solve_bytes(int nx, int ny) {
-    int64_t b = align256((int64_t)kF64Arrays * nx * ny * 8 + 64);
+    int64_t b = align256((int64_t)kF64Arrays * nx * ny * 8 + kScratch * 8);
     int lx = nx, ly = ny;
     const int L = num_levels(ny);
     for (int l = 0; l < L; ++l) {
@@ -132,7 +134,7 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny) {
     const int n = nx * ny;
     S.p = f; S.c = f + n; S.cn = f + 2 * n; S.phi = f + 3 * n; S.K = f + 4 * n; S.Rp = f + 5 * n;
     S.Rc = f + 6 * n; S.scratch = f + 7 * n;
-    uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + 64);
+    uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
     int lx = nx, ly = ny;
     for (int l = 0; l < S.L; ++l) {
         T* a = reinterpret_cast<T*>(q);
@@ -441,13 +443,13 @@ __device__ void prolong_add(const Level<T>& C, Level<T>& F) {
     }
 }
 
-__device__ inline int rweights(int I, int n, int* idx, float* w) {
-    int k = 0;
-    if (I > 0) { idx[k] = 2 * I - 1; w[k++] = 0.25f; }
-    idx[k] = 2 * I; w[k++] = (I == 0) ? 1.0f : 0.75f;
-    idx[k] = 2 * I + 1; w[k++] = (I == n - 1) ? 1.0f : 0.75f;
-    if (I < n - 1) { idx[k] = 2 * I + 2; w[k++] = 0.25f; }
-    return k;
+// 1D restriction weight of fine index I2 = 2I - 1 + a (a = 0..3) for coarse
+// index I of n: (1,3,3,1)/4, with the boundary ghost weight folded in.
+__device__ inline float rweight(int I, int n, int a) {
+    float w = (a == 0 || a == 3) ? 0.25f : 0.75f;
+    if (a == 1 && I == 0) w += 0.25f;
+    if (a == 2 && I == n - 1) w += 0.25f;
+    return w;
 }
 
 template <typename T>
@@ -455,146 +457,238 @@ __device__ void restrict_residual(const Level<T>& F, Level<T>& C) {
     const int n = C.nx * C.ny;
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
         const int I = idx % C.nx, J = idx / C.nx;
-        int ix[4], iy[4];
-        float wx[4], wy[4];
-        const int kx = rweights(I, C.nx, ix, wx), ky = rweights(J, C.ny, iy, wy);
         T s = (T)0;
-        for (int b = 0; b < ky; ++b) {
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) {
+            const int jf = 2 * J - 1 + bq;
+            if (jf < 0 || jf >= F.ny) continue;
             T row = (T)0;
-            for (int a = 0; a < kx; ++a) row += (T)wx[a] * F.r[iy[b] * F.nx + ix[a]];
-            s += (T)wy[b] * row;
+#pragma unroll
+            for (int aq = 0; aq < 4; ++aq) {
+                const int ifn = 2 * I - 1 + aq;
+                if (ifn < 0 || ifn >= F.nx) continue;
+                row += (T)rweight(I, C.nx, aq) * F.r[jf * F.nx + ifn];
+            }
+            s += (T)rweight(J, C.ny, bq) * row;
         }
         C.b[idx] = s;
         C.x[idx] = (T)0;
     }
 }
 
-// r = b - A x on one level.
+// r = b - A x on one level (operands of kBatch cells gathered first).
 template <typename T, bool kTransport>
 __device__ void level_residual(Level<T>& v) {
     const int n = v.nx * v.ny;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int i = idx % v.nx, j = idx / v.nx;
-        const Stencil<T> st = stencil<T, kTransport>(v, i, j);
-        T ax = st.d * v.x[idx];
-        if (i > 0) ax -= st.w * v.x[idx - 1];
-        if (i + 1 < v.nx) ax -= st.e * v.x[idx + 1];
-        if (j > 0) ax -= st.s * v.x[idx - v.nx];
-        if (j + 1 < v.ny) ax -= st.n * v.x[idx + v.nx];
-        v.r[idx] = v.b[idx] - ax;
+    for (int k0 = threadIdx.x; k0 < n; k0 += 4 * blockDim.x) {
+        T res[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * blockDim.x;
+            const int idx = k < n ? k : 0;
+            const int i = idx % v.nx, j = idx / v.nx;
+            const Stencil<T> st = stencil<T, kTransport>(v, i, j);
+            T ax = st.d * v.x[idx];
+            if (i > 0) ax -= st.w * v.x[idx - 1];
+            if (i + 1 < v.nx) ax -= st.e * v.x[idx + 1];
+            if (j > 0) ax -= st.s * v.x[idx - v.nx];
+            if (j + 1 < v.ny) ax -= st.n * v.x[idx + v.nx];
+            res[u] = v.b[idx] - ax;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k0 + u * (int)blockDim.x < n) v.r[k0 + u * blockDim.x] = res[u];
     }
 }
 
 // ------------------------------------------------------------------ smoothers
-// Red-black Gauss-Seidel (pressure): colour (i + j) & 1.
+// Red-black Gauss-Seidel (pressure): colour (i + j) & 1.  Cells of one
+// colour are independent; each thread gathers the operands of kBatch cells
+// before it writes any of them, so their loads are in flight together.
+constexpr int kBatch = 4;
+
 template <typename T>
 __device__ void rbgs(Level<T>& v, int sweeps) {
-    const int half = v.nx >> 1;  // nx is even on every level
-    const int m = half * v.ny;
+    const int nx = v.nx, ny = v.ny;
+    const int half = nx >> 1;  // nx is even on every level
+    const int m = half * ny;
+    const T* te = v.te;
+    const T* tn = v.tn;
+    const T* b = v.b;
+    T* x = v.x;
     for (int s = 0; s < sweeps; ++s)
         for (int col = 0; col < 2; ++col) {
-            for (int k = threadIdx.x; k < m; k += blockDim.x) {
-                const int j = k / half;
-                const int i = 2 * (k - j * half) + ((j + col) & 1);
-                const int idx = j * v.nx + i;
-                const Stencil<T> st = pstencil(v, i, j);
-                T acc = v.b[idx];
-                if (i > 0) acc += st.w * v.x[idx - 1];
-                if (i + 1 < v.nx) acc += st.e * v.x[idx + 1];
-                if (j > 0) acc += st.s * v.x[idx - v.nx];
-                if (j + 1 < v.ny) acc += st.n * v.x[idx + v.nx];
-                v.x[idx] = acc / st.d;
+            for (int k0 = threadIdx.x; k0 < m; k0 += kBatch * blockDim.x) {
+                T num[kBatch], den[kBatch];
+                int at[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int k = k0 + u * blockDim.x;
+                    const int kk = k < m ? k : 0;
+                    const int j = kk / half;
+                    const int i = 2 * (kk - j * half) + ((j + col) & 1);
+                    const int idx = j * nx + i;
+                    at[u] = k < m ? idx : -1;
+                    const T tE = te[idx];
+                    const T tW = (i > 0) ? te[idx - 1] : (T)0;
+                    const T tN = tn[idx];
+                    const T tS = (j > 0) ? tn[idx - nx] : (T)0;
+                    T a = b[idx];
+                    if (i > 0) a += tW * x[idx - 1];
+                    if (i + 1 < nx) a += tE * x[idx + 1];
+                    if (j > 0) a += tS * x[idx - nx];
+                    if (j + 1 < ny) a += tN * x[idx + nx];
+                    num[u] = a;
+                    den[u] = tE + tW + tN + tS;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u)
+                    if (at[u] >= 0) x[at[u]] = num[u] / den[u];
             }
             __syncthreads();
         }
 }
 
-// Parallel cyclic reduction of one tridiagonal system per wavefront, in LDS.
-// Every wave of the block runs the same number of rounds (so that block
-// barriers line up); waves with no line in a round only take the barriers.
-// Line `li` of a colour: x-lines are rows j = col + 2 li, y-lines columns.
+// Segmented line solve.  Every line of one colour is split over T lanes of
+// one wavefront (T a power of two dividing 64), lane t owning the m = len/T
+// consecutive rows t*m .. t*m+m-1 of the line.  The lane's last row is an
+// interface unknown iota_t; its m-1 interior rows are eliminated locally
+// (Thomas, three right-hand sides: the line rhs and the unit couplings to
+// iota_{t-1} and iota_t), which leaves a tridiagonal system in the T
+// interface unknowns.  That reduced system is solved by parallel cyclic
+// reduction across the T lanes with wavefront shuffles, then every lane
+// back-substitutes its interior rows.  All coefficients live in registers;
+// a colour of lines is one block-wide phase.
+template <typename T>
+struct SegRows { static constexpr int value = sizeof(T) == 4 ? 8 : 4; };
+
 template <typename T, bool kXLine>
-__device__ void line_sweep(Level<T>& v, int col, T* lds, int line_waves, int cap) {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+__device__ void line_sweep(Level<T>& v, int col) {
+    constexpr int MS = SegRows<T>::value;
     const int len = kXLine ? v.nx : v.ny;
     const int other = kXLine ? v.ny : v.nx;
     const int nlines = (other - col + 1) >> 1;
-    const int rounds = (nlines + line_waves - 1) / line_waves;
-    T* base = lds + (size_t)w * 8 * cap;
-    T *A = base, *B = base + cap, *C = base + 2 * cap, *D = base + 3 * cap;
-    T *A2 = base + 4 * cap, *B2 = base + 5 * cap, *C2 = base + 6 * cap, *D2 = base + 7 * cap;
-    for (int r = 0; r < rounds; ++r) {
-        const int li = r * line_waves + w;
-        const bool active = (w < line_waves) && (li < nlines);
-        const int fixed = col + 2 * li;
-        if (active) {
-            for (int k = lane; k < len; k += kWave) {
+    const int m = len < MS ? len : MS;  // rows per lane
+    const int TL = len / m;             // lanes per line (<= 64 since len <= 1024)
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t = lane & (TL - 1);
+    const int need = nlines * TL;
+    for (int base = 0; base < need; base += blockDim.x) {
+        const int g = base + threadIdx.x;
+        const int li = g / TL;
+        const bool active = li < nlines;
+        const int fixed = col + 2 * (active ? li : 0);
+        T cp[MS], y[MS], u[MS], w[MS];
+        T ar = (T)0, br = (T)1, cr = (T)0, dr = (T)0;
+        // forward elimination of the interior rows, interface row kept aside
+#pragma unroll
+        for (int q = 0; q < MS; ++q) {
+            if (q < m) {
+                const int k = t * m + q;
                 const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
                 const int idx = j * v.nx + i;
                 const Stencil<T> st = cstencil(v, i, j);
                 T rhs = v.b[idx];
+                T a, c;
                 if (kXLine) {
                     if (j > 0) rhs += st.s * v.x[idx - v.nx];
                     if (j + 1 < v.ny) rhs += st.n * v.x[idx + v.nx];
-                    A[k] = -st.w; C[k] = -st.e;
+                    a = -st.w; c = -st.e;
                 } else {
                     if (i > 0) rhs += st.w * v.x[idx - 1];
                     if (i + 1 < v.nx) rhs += st.e * v.x[idx + 1];
-                    A[k] = -st.s; C[k] = -st.n;
+                    a = -st.s; c = -st.n;
                 }
-                B[k] = st.d; D[k] = rhs;
-            }
-        }
-        __syncthreads();
-        for (int s = 1; s < len; s <<= 1) {
-            if (active) {
-                for (int k = lane; k < len; k += kWave) {
-                    const T a = A[k], b = B[k], c = C[k], d = D[k];
-                    T na = (T)0, nb = b, nc = (T)0, nd = d;
-                    if (k - s >= 0) {
-                        const T k1 = a / B[k - s];
-                        na = -A[k - s] * k1;
-                        nb -= C[k - s] * k1;
-                        nd -= D[k - s] * k1;
-                    }
-                    if (k + s < len) {
-                        const T k2 = c / B[k + s];
-                        nc = -C[k + s] * k2;
-                        nb -= A[k + s] * k2;
-                        nd -= D[k + s] * k2;
-                    }
-                    A2[k] = na; B2[k] = nb; C2[k] = nc; D2[k] = nd;
+                if (q < m - 1) {
+                    const T den = (q > 0) ? st.d - a * cp[q > 0 ? q - 1 : 0] : st.d;
+                    const T inv = (T)1 / den;
+                    const T yprev = (q > 0) ? y[q > 0 ? q - 1 : 0] : (T)0;
+                    const T uprev = (q > 0) ? u[q > 0 ? q - 1 : 0] : (T)0;
+                    const T wprev = (q > 0) ? w[q > 0 ? q - 1 : 0] : (T)0;
+                    cp[q] = c * inv;
+                    y[q] = (rhs - a * yprev) * inv;
+                    u[q] = ((q == 0 ? -a : (T)0) - a * uprev) * inv;
+                    w[q] = ((q == m - 2 ? -c : (T)0) - a * wprev) * inv;
+                } else {
+                    ar = a; br = st.d; cr = c; dr = rhs;
                 }
             }
-            __syncthreads();
-            T* t;
-            t = A; A = A2; A2 = t;
-            t = B; B = B2; B2 = t;
-            t = C; C = C2; C2 = t;
-            t = D; D = D2; D2 = t;
         }
+        // back substitution of the interior rows (coupling to iota_t sits in w)
+#pragma unroll
+        for (int q = MS - 2; q >= 0; --q) {
+            if (q < m - 2) {
+                y[q] -= cp[q] * y[q + 1];
+                u[q] -= cp[q] * u[q + 1];
+                w[q] -= cp[q] * w[q + 1];
+            }
+        }
+        // interior rows next to the interfaces
+        T yL = (T)0, uL = (T)1, wL = (T)0;  // row before the interface (m == 1: iota_{t-1} itself)
+        T yF = (T)0, uF = (T)0, wF = (T)1;  // first row of this lane (m == 1: iota_t itself)
+#pragma unroll
+        for (int q = 0; q < MS; ++q) {
+            if (q == m - 2) { yL = y[q]; uL = u[q]; wL = w[q]; }
+        }
+        if (m >= 2) { yF = y[0]; uF = u[0]; wF = w[0]; }
+        // first row of the next lane of the same line
+        const bool last = (t == TL - 1);
+        const int src = last ? lane : lane + 1;
+        T yN = __shfl(yF, src, kWave), uN = __shfl(uF, src, kWave), wN = __shfl(wF, src, kWave);
+        if (last) { yN = (T)0; uN = (T)0; wN = (T)0; cr = (T)0; }
+        T A = ar * uL;
+        T B = br + ar * wL + cr * uN;
+        T C = cr * wN;
+        T D = dr - ar * yL - cr * yN;
+        // parallel cyclic reduction over the TL interface equations
+        for (int sft = 1; sft < TL; sft <<= 1) {
+            const bool hasL = t >= sft, hasR = t + sft < TL;
+            const int l = hasL ? lane - sft : lane, r = hasR ? lane + sft : lane;
+            const T Al = __shfl(A, l, kWave), Bl = __shfl(B, l, kWave), Cl = __shfl(C, l, kWave),
+                    Dl = __shfl(D, l, kWave);
+            const T Ar = __shfl(A, r, kWave), Br = __shfl(B, r, kWave), Cr = __shfl(C, r, kWave),
+                    Dr = __shfl(D, r, kWave);
+            T nA = (T)0, nB = B, nC = (T)0, nD = D;
+            if (hasL) {
+                const T k1 = A / Bl;
+                nA = -Al * k1;
+                nB -= Cl * k1;
+                nD -= Dl * k1;
+            }
+            if (hasR) {
+                const T k2 = C / Br;
+                nC = -Cr * k2;
+                nB -= Ar * k2;
+                nD -= Dr * k2;
+            }
+            A = nA; B = nB; C = nC; D = nD;
+        }
+        const T iota = D / B;
+        const T left0 = __shfl(iota, t > 0 ? lane - 1 : lane, kWave);
+        const T left = t > 0 ? left0 : (T)0;
         if (active) {
-            for (int k = lane; k < len; k += kWave) {
-                const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
-                v.x[j * v.nx + i] = D[k] / B[k];
+#pragma unroll
+            for (int q = 0; q < MS; ++q) {
+                if (q < m) {
+                    const int k = t * m + q;
+                    const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
+                    v.x[j * v.nx + i] = (q < m - 1) ? y[q] + u[q] * left + w[q] * iota : iota;
+                }
             }
         }
-        __syncthreads();
-        // restore buffer roles for the next round (pointer parity)
-        A = base; B = base + cap; C = base + 2 * cap; D = base + 3 * cap;
-        A2 = base + 4 * cap; B2 = base + 5 * cap; C2 = base + 6 * cap; D2 = base + 7 * cap;
     }
+    __syncthreads();
 }
 
 // One zebra sweep: x-lines (even rows, odd rows), then y-lines.
 template <typename T>
-__device__ void line_smooth(Level<T>& v, T* lds, int line_waves, int cap, int sweeps) {
+__device__ void line_smooth(Level<T>& v, int sweeps) {
     for (int s = 0; s < sweeps; ++s) {
-        line_sweep<T, true>(v, 0, lds, line_waves, cap);
-        line_sweep<T, true>(v, 1, lds, line_waves, cap);
+        line_sweep<T, true>(v, 0);
+        line_sweep<T, true>(v, 1);
         if (v.ny > 1) {
-            line_sweep<T, false>(v, 0, lds, line_waves, cap);
-            line_sweep<T, false>(v, 1, lds, line_waves, cap);
+            line_sweep<T, false>(v, 0);
+            line_sweep<T, false>(v, 1);
         }
     }
 }
@@ -603,11 +697,11 @@ __device__ void line_smooth(Level<T>& v, T* lds, int line_waves, int cap, int sw
 // The coarsest level of every hierarchy has one row (ny = 1, nx = 2): the
 // system is a single x-line, solved exactly.
 template <typename T, bool kTransport>
-__device__ void vcycle(Solve<T>& S, T* lds, int line_waves, int cap) {
+__device__ void vcycle(Solve<T>& S) {
     const int L = S.L;
     for (int l = 0; l < L - 1; ++l) {
         Level<T>& v = S.lv[l];
-        if constexpr (kTransport) line_smooth(v, lds, line_waves, cap, 1);
+        if constexpr (kTransport) line_smooth(v, 1);
         else rbgs(v, 2);
         level_residual<T, kTransport>(v);
         __syncthreads();
@@ -616,21 +710,14 @@ __device__ void vcycle(Solve<T>& S, T* lds, int line_waves, int cap) {
     }
     {
         Level<T>& v = S.lv[L - 1];
-        if constexpr (kTransport) line_sweep<T, true>(v, 0, lds, line_waves, cap);
+        if constexpr (kTransport) line_sweep<T, true>(v, 0);
         else {
-            // pressure coarsest (2 x 1 cells): direct Thomas solve in one thread
+            // pressure coarsest (2 x 1 cells): direct solve of the 2 x 2 system
             if (threadIdx.x == 0) {
-                T cp[2], dp[2];
-                const int n = v.nx;  // == 2 by construction
-                for (int i = 0; i < n; ++i) {
-                    const Stencil<T> st = pstencil(v, i, 0);
-                    const T a = -st.w, b = st.d, c = -st.e, d = v.b[i];
-                    const T den = (i > 0) ? b - a * cp[i - 1] : b;
-                    cp[i] = c / den;
-                    dp[i] = (i > 0) ? (d - a * dp[i - 1]) / den : d / den;
-                }
-                v.x[n - 1] = dp[n - 1];
-                for (int i = n - 2; i >= 0; --i) v.x[i] = dp[i] - cp[i] * v.x[i + 1];
+                const Stencil<T> s0 = pstencil(v, 0, 0), s1 = pstencil(v, 1, 0);
+                const T det = s0.d * s1.d - s0.e * s1.w;
+                v.x[0] = (v.b[0] * s1.d + s0.e * v.b[1]) / det;
+                v.x[1] = (s0.d * v.b[1] + s1.w * v.b[0]) / det;
             }
             __syncthreads();
         }
@@ -639,18 +726,16 @@ __device__ void vcycle(Solve<T>& S, T* lds, int line_waves, int cap) {
         Level<T>& v = S.lv[l];
         prolong_add(S.lv[l + 1], v);
         __syncthreads();
-        if constexpr (kTransport) line_smooth(v, lds, line_waves, cap, 1);
+        if constexpr (kTransport) line_smooth(v, 1);
         else rbgs(v, 2);
     }
 }
 
 // ------------------------------------------------------------------ the solve kernel
 template <typename T>
-__global__ void __launch_bounds__(1024) henry_solve_kernel(Launch lp) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+__global__ void __launch_bounds__(512) henry_solve_kernel(Launch lp) {
     __shared__ Solve<T> S;
     __shared__ double red[16];
-    T* lds = reinterpret_cast<T*>(smem_raw);
     const SolveDesc d = lp.descs[blockIdx.x];
     const Phys& ph = lp.ph;
     if (threadIdx.x == 0) {
@@ -681,29 +766,51 @@ __global__ void __launch_bounds__(1024) henry_solve_kernel(Launch lp) {
     __syncthreads();
     int status = (int)sp[1];
     double iters = sp[2];
+#ifdef HENRY_PHASE_TIMERS
+    uint64_t tacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t tlast = wall_clock64();
+#define HENRY_PT(k) do { const uint64_t t_ = wall_clock64(); tacc[k] += t_ - tlast; tlast = t_; } while (0)
+#else
+#define HENRY_PT(k) do { } while (0)
+#endif
     for (int s = s_begin; s < s_end && status != 2; ++s) {
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.cn[idx] = S.c[idx];
         __syncthreads();
         bool conv = false;
+        HENRY_PT(7);
         for (int it = 0; it < lp.max_outer; ++it) {
             double np, nc;
             residual_pass(ph, S, 0, red, np, nc);
+            HENRY_PT(0);
             if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) { status = 2; break; }
             if (np <= lp.tol && nc <= lp.tol) { conv = true; break; }
             iters += 1.0;
             coarsen_pressure(S);
-            vcycle<T, false>(S, lds, lp.line_waves, lp.line_cap);
+            HENRY_PT(1);
+            vcycle<T, false>(S);
+            HENRY_PT(2);
             for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.p[idx] += (double)S.lv[0].x[idx];
             __syncthreads();
             residual_pass(ph, S, 1, red, np, nc);
+            HENRY_PT(3);
             coarsen_transport(S);
-            vcycle<T, true>(S, lds, lp.line_waves, lp.line_cap);
+            HENRY_PT(4);
+            vcycle<T, true>(S);
+            HENRY_PT(5);
             for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.c[idx] += (double)S.lv[0].x[idx];
             __syncthreads();
+            HENRY_PT(6);
         }
         if (!conv && status == 0) status = 1;
     }
-    if (threadIdx.x == 0) { sp[1] = (double)status; sp[2] = iters; }
+#undef HENRY_PT
+    if (threadIdx.x == 0) {
+        sp[1] = (double)status;
+        sp[2] = iters;
+#ifdef HENRY_PHASE_TIMERS
+        for (int k = 0; k < 8; ++k) sp[8 + k] = (double)tacc[k];
+#endif
+    }
     if (s_end == d.nsteps) {
         // outputs: c, p at T and the QoI Q = h^2 sum_{x<1} phi rho(c) c (FP64)
         double part = 0.0;
