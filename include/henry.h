@@ -159,6 +159,38 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
  * with the recorded events (blocks the host until that work is done). */
 int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int32_t* ngroups);
 
+/* Workspace for henry_adjoint_batch: the forward workspace plus, per solve,
+ * FP64 adjoint state and checkpoints: 8 (10 n + 8 + (ceil(r/k) + k + 1) 2 n)
+ * bytes for n cells, r steps, checkpoint interval k. */
+int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
+                                  const henry_opts_t* opts, int32_t ckpt_every, size_t* bytes_out);
+
+/* Discrete adjoint of the batched solves (not in the paper; gradients of
+ * the QoI of henry_solve_batch with respect to the uncertain inputs of
+ * Sec. 2.2).  For the implicit steps R^n(u^n, c^{n-1}) = 0 and
+ * Q = h^2 sum_{x<1} phi rho(c^N) c^N:
+ *   (J^N)^T lam^N = (dQ/du^N)^T,  (J^n)^T lam^n = -(dR^{n+1}/dc^n)^T lam^{n+1},
+ *   dQ/dtheta = dQ/dtheta|explicit - sum_n (lam^n)^T dR^n/dtheta,
+ * J^n the exact step Jacobian.  Each transposed system is solved by FP64
+ * defect correction to max |r|/diag <= adj_tol * max |b|/diag (at most
+ * adj_max_it iterations) with the forward V-cycles (opts->prec inner
+ * precision) as preconditioner.  The forward pass keeps (p, c) every
+ * ckpt_every steps and recomputes each segment during the reverse sweep.
+ *   qoi_out   device [nsolves]
+ *   dq_dxi    device [nsolves][3] (CLOSED3 only; must be NULL for EXPLICIT)
+ *   dq_dlogk  device packed per cell, dQ/d(log K), or NULL
+ *   dq_dphi   device packed per cell, dQ/dphi, or NULL
+ *   dq_dq     device [nsolves], dQ/dq (q in m/s), or NULL
+ *   status    device [nsolves]: HENRY_STATUS_NOCONV if a forward or an
+ *             adjoint step did not converge
+ *   iters     device [nsolves] forward + adjoint iterations, or NULL
+ * Errors as henry_solve_batch. */
+int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                        const double* xi, const double* phi, const double* logk, const double* qin,
+                        const henry_opts_t* opts, int32_t ckpt_every, double adj_tol, int32_t adj_max_it,
+                        double* qoi_out, double* dq_dxi, double* dq_dlogk, double* dq_dphi, double* dq_dq,
+                        int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes, void* stream);
+
 /* MLMC level-difference statistics (Sec. 3: eq:EgL / eq:A, Def. eq:Yell).
  * For each level l = 0..L with m[l] samples on grid fine[l]:
  *   Y_l = c_l - I c_{l-1}   (field; I = piecewise-constant injection from

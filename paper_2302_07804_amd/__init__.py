@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libhenry.so")
 _SOURCES = [os.path.join(_HERE, "csrc", "henry_api.hip")]
-_DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlmc.hpp")] + \
+_DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlmc.hpp", "henry_adjoint.hpp")] + \
     [os.path.join(_ROOT, "include", "henry.h")]
 
 HENRY_OK, HENRY_EINVAL, HENRY_ENOMEM, HENRY_EHIP, HENRY_ENOCONV, HENRY_ENONFINITE = 0, -1, -2, -3, -4, -5
@@ -25,7 +25,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 # every symbol the header declares
 EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opts_default", "henry_sample_xi",
-           "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "mlmc_level_estimate")
+           "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_adjoint_workspace_bytes",
+           "henry_adjoint_batch", "mlmc_level_estimate")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -101,6 +102,10 @@ def lib():
     L.henry_solve_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), vp, vp,
                                     vp, vp, vp, vp, ct.c_size_t, vp]
     L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
+    L.henry_adjoint_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), i32,
+                                                ct.POINTER(ct.c_size_t)]
+    L.henry_adjoint_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, ct.POINTER(Opts), i32, dbl, i32,
+                                      vp, vp, vp, vp, vp, vp, vp, vp, ct.c_size_t, vp]
     L.mlmc_level_estimate.argtypes = [vp, i32, ct.POINTER(Grid), ct.POINTER(i32), ct.POINTER(vp), ct.POINTER(vp),
                                       ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), vp, vp, vp, vp]
     _lib = L
@@ -255,3 +260,118 @@ def unpack(flat, solves):
         res.append(flat[off:off + n].view(int(s[1]), int(s[0])))
         off += n
     return res
+
+
+# ------------------------------------------------------------------ discrete adjoint
+def henry_adjoint_workspace_bytes(solves, opts: Opts | None = None, ckpt_every: int = 20, ctx=None) -> int:
+    g = grids(solves)
+    n = ct.c_size_t()
+    _chk(lib().henry_adjoint_workspace_bytes(ctx, g, len(solves), ct.byref(opts) if opts else None, ckpt_every,
+                                             ct.byref(n)), "henry_adjoint_workspace_bytes")
+    return n.value
+
+
+def henry_adjoint_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None,
+                        opts: Opts | None = None, ckpt_every=20, adj_tol=1e-10, adj_max_it=60, qoi_out=None,
+                        dq_dxi=None, dq_dlogk=None, dq_dphi=None, dq_dq=None, status=None, iters=None,
+                        workspace=None, stream=None):
+    """Thin wrapper: tensors are device tensors owned by the caller."""
+    g = grids(solves)
+    rc = lib().henry_adjoint_batch(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk), _ptr(qin),
+                                   ct.byref(opts) if opts else None, int(ckpt_every), float(adj_tol),
+                                   int(adj_max_it), _ptr(qoi_out), _ptr(dq_dxi), _ptr(dq_dlogk), _ptr(dq_dphi),
+                                   _ptr(dq_dq), _ptr(status), _ptr(iters), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                   _stream_of(stream))
+    _chk(rc, "henry_adjoint_batch")
+
+
+def _aligned_workspace(nbytes, dev):
+    import torch
+    raw = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=dev)
+    off = (-raw.data_ptr()) % 256 // 8
+    return raw[off:off + (nbytes + 7) // 8]
+
+
+def adjoint(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, opts: Opts | None = None,
+            ckpt_every=20, adj_tol=1e-10, adj_max_it=60, stream=None):
+    """Allocate outputs and run the adjoint; returns dict of device tensors
+    (qoi, dq_dxi for closed-form fields, dq_dlogk, dq_dphi, dq_dq, status)."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    opts = opts or opts_default()
+    cells = sum(int(s[0]) * int(s[1]) for s in solves)
+    ns = len(solves)
+    ws = _aligned_workspace(henry_adjoint_workspace_bytes(solves, opts, ckpt_every), dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = dict(qoi=torch.empty(ns, **f64), dq_dlogk=torch.empty(cells, **f64), dq_dphi=torch.empty(cells, **f64),
+               dq_dq=torch.empty(ns, **f64), status=torch.empty(ns, dtype=torch.int32, device=dev),
+               iters=torch.empty(ns, dtype=torch.int32, device=dev))
+    closed = xi is not None
+    out["dq_dxi"] = torch.empty((ns, 3), **f64) if closed else None
+    henry_adjoint_batch(ctx, solves, FIELD_CLOSED3 if closed else FIELD_EXPLICIT, xi=xi, phi=phi, logk=logk,
+                        qin=qin, opts=opts, ckpt_every=ckpt_every, adj_tol=adj_tol, adj_max_it=adj_max_it,
+                        qoi_out=out["qoi"], dq_dxi=out["dq_dxi"], dq_dlogk=out["dq_dlogk"], dq_dphi=out["dq_dphi"],
+                        dq_dq=out["dq_dq"], status=out["status"], iters=out["iters"], workspace=ws, stream=stream)
+    return out
+
+
+def _autograd_classes():
+    import torch
+
+    class HenryQoI(torch.autograd.Function):
+        """Q(xi) for a batch of solves with the closed-form random fields;
+        backward runs the discrete adjoint.  Usage:
+        HenryQoI.apply(xi, ctx, solves, opts, ckpt_every, adj_tol)."""
+
+        @staticmethod
+        def forward(fctx, xi, ctx, solves, opts=None, ckpt_every=20, adj_tol=1e-10):
+            xi = xi.detach().contiguous()
+            out = solve(ctx, solves, xi=xi, opts=opts)
+            fctx.save_for_backward(xi)
+            fctx.henry = (ctx, solves, opts, ckpt_every, adj_tol)
+            return out["qoi"]
+
+        @staticmethod
+        def backward(fctx, gq):
+            (xi,) = fctx.saved_tensors
+            ctx, solves, opts, ckpt_every, adj_tol = fctx.henry
+            a = adjoint(ctx, solves, xi=xi, opts=opts, ckpt_every=ckpt_every, adj_tol=adj_tol)
+            return gq[:, None] * a["dq_dxi"], None, None, None, None, None
+
+    class HenryQoILogK(torch.autograd.Function):
+        """Q(log K) for caller-provided per-cell fields (packed per solve);
+        backward gives dQ/dlog K per cell.  Usage:
+        HenryQoILogK.apply(logk, phi, qin, ctx, solves, opts, ckpt_every, adj_tol)."""
+
+        @staticmethod
+        def forward(fctx, logk, phi, qin, ctx, solves, opts=None, ckpt_every=20, adj_tol=1e-10):
+            logk = logk.detach().contiguous()
+            phi = phi.detach().contiguous()
+            qin = qin.detach().contiguous()
+            out = solve(ctx, solves, phi=phi, logk=logk, qin=qin, opts=opts)
+            fctx.save_for_backward(logk, phi, qin)
+            fctx.henry = (ctx, solves, opts, ckpt_every, adj_tol)
+            return out["qoi"]
+
+        @staticmethod
+        def backward(fctx, gq):
+            logk, phi, qin = fctx.saved_tensors
+            ctx, solves, opts, ckpt_every, adj_tol = fctx.henry
+            a = adjoint(ctx, solves, phi=phi, logk=logk, qin=qin, opts=opts, ckpt_every=ckpt_every,
+                        adj_tol=adj_tol)
+            import torch
+            scale = torch.repeat_interleave(gq, torch.tensor([int(s[0]) * int(s[1]) for s in solves],
+                                                             device=gq.device))
+            return (scale * a["dq_dlogk"], scale * a["dq_dphi"], gq * a["dq_dq"], None, None, None, None,
+                    None)
+
+    return HenryQoI, HenryQoILogK
+
+
+def __getattr__(name):
+    if name in ("HenryQoI", "HenryQoILogK"):
+        a, b = _autograd_classes()
+        globals()["HenryQoI"], globals()["HenryQoILogK"] = a, b
+        return globals()[name]
+    raise AttributeError(name)

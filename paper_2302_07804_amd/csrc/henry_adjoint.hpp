@@ -1,0 +1,419 @@
+// henry_adjoint.hpp -- discrete adjoint of the batched Henry solves.
+//
+// For the implicit steps R^n(u^n, c^{n-1}; theta) = 0, n = 1..N, and the
+// QoI Q(c^N; phi) (salt mass in x < 1), the gradient is
+//   dQ/dtheta = dQ/dtheta|explicit - sum_n (lam^n)^T dR^n/dtheta,
+// with (J^N)^T lam^N = (dQ/du^N)^T and
+//      (J^n)^T lam^n = -(dR^{n+1}/dc^n)^T lam^{n+1}   (diagonal coupling),
+// J^n = dR^n/du^n the exact step Jacobian.  theta: per-cell K (reported as
+// d/dlog K), per-cell phi, the recharge q, and through the closed-form
+// fields the three xi.
+//
+// Each transposed system is solved by FP64 defect correction with the exact
+// J^T product (hand-derived flux derivatives below).  With E = [[I,0],[-C,I]]
+// (C = diag c, the recombination S = R^c - c R^p of the forward solve),
+// lam = E^T mu turns J^T lam = b into (E J)^T mu = b, whose diagonal blocks
+// are the pressure operator (symmetric) and the non-conservative transport
+// operator; they are preconditioned by the forward V-cycles, the transport
+// one with the transposed stencil.  The salt block goes first, then the
+// pressure block on the recomputed residual.
+//
+// Time reversal by checkpointing: the forward pass stores (p, c) every
+// `ckpt` steps; each segment is recomputed from its checkpoint (bitwise the
+// same states) and then walked backwards.
+#pragma once
+
+#include "henry_device.hpp"
+
+namespace henry {
+
+struct AdjLaunch {
+    int32_t ckpt;       // checkpoint interval (steps)
+    int32_t max_it;     // transposed defect-correction iterations per step
+    double tol;         // relative tolerance of the transposed residual
+    double* dq_dxi;     // [nsolves][3] or null (closed-form fields)
+    double* dq_dlogk;   // packed per cell or null
+    double* dq_dphi;    // packed per cell or null
+    double* dq_dq;      // [nsolves] or null
+};
+
+__host__ __device__ inline int num_ckpts(int nsteps, int k) { return (nsteps + k - 1) / k; }
+
+// FP64 adjoint region: mu_p, mu_c, lam_p, lam_c, r_p, r_c, b_p, b_c, gK,
+// gphi (n each), 8 doubles of scratch, checkpoints (ncp x 2n), segment
+// states ((k+1) x 2n).
+__host__ __device__ inline int64_t adjoint_bytes(int nx, int ny, int nsteps, int k) {
+    const int64_t n = (int64_t)nx * ny;
+    const int64_t ncp = num_ckpts(nsteps, k);
+    return align256(8 * (10 * n + 8 + (ncp + k + 1) * 2 * n));
+}
+
+struct Adj {
+    double *mu_p, *mu_c, *lam_p, *lam_c, *r_p, *r_c, *b_p, *b_c, *gK, *gphi, *scr, *ckpt, *seg;
+    int k, ncp;
+};
+
+__device__ inline void bind_adj(Adj& A, uint8_t* base, int n, int nsteps, int k) {
+    double* f = reinterpret_cast<double*>(base);
+    A.mu_p = f; A.mu_c = f + n; A.lam_p = f + 2 * n; A.lam_c = f + 3 * n; A.r_p = f + 4 * n; A.r_c = f + 5 * n;
+    A.b_p = f + 6 * n; A.b_c = f + 7 * n; A.gK = f + 8 * n; A.gphi = f + 9 * n; A.scr = f + 10 * n;
+    A.k = k;
+    A.ncp = num_ckpts(nsteps, k);
+    A.ckpt = f + 10 * n + 8;
+    A.seg = A.ckpt + (int64_t)A.ncp * 2 * n;
+}
+
+// ------------------------------------------------------------------ flux derivatives (FP64)
+// Derivatives of the flux from cell a to its east (vertical = false) or
+// north (vertical = true) neighbour b with respect to the states and the
+// coefficients of both cells; same flux definition as flux_x / flux_y.
+struct FaceDer {
+    double M, F;
+    double Mpa, Mpb, Mca, Mcb;
+    double Fpa, Fpb, Fca, Fcb;
+    double MKa, MKb, FKa, FKb;
+    double Fphia, Fphib;
+};
+
+__device__ inline FaceDer face_der(const Phys& ph, double h, bool vertical, double pa, double pb, double ca,
+                                   double cb, double Ka, double Kb, double fa, double fb) {
+    FaceDer d;
+    const double dr = ph.rho1 - ph.rho0;
+    const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
+    const double sK = Ka + Kb, Kf = 2.0 * Ka * Kb / sK;
+    const double sf = fa + fb, ff = 2.0 * fa * fb / sf;
+    const double lam = rf * Kf / ph.mu, dlam = 0.5 * dr * Kf / ph.mu;  // d lam / d c_a = d lam / d c_b
+    const double dif = rf * ff * ph.D, ddif = 0.5 * dr * ff * ph.D;
+    double gr = pb - pa, dgr = 0.0;
+    if (vertical) {
+        gr += rf * ph.g * h;
+        dgr = 0.5 * dr * ph.g * h;
+    }
+    d.M = -lam * gr;
+    d.Mpa = lam;
+    d.Mpb = -lam;
+    d.Mca = -(dlam * gr + lam * dgr);
+    d.Mcb = d.Mca;
+    const bool upa = d.M >= 0.0;
+    const double cup = upa ? ca : cb;
+    d.F = d.M * cup - dif * (cb - ca);
+    d.Fpa = d.Mpa * cup;
+    d.Fpb = d.Mpb * cup;
+    d.Fca = d.Mca * cup + (upa ? d.M : 0.0) - ddif * (cb - ca) + dif;
+    d.Fcb = d.Mcb * cup + (upa ? 0.0 : d.M) - ddif * (cb - ca) - dif;
+    const double dKa = 2.0 * Kb * Kb / (sK * sK), dKb = 2.0 * Ka * Ka / (sK * sK);
+    d.MKa = -(rf / ph.mu) * gr * dKa;
+    d.MKb = -(rf / ph.mu) * gr * dKb;
+    d.FKa = d.MKa * cup;
+    d.FKb = d.MKb * cup;
+    const double dfa = 2.0 * fb * fb / (sf * sf), dfb = 2.0 * fa * fa / (sf * sf);
+    d.Fphia = -rf * ph.D * dfa * (cb - ca);
+    d.Fphib = -rf * ph.D * dfb * (cb - ca);
+    return d;
+}
+
+// Seawater face: derivatives with respect to the cell's own p, c, K, phi.
+struct BndDer { double Mp, Mc, Fp, Fc, MK, FK, Fphi; };
+
+__device__ inline BndDer right_der(const Phys& ph, double y, double pP, double cP, double KP, double fP) {
+    BndDer d;
+    const double dr = ph.rho1 - ph.rho0;
+    const double rB = 0.5 * (rho_of(ph, cP) + ph.rho1);
+    const double lamB = 2.0 * rB * KP / ph.mu;
+    const double gB = -ph.rho1 * ph.g * y - pP;
+    const double M = -lamB * gB;
+    d.Mp = lamB;
+    d.Mc = -(dr * KP / ph.mu) * gB;
+    d.MK = -(2.0 * rB / ph.mu) * gB;
+    const bool up = M >= 0.0;
+    const double cup = up ? cP : 1.0;
+    const double dif = 2.0 * rB * fP * ph.D, ddif = dr * fP * ph.D;
+    d.Fp = d.Mp * cup;
+    d.Fc = d.Mc * cup + (up ? M : 0.0) - ddif * (1.0 - cP) + dif;
+    d.FK = d.MK * cup;
+    d.Fphi = -2.0 * rB * ph.D * (1.0 - cP);
+    return d;
+}
+
+// Recharge face: the mass flux -rho0 q h depends on q only; the salt flux
+// 2 rho_B phi D c_P on c and phi.
+__device__ inline BndDer left_der(const Phys& ph, double cP, double fP) {
+    BndDer d;
+    const double dr = ph.rho1 - ph.rho0;
+    const double rB = 0.5 * (rho_of(ph, cP) + ph.rho0);
+    d.Mp = 0.0; d.Mc = 0.0; d.Fp = 0.0; d.MK = 0.0; d.FK = 0.0;
+    d.Fc = dr * fP * ph.D * cP + 2.0 * rB * fP * ph.D;
+    d.Fphi = 2.0 * rB * ph.D * cP;
+    return d;
+}
+
+// ------------------------------------------------------------------ J^T lam and gradients
+// mode 0: r = b - J^T lam (lam from mu), scaled max norm returned; the
+//         inner rhs of the requested block is written to level 0.
+// mode 1: gradient accumulation g -= lam^T dR/dtheta and the rhs of the
+//         previous step.
+template <typename T>
+__device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int mode, int block) {
+    const int nx = S.nx, ny = S.ny, n = S.n;
+    const double h = S.h, h2t = h * h / S.tau;
+    const double dr = ph.rho1 - ph.rho0;
+    const double* p = S.p;
+    const double* c = S.c;
+    const double* K = S.K;
+    const double* f = S.phi;
+    const double* lp = A.lam_p;
+    const double* lc = A.lam_c;
+    Level<T>& L0 = S.lv[0];
+    double rmax = 0.0, gq = 0.0;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const int i = idx % nx, j = idx / nx;
+        const double cP = c[idx], cnP = S.cn[idx], fP = f[idx];
+        const double lpP = lp[idx], lcP = lc[idx];
+        double jp = 0.0, jc = 0.0;       // (J^T lam) at p_P, c_P
+        double gK = 0.0, gf = 0.0;       // lam^T dR/dK_P, lam^T dR/dphi_P
+        // stored mass
+        jc += lpP * h2t * fP * dr + lcP * h2t * fP * (ph.rho0 + 2.0 * dr * cP);
+        gf += lpP * h2t * (rho_of(ph, cP) - rho_of(ph, cnP)) +
+              lcP * h2t * (rho_of(ph, cP) * cP - rho_of(ph, cnP) * cnP);
+        // east: P = a
+        if (i + 1 < nx) {
+            const int q = idx + 1;
+            const FaceDer d = face_der(ph, h, false, p[idx], p[q], cP, c[q], K[idx], K[q], fP, f[q]);
+            const double wp = lpP - lp[q], wc = lcP - lc[q];
+            jp += wp * d.Mpa + wc * d.Fpa;
+            jc += wp * d.Mca + wc * d.Fca;
+            gK += wp * d.MKa + wc * d.FKa;
+            gf += wc * d.Fphia;
+        } else {
+            const double y = -1.0 + (j + 0.5) * h;
+            const BndDer d = right_der(ph, y, p[idx], cP, K[idx], fP);
+            jp += lpP * d.Mp + lcP * d.Fp;
+            jc += lpP * d.Mc + lcP * d.Fc;
+            gK += lpP * d.MK + lcP * d.FK;
+            gf += lcP * d.Fphi;
+        }
+        // west: P = b
+        if (i > 0) {
+            const int q = idx - 1;
+            const FaceDer d = face_der(ph, h, false, p[q], p[idx], c[q], cP, K[q], K[idx], f[q], fP);
+            const double wp = lp[q] - lpP, wc = lc[q] - lcP;
+            jp += wp * d.Mpb + wc * d.Fpb;
+            jc += wp * d.Mcb + wc * d.Fcb;
+            gK += wp * d.MKb + wc * d.FKb;
+            gf += wc * d.Fphib;
+        } else {
+            const BndDer d = left_der(ph, cP, fP);
+            jc += lcP * d.Fc;
+            gf += lcP * d.Fphi;
+            gq += lpP * (-ph.rho0 * h);
+        }
+        // north: P = a
+        if (j + 1 < ny) {
+            const int q = idx + nx;
+            const FaceDer d = face_der(ph, h, true, p[idx], p[q], cP, c[q], K[idx], K[q], fP, f[q]);
+            const double wp = lpP - lp[q], wc = lcP - lc[q];
+            jp += wp * d.Mpa + wc * d.Fpa;
+            jc += wp * d.Mca + wc * d.Fca;
+            gK += wp * d.MKa + wc * d.FKa;
+            gf += wc * d.Fphia;
+        }
+        // south: P = b
+        if (j > 0) {
+            const int q = idx - nx;
+            const FaceDer d = face_der(ph, h, true, p[q], p[idx], c[q], cP, K[q], K[idx], f[q], fP);
+            const double wp = lp[q] - lpP, wc = lc[q] - lcP;
+            jp += wp * d.Mpb + wc * d.Fpb;
+            jc += wp * d.Mcb + wc * d.Fcb;
+            gK += wp * d.MKb + wc * d.FKb;
+            gf += wc * d.Fphib;
+        }
+        if (mode == 0) {
+            const double rp = A.b_p[idx] - jp, rc = A.b_c[idx] - jc;
+            A.r_p[idx] = rp;
+            A.r_c[idx] = rc;
+            // norm in units of the local diagonal of each block
+            const Stencil<T> sp = pstencil(L0, i, j);
+            const Stencil<T> sc = cstencil_t(L0, i, j);
+            rmax = nanmax(rmax, fabs(rp) / (double)sp.d);
+            rmax = nanmax(rmax, fabs(rc) / (double)sc.d);
+            L0.b[idx] = (T)(block == 0 ? rp : rc);
+            L0.x[idx] = (T)0;
+        } else {
+            A.gK[idx] -= gK;
+            A.gphi[idx] -= gf;
+            // rhs of the previous step: -(dR^n/dc^{n-1})^T lam^n
+            A.b_p[idx] = 0.0;
+            A.b_c[idx] = lpP * h2t * fP * dr + lcP * h2t * fP * (ph.rho0 + 2.0 * dr * cnP);
+        }
+    }
+    if (mode == 0) return block_max(rmax, red);
+    const double g = block_sum(gq, red);
+    if (threadIdx.x == 0) A.scr[0] -= g;
+    __syncthreads();
+    return 0.0;
+}
+
+// lam = E^T mu: lam_p = mu_p - c mu_c, lam_c = mu_c.
+template <typename T>
+__device__ void lam_from_mu(Solve<T>& S, Adj& A) {
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+        A.lam_p[idx] = A.mu_p[idx] - S.c[idx] * A.mu_c[idx];
+        A.lam_c[idx] = A.mu_c[idx];
+    }
+    __syncthreads();
+}
+
+// One transposed step solve at the state in S (p^n, c^n; c^{n-1} in S.cn)
+// for the rhs in A.b; mu holds the previous step's solution as the initial
+// guess.  Returns 0 converged, 1 not converged, 2 non-finite.
+template <typename T>
+__device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, int max_it, double tol,
+                            double& iters) {
+    double np, nc;
+    residual_pass(ph, S, 0, red, np, nc);
+    coarsen_pressure(S);
+    residual_pass(ph, S, 1, red, np, nc);
+    coarsen_transport(S);
+    // scaled norm of the rhs
+    double bm = 0.0;
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+        const int i = idx % S.nx, j = idx / S.nx;
+        bm = nanmax(bm, fabs(A.b_p[idx]) / (double)pstencil(S.lv[0], i, j).d);
+        bm = nanmax(bm, fabs(A.b_c[idx]) / (double)cstencil_t(S.lv[0], i, j).d);
+    }
+    bm = block_max(bm, red);
+    if (!(bm == bm)) return 2;
+    int st = 1;
+    for (int it = 0; it < max_it; ++it) {
+        lam_from_mu(S, A);
+        const double rn = jt_pass(ph, S, A, red, 0, 1);
+        if (!(rn == rn)) { st = 2; break; }
+        if (rn <= tol * bm) { st = 0; break; }
+        iters += 1.0;
+        vcycle<T, true, true>(S);
+        for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) A.mu_c[idx] += (double)S.lv[0].x[idx];
+        __syncthreads();
+        lam_from_mu(S, A);
+        jt_pass(ph, S, A, red, 0, 0);
+        vcycle<T, false>(S);
+        for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) A.mu_p[idx] += (double)S.lv[0].x[idx];
+        __syncthreads();
+    }
+    lam_from_mu(S, A);
+    return st;
+}
+
+template <typename T>
+__device__ void save_state(const Solve<T>& S, double* dst) {
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+        dst[idx] = S.p[idx];
+        dst[S.n + idx] = S.c[idx];
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void load_state(Solve<T>& S, const double* src, const double* prev) {
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+        S.p[idx] = src[idx];
+        S.c[idx] = src[S.n + idx];
+        if (prev) S.cn[idx] = prev[S.n + idx];
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ the adjoint kernel
+template <typename T>
+__global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch al) {
+    __shared__ Solve<T> S;
+    __shared__ Adj A;
+    __shared__ double red[16];
+    const SolveDesc d = lp.descs[blockIdx.x];
+    const Phys& ph = lp.ph;
+    if (threadIdx.x == 0) {
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny);
+        S.nsteps = d.nsteps;
+        S.tau = ph.T / d.nsteps;
+        S.q = S.scratch[0];
+        bind_adj(A, lp.ws + d.adj_off, d.nx * d.ny, d.nsteps, al.ckpt);
+    }
+    __syncthreads();
+    const int n = S.n, N = d.nsteps, k = A.k;
+    PhaseClock pc;
+    pc.init();
+    double fiters = 0.0, aiters = 0.0;
+    int status = 0;
+    // ---- forward pass with checkpoints
+    initial_state(ph, S, nullptr);
+    __syncthreads();
+    for (int s = 0; s < N; ++s) {
+        if (s % k == 0) save_state(S, A.ckpt + (int64_t)(s / k) * 2 * n);
+        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, fiters, pc);
+        if (st == 2) { status = 2; break; }
+        if (st == 1 && status == 0) status = 1;
+    }
+    const double Q = qoi_of(ph, S, red);
+    // ---- adjoint initial conditions: dQ/du^N and the explicit dQ/dphi
+    const double h2 = S.h * S.h;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const bool left = (idx % S.nx) < S.nx / 2;
+        const double cP = S.c[idx];
+        A.b_p[idx] = 0.0;
+        A.b_c[idx] = left ? h2 * S.phi[idx] * (ph.rho0 + 2.0 * (ph.rho1 - ph.rho0) * cP) : 0.0;
+        A.mu_p[idx] = 0.0;
+        A.mu_c[idx] = 0.0;
+        A.gK[idx] = 0.0;
+        A.gphi[idx] = left ? h2 * rho_of(ph, cP) * cP : 0.0;
+    }
+    if (threadIdx.x == 0) A.scr[0] = 0.0;
+    __syncthreads();
+    // ---- reverse sweep over the checkpoint segments
+    for (int seg = A.ncp - 1; seg >= 0 && status != 2; --seg) {
+        const int s0 = seg * k, s1 = min(N, s0 + k);
+        load_state(S, A.ckpt + (int64_t)seg * 2 * n, nullptr);
+        save_state(S, A.seg);
+        for (int s = s0; s < s1; ++s) {
+            double dummy = 0.0;
+            implicit_step(ph, S, red, lp.max_outer, lp.tol, dummy, pc);
+            save_state(S, A.seg + (int64_t)(s - s0 + 1) * 2 * n);
+        }
+        for (int m = s1; m > s0; --m) {
+            load_state(S, A.seg + (int64_t)(m - s0) * 2 * n, A.seg + (int64_t)(m - 1 - s0) * 2 * n);
+            const int st = adjoint_step(ph, S, A, red, al.max_it, al.tol, aiters);
+            if (st == 2) { status = 2; break; }
+            if (st == 1 && status == 0) status = 1;
+            jt_pass(ph, S, A, red, 1, 0);
+        }
+    }
+    // ---- outputs
+    const double gq = A.scr[0];
+    const double h = S.h;
+    double g1 = 0.0, g2 = 0.0;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const double KP = S.K[idx];
+        if (al.dq_dlogk) al.dq_dlogk[d.field_off + idx] = A.gK[idx] * KP;
+        if (al.dq_dphi) al.dq_dphi[d.field_off + idx] = A.gphi[idx];
+        if (lp.field_kind == 0) {
+            const int i = idx % S.nx, j = idx / S.nx;
+            const double x = (i + 0.5) * h, y = -1.0 + (j + 0.5) * h;
+            // derivatives of the closed-form fields with respect to xi1, xi2
+            g1 += A.gphi[idx] * ph.phi0 * 0.2 * cos(M_PI * x / 2.0) * cos(M_PI * y);
+            g2 += A.gK[idx] * KP * 0.5 * sin(M_PI * x / 2.0);
+        }
+    }
+    g1 = block_sum(g1, red);
+    g2 = block_sum(g2, red);
+    if (threadIdx.x == 0) {
+        lp.qoi_out[d.index] = Q;
+        lp.status[d.index] = status;
+        if (lp.iters) lp.iters[d.index] = (int32_t)(fiters + aiters);
+        if (al.dq_dq) al.dq_dq[d.index] = gq;
+        if (al.dq_dxi && lp.field_kind == 0) {
+            al.dq_dxi[3 * d.index + 0] = g1;
+            al.dq_dxi[3 * d.index + 1] = g2;
+            al.dq_dxi[3 * d.index + 2] = gq * ph.q_in * 0.2;
+        }
+    }
+}
+
+}  // namespace henry

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "henry.h"
+#include "henry_adjoint.hpp"
 #include "henry_device.hpp"
 #include "henry_mlmc.hpp"
 
@@ -329,7 +330,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
         const henry_grid_t& g = solves[k];
         henry::SolveDesc& d = desc[k];
         d.nx = g.nx; d.ny = g.ny; d.nsteps = g.nsteps; d.nlev = henry::num_levels(g.ny);
-        d.reserved = 0; d.index = k; d.ws_off = off; d.field_off = foff;
+        d.reserved = 0; d.index = k; d.ws_off = off; d.field_off = foff; d.adj_off = 0;
         off += solve_bytes(g.nx, g.ny, prec);
         foff += (int64_t)g.nx * g.ny;
         Group& G = groups[(long)g.nx];
@@ -464,6 +465,133 @@ int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int
         if (hipEventElapsedTime(&ms, ctx->prof_ev[2 * g], ctx->prof_ev[2 * g + 1]) != hipSuccess) return HENRY_EHIP;
         ctx->prof[g].ms = ms;
         out[g] = ctx->prof[g];
+    }
+    return HENRY_OK;
+}
+
+int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
+                                  const henry_opts_t* opts, int32_t ckpt_every, size_t* bytes_out) {
+    (void)ctx;
+    if (!bytes_out || nsolves < 0 || (nsolves > 0 && !solves) || ckpt_every < 1) return HENRY_EINVAL;
+    henry_opts_t def;
+    henry_opts_default(&def);
+    const henry_opts_t* o = opts ? opts : &def;
+    if (int rc = check_opts(o)) return rc;
+    int64_t total = desc_bytes(nsolves);
+    for (int k = 0; k < nsolves; ++k) {
+        if (int rc = check_grid(solves[k])) return rc;
+        total += solve_bytes(solves[k].nx, solves[k].ny, o->prec);
+        total += henry::adjoint_bytes(solves[k].nx, solves[k].ny, solves[k].nsteps, ckpt_every);
+    }
+    *bytes_out = (size_t)total;
+    return HENRY_OK;
+}
+
+int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field, const double* xi,
+                        const double* phi, const double* logk, const double* qin, const henry_opts_t* opts,
+                        int32_t ckpt_every, double adj_tol, int32_t adj_max_it, double* qoi_out, double* dq_dxi,
+                        double* dq_dlogk, double* dq_dphi, double* dq_dq, int32_t* status, int32_t* iters,
+                        void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx || nsolves < 0) return HENRY_EINVAL;
+    if (nsolves == 0) return HENRY_OK;
+    if (!solves || ckpt_every < 1 || !(adj_tol > 0.0) || !std::isfinite(adj_tol) || adj_max_it < 1)
+        return HENRY_EINVAL;
+    henry_opts_t def;
+    henry_opts_default(&def);
+    const henry_opts_t* o = opts ? opts : &def;
+    if (int rc = check_opts(o)) return rc;
+    if (field == HENRY_FIELD_CLOSED3) {
+        if (!xi) return HENRY_EINVAL;
+    } else if (field == HENRY_FIELD_EXPLICIT) {
+        if (!phi || !logk || !qin || dq_dxi) return HENRY_EINVAL;
+    } else {
+        return HENRY_EINVAL;
+    }
+    if (!qoi_out || !status || !workspace) return HENRY_EINVAL;
+    size_t need = 0;
+    if (int rc = henry_adjoint_workspace_bytes(ctx, solves, nsolves, o, ckpt_every, &need)) return rc;
+    if (ws_bytes < need) return HENRY_ENOMEM;
+    if (((uintptr_t)workspace & 255) != 0) return HENRY_EINVAL;
+    const int prec = o->prec;
+    // plan: one descriptor per solve, grouped by grid
+    std::vector<henry::SolveDesc> desc(nsolves);
+    int64_t off = desc_bytes(nsolves), foff = 0;
+    std::map<long, Group> groups;
+    for (int k = 0; k < nsolves; ++k) {
+        const henry_grid_t& g = solves[k];
+        henry::SolveDesc& d = desc[k];
+        d.nx = g.nx; d.ny = g.ny; d.nsteps = g.nsteps; d.nlev = henry::num_levels(g.ny);
+        d.reserved = 0; d.index = k; d.field_off = foff;
+        d.ws_off = off;
+        off += solve_bytes(g.nx, g.ny, prec);
+        d.adj_off = off;
+        off += henry::adjoint_bytes(g.nx, g.ny, g.nsteps, ckpt_every);
+        foff += (int64_t)g.nx * g.ny;
+        Group& G = groups[(long)g.nx];
+        G.nx = g.nx; G.ny = g.ny;
+        G.members.push_back(k);
+        G.cost += (double)g.nx * g.ny * g.nsteps;
+    }
+    std::vector<Group> order;
+    for (auto& kv : groups) order.push_back(kv.second);
+    std::sort(order.begin(), order.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
+    std::vector<henry::SolveDesc> table;
+    std::vector<int> gstart;
+    for (auto& G : order) {
+        gstart.push_back((int)table.size());
+        for (int k : G.members) table.push_back(desc[k]);
+        G.threads = o->threads ? o->threads : default_threads(G.nx, G.ny);
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    const size_t tbytes = sizeof(henry::SolveDesc) * (size_t)nsolves;
+    if (ctx->pinned && hipEventSynchronize(ctx->staging_done) != hipSuccess) return HENRY_EHIP;
+    if (ctx->pinned_bytes < tbytes) {
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+        if (hipHostMalloc(&ctx->pinned, tbytes, hipHostMallocDefault) != hipSuccess) return HENRY_ENOMEM;
+        ctx->pinned_bytes = tbytes;
+    }
+    std::memcpy(ctx->pinned, table.data(), tbytes);
+    uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
+    henry::SolveDesc* dtable = reinterpret_cast<henry::SolveDesc*>(ws);
+    if (hipMemcpyAsync(dtable, ctx->pinned, tbytes, hipMemcpyHostToDevice, s0) != hipSuccess) return HENRY_EHIP;
+    if (hipEventRecord(ctx->staging_done, s0) != hipSuccess) return HENRY_EHIP;
+    henry::Launch lp{};
+    lp.ws = ws;
+    lp.xi = xi; lp.phi_in = phi; lp.logk_in = logk; lp.qin_in = qin; lp.c0 = nullptr;
+    lp.qoi_out = qoi_out; lp.status = status; lp.iters = iters;
+    std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
+    lp.tol = o->tol;
+    lp.max_outer = o->max_outer;
+    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : 1;
+    henry::AdjLaunch al{};
+    al.ckpt = ckpt_every;
+    al.max_it = adj_max_it;
+    al.tol = adj_tol;
+    al.dq_dxi = dq_dxi; al.dq_dlogk = dq_dlogk; al.dq_dphi = dq_dphi; al.dq_dq = dq_dq;
+    const int ng = (int)order.size();
+    const int nstreams = std::min(kStreams, ng);
+    if (hipEventRecord(ctx->fork, s0) != hipSuccess) return HENRY_EHIP;
+    for (int k = 0; k < nstreams; ++k)
+        if (hipStreamWaitEvent(ctx->streams[k], ctx->fork, 0) != hipSuccess) return HENRY_EHIP;
+    for (int gi = 0; gi < ng; ++gi) {
+        const Group& G = order[gi];
+        hipStream_t st = ctx->streams[gi % kStreams];
+        henry::Launch l = lp;
+        l.descs = dtable + gstart[gi];
+        const int nb = (int)G.members.size();
+        hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
+        if (prec == HENRY_PREC_MIXED)
+            hipLaunchKernelGGL(henry::henry_adjoint_kernel<float>, dim3(nb), dim3(G.threads), 0, st, l, al);
+        else
+            hipLaunchKernelGGL(henry::henry_adjoint_kernel<double>, dim3(nb), dim3(G.threads), 0, st, l, al);
+        if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    }
+    for (int k = 0; k < nstreams; ++k) {
+        if (hipEventRecord(ctx->joins[k], ctx->streams[k]) != hipSuccess) return HENRY_EHIP;
+        if (hipStreamWaitEvent(s0, ctx->joins[k], 0) != hipSuccess) return HENRY_EHIP;
     }
     return HENRY_OK;
 }

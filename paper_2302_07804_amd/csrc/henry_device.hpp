@@ -49,6 +49,7 @@ struct SolveDesc {
     int32_t index;       // position in the caller's solve list
     int64_t ws_off;
     int64_t field_off;
+    int64_t adj_off;     // adjoint region (adjoint calls only)
 };
 
 struct Launch {
@@ -419,10 +420,51 @@ __device__ inline Stencil<T> cstencil(const Level<T>& v, int i, int j) {
     return st;
 }
 
-template <typename T, bool kTransport>
+// Transpose of the transport operator (adjoint solves): a cell couples to
+// a neighbour with that neighbour's coupling to it; the diagonal is the same.
+template <typename T>
+__device__ inline Stencil<T> cstencil_t(const Level<T>& v, int i, int j) {
+    const int idx = j * v.nx + i;
+    Stencil<T> st;
+    T d = v.acc[idx];
+    if (i + 1 < v.nx) {
+        const T M = v.mx[idx], D = v.dx[idx];
+        d += pos(-M) + D;
+        st.e = pos(M) + D;
+    } else {
+        st.e = (T)0;
+        d += pos(-v.mr[j]) + v.dr[j];
+    }
+    if (i > 0) {
+        const T M = v.mx[idx - 1], D = v.dx[idx - 1];
+        d += pos(M) + D;
+        st.w = pos(-M) + D;
+    } else {
+        st.w = (T)0;
+        d += v.dl[j] + v.ml[j];
+    }
+    if (j + 1 < v.ny) {
+        const T M = v.my[idx], D = v.dy[idx];
+        d += pos(-M) + D;
+        st.n = pos(M) + D;
+    } else st.n = (T)0;
+    if (j > 0) {
+        const T M = v.my[idx - v.nx], D = v.dy[idx - v.nx];
+        d += pos(M) + D;
+        st.s = pos(-M) + D;
+    } else st.s = (T)0;
+    st.d = d;
+    return st;
+}
+
+template <typename T, bool kTransport, bool kTrans = false>
 __device__ inline Stencil<T> stencil(const Level<T>& v, int i, int j) {
-    if constexpr (kTransport) return cstencil(v, i, j);
-    else return pstencil(v, i, j);
+    if constexpr (kTransport) {
+        if constexpr (kTrans) return cstencil_t(v, i, j);
+        else return cstencil(v, i, j);
+    } else {
+        return pstencil(v, i, j);
+    }
 }
 
 // ------------------------------------------------------------------ grid transfer
@@ -477,7 +519,7 @@ __device__ void restrict_residual(const Level<T>& F, Level<T>& C) {
 }
 
 // r = b - A x on one level (operands of kBatch cells gathered first).
-template <typename T, bool kTransport>
+template <typename T, bool kTransport, bool kTrans = false>
 __device__ void level_residual(Level<T>& v) {
     const int n = v.nx * v.ny;
     for (int k0 = threadIdx.x; k0 < n; k0 += 4 * blockDim.x) {
@@ -487,7 +529,7 @@ __device__ void level_residual(Level<T>& v) {
             const int k = k0 + u * blockDim.x;
             const int idx = k < n ? k : 0;
             const int i = idx % v.nx, j = idx / v.nx;
-            const Stencil<T> st = stencil<T, kTransport>(v, i, j);
+            const Stencil<T> st = stencil<T, kTransport, kTrans>(v, i, j);
             T ax = st.d * v.x[idx];
             if (i > 0) ax -= st.w * v.x[idx - 1];
             if (i + 1 < v.nx) ax -= st.e * v.x[idx + 1];
@@ -562,7 +604,7 @@ __device__ void rbgs(Level<T>& v, int sweeps) {
 template <typename T>
 struct SegRows { static constexpr int value = sizeof(T) == 4 ? 8 : 4; };
 
-template <typename T, bool kXLine>
+template <typename T, bool kXLine, bool kTrans = false>
 __device__ void line_sweep(Level<T>& v, int col) {
     constexpr int MS = SegRows<T>::value;
     const int len = kXLine ? v.nx : v.ny;
@@ -587,7 +629,7 @@ __device__ void line_sweep(Level<T>& v, int col) {
                 const int k = t * m + q;
                 const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
                 const int idx = j * v.nx + i;
-                const Stencil<T> st = cstencil(v, i, j);
+                const Stencil<T> st = stencil<T, true, kTrans>(v, i, j);
                 T rhs = v.b[idx];
                 T a, c;
                 if (kXLine) {
@@ -681,14 +723,14 @@ __device__ void line_sweep(Level<T>& v, int col) {
 }
 
 // One zebra sweep: x-lines (even rows, odd rows), then y-lines.
-template <typename T>
+template <typename T, bool kTrans = false>
 __device__ void line_smooth(Level<T>& v, int sweeps) {
     for (int s = 0; s < sweeps; ++s) {
-        line_sweep<T, true>(v, 0);
-        line_sweep<T, true>(v, 1);
+        line_sweep<T, true, kTrans>(v, 0);
+        line_sweep<T, true, kTrans>(v, 1);
         if (v.ny > 1) {
-            line_sweep<T, false>(v, 0);
-            line_sweep<T, false>(v, 1);
+            line_sweep<T, false, kTrans>(v, 0);
+            line_sweep<T, false, kTrans>(v, 1);
         }
     }
 }
@@ -696,21 +738,21 @@ __device__ void line_smooth(Level<T>& v, int sweeps) {
 // ------------------------------------------------------------------ V-cycles
 // The coarsest level of every hierarchy has one row (ny = 1, nx = 2): the
 // system is a single x-line, solved exactly.
-template <typename T, bool kTransport>
+template <typename T, bool kTransport, bool kTrans = false>
 __device__ void vcycle(Solve<T>& S) {
     const int L = S.L;
     for (int l = 0; l < L - 1; ++l) {
         Level<T>& v = S.lv[l];
-        if constexpr (kTransport) line_smooth(v, 1);
+        if constexpr (kTransport) line_smooth<T, kTrans>(v, 1);
         else rbgs(v, 2);
-        level_residual<T, kTransport>(v);
+        level_residual<T, kTransport, kTrans>(v);
         __syncthreads();
         restrict_residual(v, S.lv[l + 1]);
         __syncthreads();
     }
     {
         Level<T>& v = S.lv[L - 1];
-        if constexpr (kTransport) line_sweep<T, true>(v, 0);
+        if constexpr (kTransport) line_sweep<T, true, kTrans>(v, 0);
         else {
             // pressure coarsest (2 x 1 cells): direct solve of the 2 x 2 system
             if (threadIdx.x == 0) {
@@ -726,9 +768,89 @@ __device__ void vcycle(Solve<T>& S) {
         Level<T>& v = S.lv[l];
         prolong_add(S.lv[l + 1], v);
         __syncthreads();
-        if constexpr (kTransport) line_smooth(v, 1);
+        if constexpr (kTransport) line_smooth<T, kTrans>(v, 1);
         else rbgs(v, 2);
     }
+}
+
+// ------------------------------------------------------------------ one implicit step
+// Wall-clock accumulators of the phases of one step (builds with
+// HENRY_PHASE_TIMERS only; wall_clock64 runs at a constant 100 MHz).
+struct PhaseClock {
+#ifdef HENRY_PHASE_TIMERS
+    uint64_t acc[8];
+    uint64_t last;
+    __device__ void init() {
+        for (int k = 0; k < 8; ++k) acc[k] = 0;
+        last = wall_clock64();
+    }
+    __device__ void tick(int k) {
+        const uint64_t t = wall_clock64();
+        acc[k] += t - last;
+        last = t;
+    }
+#else
+    __device__ void init() {}
+    __device__ void tick(int) {}
+#endif
+};
+
+// One implicit Euler step (Sec. 2.3) from the state in S.p, S.c: saves c^n
+// in S.cn and runs the defect correction until both scaled residual max
+// norms are <= tol.  Returns HENRY status: 0 converged, 1 max_outer reached,
+// 2 non-finite residual.  Adds the iterations used to `iters`.
+template <typename T>
+__device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_outer, double tol, double& iters,
+                             PhaseClock& pc) {
+    const int n = S.n;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.cn[idx] = S.c[idx];
+    __syncthreads();
+    pc.tick(7);
+    for (int it = 0; it < max_outer; ++it) {
+        double np, nc;
+        residual_pass(ph, S, 0, red, np, nc);
+        pc.tick(0);
+        if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) return 2;
+        if (np <= tol && nc <= tol) return 0;
+        iters += 1.0;
+        coarsen_pressure(S);
+        pc.tick(1);
+        vcycle<T, false>(S);
+        pc.tick(2);
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.p[idx] += (double)S.lv[0].x[idx];
+        __syncthreads();
+        residual_pass(ph, S, 1, red, np, nc);
+        pc.tick(3);
+        coarsen_transport(S);
+        pc.tick(4);
+        vcycle<T, true>(S);
+        pc.tick(5);
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.c[idx] += (double)S.lv[0].x[idx];
+        __syncthreads();
+        pc.tick(6);
+    }
+    return 1;
+}
+
+// Initial state: c = c0 (or 0, Sec. 2.1); p only seeds the iteration: the
+// cell's own hydrostatic value -rho(c) g y.
+template <typename T>
+__device__ void initial_state(const Phys& ph, Solve<T>& S, const double* c0) {
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+        const int j = idx / S.nx;
+        const double c = c0 ? c0[idx] : 0.0;
+        S.c[idx] = c;
+        S.p[idx] = -rho_of(ph, c) * ph.g * (-1.0 + (j + 0.5) * S.h);
+    }
+}
+
+// Q = h^2 sum_{x<1} phi rho(c) c (FP64, fixed-order block reduction).
+template <typename T>
+__device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
+    double part = 0.0;
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x)
+        if ((idx % S.nx) < S.nx / 2) part += S.phi[idx] * rho_of(ph, S.c[idx]) * S.c[idx];
+    return block_sum(part, red) * S.h * S.h;
 }
 
 // ------------------------------------------------------------------ the solve kernel
@@ -752,77 +874,36 @@ __global__ void __launch_bounds__(512) henry_solve_kernel(Launch lp) {
     if (s_begin >= s_end) return;
     double* sp = S.scratch;  // [0] = q, [1] = status, [2] = iterations
     if (s_begin == 0) {
-        // initial state: c = c0 (or 0, Sec. 2.1); p only seeds the
-        // iteration: the cell's own hydrostatic value -rho(c) g y
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-            const int j = idx / S.nx;
-            const double c0 = lp.c0 ? lp.c0[d.field_off + idx] : 0.0;
-            S.c[idx] = c0;
-            S.p[idx] = -rho_of(ph, c0) * ph.g * (-1.0 + (j + 0.5) * S.h);
-        }
+        initial_state(ph, S, lp.c0 ? lp.c0 + d.field_off : nullptr);
         if (threadIdx.x == 0) { sp[1] = 0.0; sp[2] = 0.0; }
     }
     if (threadIdx.x == 0) S.q = sp[0];
     __syncthreads();
     int status = (int)sp[1];
     double iters = sp[2];
-#ifdef HENRY_PHASE_TIMERS
-    uint64_t tacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    uint64_t tlast = wall_clock64();
-#define HENRY_PT(k) do { const uint64_t t_ = wall_clock64(); tacc[k] += t_ - tlast; tlast = t_; } while (0)
-#else
-#define HENRY_PT(k) do { } while (0)
-#endif
+    PhaseClock pc;
+    pc.init();
     for (int s = s_begin; s < s_end && status != 2; ++s) {
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.cn[idx] = S.c[idx];
-        __syncthreads();
-        bool conv = false;
-        HENRY_PT(7);
-        for (int it = 0; it < lp.max_outer; ++it) {
-            double np, nc;
-            residual_pass(ph, S, 0, red, np, nc);
-            HENRY_PT(0);
-            if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) { status = 2; break; }
-            if (np <= lp.tol && nc <= lp.tol) { conv = true; break; }
-            iters += 1.0;
-            coarsen_pressure(S);
-            HENRY_PT(1);
-            vcycle<T, false>(S);
-            HENRY_PT(2);
-            for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.p[idx] += (double)S.lv[0].x[idx];
-            __syncthreads();
-            residual_pass(ph, S, 1, red, np, nc);
-            HENRY_PT(3);
-            coarsen_transport(S);
-            HENRY_PT(4);
-            vcycle<T, true>(S);
-            HENRY_PT(5);
-            for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.c[idx] += (double)S.lv[0].x[idx];
-            __syncthreads();
-            HENRY_PT(6);
-        }
-        if (!conv && status == 0) status = 1;
+        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, iters, pc);
+        if (st == 2) status = 2;
+        else if (st == 1 && status == 0) status = 1;
     }
-#undef HENRY_PT
     if (threadIdx.x == 0) {
         sp[1] = (double)status;
         sp[2] = iters;
 #ifdef HENRY_PHASE_TIMERS
-        for (int k = 0; k < 8; ++k) sp[8 + k] = (double)tacc[k];
+        for (int k = 0; k < 8; ++k) sp[8 + k] = (double)pc.acc[k];
 #endif
     }
     if (s_end == d.nsteps) {
-        // outputs: c, p at T and the QoI Q = h^2 sum_{x<1} phi rho(c) c (FP64)
-        double part = 0.0;
+        // outputs: c, p at T and the QoI
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-            const double cP = S.c[idx];
-            lp.c_out[d.field_off + idx] = cP;
+            lp.c_out[d.field_off + idx] = S.c[idx];
             if (lp.p_out) lp.p_out[d.field_off + idx] = S.p[idx];
-            if ((idx % S.nx) < S.nx / 2) part += S.phi[idx] * rho_of(ph, cP) * cP;
         }
-        const double Q = block_sum(part, red);
+        const double Q = qoi_of(ph, S, red);
         if (threadIdx.x == 0) {
-            lp.qoi_out[d.index] = Q * S.h * S.h;
+            lp.qoi_out[d.index] = Q;
             lp.status[d.index] = status;
             if (lp.iters) lp.iters[d.index] = (int32_t)iters;
         }
