@@ -246,6 +246,23 @@ def main():
                 worst_p = max(worst_p, np.abs(c - r["c"]).max() / np.abs(r["c"]).max())
             errs["plain_fp64_max_rel_c_err"] = worst_p
         log(f"oracle: {cpu['value']:.3e} cell-steps/s on {threads} threads; errors {errs}")
+    # the finest level is beyond the oracle's reach (banded LU, hours per
+    # solve): check two of its solves against tightly converged FP64 GPU solves
+    fine_idx = [k for k, s in enumerate(solves) if s.nx == 256][:2]
+    if fine_idx and not args.no_cpu:
+        tight = hm.make_opts(prec=hm.PREC_FP64, tol=1e-11, max_outer=100)
+        ref = hm.solve(ctx, [grids[k] for k in fine_idx], xi=xi[fine_idx[0]:fine_idx[-1] + 1].contiguous(),
+                       opts=tight)
+        torch.cuda.synchronize()
+        c_all = c_out.cpu().numpy()
+        rc = ref["c"].cpu().numpy()
+        worst = 0.0
+        for j, k in enumerate(fine_idx):
+            a = c_all[offs[k]:offs[k + 1]]
+            b = rc[j * solves[k].cells:(j + 1) * solves[k].cells]
+            worst = max(worst, np.abs(a - b).max() / np.abs(b).max())
+        errs["batched_mixed_max_rel_c_err_256x128_vs_fp64_tol1e-11"] = worst
+        log(f"256x128 vs tight FP64: {worst:.3e}")
 
     res = {
         "metric": "Henry sample solves/s (cell-steps/s) batched vs plain, same 1e-5 E[c] error",

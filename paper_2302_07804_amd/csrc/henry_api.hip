@@ -78,7 +78,7 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 int check_grid(const henry_grid_t& g) {
     if (g.reserved != 0) return HENRY_EINVAL;
-    if (g.ny < 1 || g.ny > 512 || !pow2(g.ny) || g.nx != 2 * g.ny) return HENRY_EINVAL;
+    if (g.ny < 1 || g.ny > 128 || !pow2(g.ny) || g.nx != 2 * g.ny) return HENRY_EINVAL;
     if (g.nsteps < 1) return HENRY_EINVAL;
     return HENRY_OK;
 }

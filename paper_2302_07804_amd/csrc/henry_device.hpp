@@ -34,7 +34,7 @@
 
 namespace henry {
 
-constexpr int kMaxLevels = 12;  // ny <= 512 -> at most 10 multigrid levels
+constexpr int kMaxLevels = 12;  // ny <= 128 -> at most 8 multigrid levels
 constexpr int kWave = 64;
 
 struct Phys {
@@ -94,10 +94,10 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
     return align256((int64_t)(kLevelArrays * nx * ny + kRowArrays * ny) * (int64_t)sizeof(T));
 }
 
-// FP64 arrays: p, c, cn, phi, K, Rp, Rc, then kScratch doubles of scratch
-// ([0] recharge, [1] status, [2] outer iterations, [8..] phase timers of
-// builds with HENRY_PHASE_TIMERS).
-constexpr int kF64Arrays = 7;
+// FP64 arrays: p, c, cn, phi, K, Rp, Rc, pp (previous p), then kScratch
+// doubles of scratch ([0] recharge, [1] status, [2] outer iterations,
+// [8..] phase timers of builds with HENRY_PHASE_TIMERS).
+constexpr int kF64Arrays = 8;
 constexpr int kScratch = 32;
 
 template <typename T>
@@ -123,7 +123,7 @@ struct Solve {
     int nx, ny, n, nsteps, L;
     double h, tau;
     double q;  // recharge (m/s)
-    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *scratch;
+    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *scratch;
     Level<T> lv[kMaxLevels];
 };
 
@@ -134,7 +134,7 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny) {
     double* f = reinterpret_cast<double*>(base);
     const int n = nx * ny;
     S.p = f; S.c = f + n; S.cn = f + 2 * n; S.phi = f + 3 * n; S.K = f + 4 * n; S.Rp = f + 5 * n;
-    S.Rc = f + 6 * n; S.scratch = f + 7 * n;
+    S.Rc = f + 6 * n; S.pp = f + 7 * n; S.scratch = f + 8 * n;
     uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
     int lx = nx, ly = ny;
     for (int l = 0; l < S.L; ++l) {
@@ -601,17 +601,15 @@ __device__ void rbgs(Level<T>& v, int sweeps) {
 // reduction across the T lanes with wavefront shuffles, then every lane
 // back-substitutes its interior rows.  All coefficients live in registers;
 // a colour of lines is one block-wide phase.
-template <typename T>
-struct SegRows { static constexpr int value = sizeof(T) == 4 ? 8 : 4; };
-
-template <typename T, bool kXLine, bool kTrans = false>
-__device__ void line_sweep(Level<T>& v, int col) {
-    constexpr int MS = SegRows<T>::value;
+// MS = rows per lane (a power of two); line lengths are powers of two, so
+// m = MS = max(2, len/64) rows and TL = len/m <= 64 lanes per line.
+template <typename T, bool kXLine, bool kTrans, int MS>
+__device__ void line_sweep_m(Level<T>& v, int col) {
     const int len = kXLine ? v.nx : v.ny;
     const int other = kXLine ? v.ny : v.nx;
     const int nlines = (other - col + 1) >> 1;
-    const int m = len < MS ? len : MS;  // rows per lane
-    const int TL = len / m;             // lanes per line (<= 64 since len <= 1024)
+    const int m = MS;                   // rows per lane
+    const int TL = len / m;             // lanes per line
     const int lane = threadIdx.x & (kWave - 1);
     const int t = lane & (TL - 1);
     const int need = nlines * TL;
@@ -722,6 +720,13 @@ __device__ void line_sweep(Level<T>& v, int col) {
     __syncthreads();
 }
 
+template <typename T, bool kXLine, bool kTrans = false>
+__device__ void line_sweep(Level<T>& v, int col) {
+    const int len = kXLine ? v.nx : v.ny;  // 2 .. 256, a power of two
+    if (len <= 128) line_sweep_m<T, kXLine, kTrans, 2>(v, col);
+    else line_sweep_m<T, kXLine, kTrans, 4>(v, col);
+}
+
 // One zebra sweep: x-lines (even rows, odd rows), then y-lines.
 template <typename T, bool kTrans = false>
 __device__ void line_smooth(Level<T>& v, int sweeps) {
@@ -796,14 +801,25 @@ struct PhaseClock {
 };
 
 // One implicit Euler step (Sec. 2.3) from the state in S.p, S.c: saves c^n
-// in S.cn and runs the defect correction until both scaled residual max
-// norms are <= tol.  Returns HENRY status: 0 converged, 1 max_outer reached,
-// 2 non-finite residual.  Adds the iterations used to `iters`.
+// in S.cn (and p^n in S.pp) and runs the defect correction until both
+// scaled residual max norms are <= tol.  With `extrap` the iteration
+// starts from the linear extrapolation 2 u^n - u^{n-1} of the two previous
+// states (S.cn, S.pp hold u^{n-1} on entry).  Returns 0 converged,
+// 1 max_outer reached, 2 non-finite residual; adds the iterations used to
+// `iters`.
 template <typename T>
 __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_outer, double tol, double& iters,
-                             PhaseClock& pc) {
+                             PhaseClock& pc, bool extrap = false) {
     const int n = S.n;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.cn[idx] = S.c[idx];
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const double c1 = S.c[idx], p1 = S.p[idx];
+        if (extrap) {
+            S.c[idx] = 2.0 * c1 - S.cn[idx];
+            S.p[idx] = 2.0 * p1 - S.pp[idx];
+        }
+        S.cn[idx] = c1;
+        S.pp[idx] = p1;
+    }
     __syncthreads();
     pc.tick(7);
     for (int it = 0; it < max_outer; ++it) {
@@ -884,7 +900,7 @@ __global__ void __launch_bounds__(512) henry_solve_kernel(Launch lp) {
     PhaseClock pc;
     pc.init();
     for (int s = s_begin; s < s_end && status != 2; ++s) {
-        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, iters, pc);
+        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, iters, pc, s > 0);
         if (st == 2) status = 2;
         else if (st == 1 && status == 0) status = 1;
     }
@@ -921,7 +937,7 @@ __global__ void henry_fields_kernel(Launch lp) {
     const int nx = d.nx, ny = d.ny, n = nx * ny;
     double* phi = f + 3 * n;
     double* K = f + 4 * n;
-    double* sp = f + 7 * n;
+    double* sp = f + kF64Arrays * n;
     const double h = 1.0 / ny;
     if (lp.field_kind == 0) {
         const double x1 = lp.xi[3 * d.index], x2 = lp.xi[3 * d.index + 1], x3 = lp.xi[3 * d.index + 2];
