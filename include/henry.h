@@ -155,6 +155,16 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
                       double* qoi_out, int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes,
                       void* stream);
 
+/* Tuning cache of a context: threads per solve-workgroup for grids of
+ * width nx at precision prec, used by henry_solve_batch and
+ * henry_adjoint_batch when opts->threads == 0.  threads = 0 clears the
+ * entry (back to the built-in default: 64 threads up to 128 cells, 128 up
+ * to 512, 256 up to 2048, 512 above).  The measuring driver that fills it
+ * times candidate sizes on short runs of the caller's own batch (Python
+ * binding: paper_2302_07804_amd.autotune). */
+int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads);
+int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads);
+
 /* Per-group timings of the last profiled henry_solve_batch call: writes up
  * to `cap` entries, returns the group count through *ngroups.  Synchronises
  * with the recorded events (blocks the host until that work is done). */

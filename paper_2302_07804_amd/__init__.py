@@ -25,8 +25,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 # every symbol the header declares
 EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opts_default", "henry_sample_xi",
-           "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_adjoint_workspace_bytes",
-           "henry_adjoint_batch", "mlmc_level_estimate")
+           "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_tune_set", "henry_tune_get",
+           "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -102,6 +102,8 @@ def lib():
     L.henry_solve_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), vp, vp,
                                     vp, vp, vp, vp, ct.c_size_t, vp]
     L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
+    L.henry_tune_set.argtypes = [vp, i32, i32, i32]
+    L.henry_tune_get.argtypes = [vp, i32, i32, ct.POINTER(i32)]
     L.henry_adjoint_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), i32,
                                                 ct.POINTER(ct.c_size_t)]
     L.henry_adjoint_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, ct.POINTER(Opts), i32, dbl, i32,
@@ -375,3 +377,66 @@ def __getattr__(name):
         globals()["HenryQoI"], globals()["HenryQoILogK"] = a, b
         return globals()[name]
     raise AttributeError(name)
+
+
+# ------------------------------------------------------------------ autotuning
+def henry_tune_set(ctx: Context, nx: int, prec: int, threads: int):
+    _chk(lib().henry_tune_set(ctx.handle, nx, prec, threads), "henry_tune_set")
+
+
+def henry_tune_get(ctx: Context, nx: int, prec: int) -> int:
+    t = ct.c_int32()
+    _chk(lib().henry_tune_get(ctx.handle, nx, prec, ct.byref(t)), "henry_tune_get")
+    return t.value
+
+
+def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int = 8, max_solves: int = 1024,
+             candidates=(64, 128, 256, 512), cache_path: str | None = None):
+    """Choose the threads per solve-workgroup for every grid of `solves` by
+    timing short runs (the first `tune_steps` steps of up to `max_solves`
+    solves of that grid, each candidate twice, HIP-event group time on the
+    stream the kernels run on) and store the fastest in the context's
+    tuning cache; optionally persist the choices as JSON.  Returns
+    {(nx, prec): (threads, {candidate: ms})}."""
+    import json
+    import torch
+    opts = opts or opts_default()
+    prec = opts.prec
+    by_grid = {}
+    for k, s in enumerate(solves):
+        by_grid.setdefault(int(s[0]), []).append(k)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    result = {}
+    for nx, ks in sorted(by_grid.items()):
+        key = f"{nx}:{prec}"
+        if key in cache:
+            henry_tune_set(ctx, nx, prec, int(cache[key]))
+            result[(nx, prec)] = (int(cache[key]), {})
+            continue
+        ks = ks[:max_solves]
+        sub = [(int(solves[k][0]), int(solves[k][1]), min(int(solves[k][2]), tune_steps)) for k in ks]
+        xs = xi[ks].contiguous()
+        cells = nx * (nx // 2)
+        times = {}
+        for t in candidates:
+            if t > 64 and t > 2 * cells:
+                continue
+            o = make_opts(prec=prec, tol=opts.tol, max_outer=opts.max_outer, threads=t, profile=1)
+            best = None
+            for _ in range(2):
+                solve(ctx, sub, xi=xs, opts=o)
+                torch.cuda.synchronize()
+                ms = sum(g["ms"] for g in henry_profile_last(ctx))
+                best = ms if best is None else min(best, ms)
+            times[t] = best
+        choice = min(times, key=times.get)
+        henry_tune_set(ctx, nx, prec, choice)
+        cache[key] = choice
+        result[(nx, prec)] = (choice, times)
+    if cache_path:
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return result

@@ -454,6 +454,26 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     return HENRY_OK;
 }
 
+int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
+    if (!ctx || nx < 2 || nx > 256 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
+    if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
+    if (threads == 0) {
+        ctx->tuned_threads.erase((long)nx * 4 + prec);
+        return HENRY_OK;
+    }
+    if (threads < 64 || threads > 512 || !pow2(threads)) return HENRY_EINVAL;
+    ctx->tuned_threads[(long)nx * 4 + prec] = threads;
+    return HENRY_OK;
+}
+
+int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads) {
+    if (!ctx || !threads || nx < 2 || nx > 256 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
+    if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
+    auto it = ctx->tuned_threads.find((long)nx * 4 + prec);
+    *threads = it != ctx->tuned_threads.end() ? it->second : default_threads(nx, nx / 2);
+    return HENRY_OK;
+}
+
 int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int32_t* ngroups) {
     if (!ctx || !ngroups || cap < 0 || (cap > 0 && !out)) return HENRY_EINVAL;
     DeviceGuard dg(ctx->device);
@@ -540,7 +560,12 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     for (auto& G : order) {
         gstart.push_back((int)table.size());
         for (int k : G.members) table.push_back(desc[k]);
-        G.threads = o->threads ? o->threads : default_threads(G.nx, G.ny);
+        int t = o->threads;
+        if (t == 0) {
+            auto it = ctx->tuned_threads.find((long)G.nx * 4 + prec);
+            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny);
+        }
+        G.threads = t;
     }
     DeviceGuard dg(ctx->device);
     hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
