@@ -325,13 +325,14 @@ __device__ void load_state(Solve<T>& S, const double* src, const double* prev) {
 // ------------------------------------------------------------------ the adjoint kernel
 template <typename T>
 __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch al) {
+    extern __shared__ __align__(256) uint8_t lds_levels[];
     __shared__ Solve<T> S;
     __shared__ Adj A;
     __shared__ double red[16];
     const SolveDesc d = lp.descs[blockIdx.x];
     const Phys& ph = lp.ph;
     if (threadIdx.x == 0) {
-        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny);
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
         S.q = S.scratch[0];

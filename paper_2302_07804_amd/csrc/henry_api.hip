@@ -25,6 +25,9 @@
 namespace {
 
 constexpr int kStreams = 4;
+// Multigrid levels of at most this many cells (32 x 16 and coarser) are kept
+// in LDS: 28 KB per workgroup at FP32, 56 KB at FP64.
+constexpr int kLdsCells = 512;
 
 struct Group {
     int nx, ny, threads;
@@ -133,6 +136,10 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
         // lockstep time chunks: local step s of a solve with r steps runs in
         // global step s * rmax / r; one chunk when steps_per_launch == 0
+        l.lds_cells = kLdsCells;
+        const size_t lds = (size_t)(prec == HENRY_PREC_MIXED
+                                        ? henry::lds_level_bytes<float>(G.nx, G.ny, kLdsCells)
+                                        : henry::lds_level_bytes<double>(G.nx, G.ny, kLdsCells));
         const int chunk = spl > 0 ? spl : rmax;
         if (profile) {
             henry_group_time_t& pt = ctx->prof[gi];
@@ -146,9 +153,9 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
             l.g_end = std::min(rmax, g0 + chunk);
             l.g_total = rmax;
             if (prec == HENRY_PREC_MIXED)
-                hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nb), dim3(G.threads), 0, st, l);
+                hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nb), dim3(G.threads), lds, st, l);
             else
-                hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nb), dim3(G.threads), 0, st, l);
+                hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nb), dim3(G.threads), lds, st, l);
         }
         if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
         if (profile && hipEventRecord(ctx->prof_ev[2 * gi + 1], st) != hipSuccess) return HENRY_EHIP;
@@ -608,10 +615,14 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
         hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
+        l.lds_cells = kLdsCells;
+        const size_t lds = (size_t)(prec == HENRY_PREC_MIXED
+                                        ? henry::lds_level_bytes<float>(G.nx, G.ny, kLdsCells)
+                                        : henry::lds_level_bytes<double>(G.nx, G.ny, kLdsCells));
         if (prec == HENRY_PREC_MIXED)
-            hipLaunchKernelGGL(henry::henry_adjoint_kernel<float>, dim3(nb), dim3(G.threads), 0, st, l, al);
+            hipLaunchKernelGGL(henry::henry_adjoint_kernel<float>, dim3(nb), dim3(G.threads), lds, st, l, al);
         else
-            hipLaunchKernelGGL(henry::henry_adjoint_kernel<double>, dim3(nb), dim3(G.threads), 0, st, l, al);
+            hipLaunchKernelGGL(henry::henry_adjoint_kernel<double>, dim3(nb), dim3(G.threads), lds, st, l, al);
         if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
     }
     for (int k = 0; k < nstreams; ++k) {

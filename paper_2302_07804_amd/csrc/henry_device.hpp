@@ -10,7 +10,8 @@
 //     (A_pp) dp = -R^p    one V(2,2) cycle, red-black Gauss-Seidel   inner T
 //     p += dp                                                         FP64
 //     S = R^c(p, c) - c R^p(p, c)                                     FP64
-//     (A_cc) dc = -S      one V(1,1) cycle, zebra x/y line relaxation inner T
+//     (A_cc) dc = -S      one V-cycle, zebra x-lines before / y-lines after
+//                         the coarse correction                   inner T
 //     c += dc                                                         FP64
 //   until both scaled residual norms <= tol
 //
@@ -71,6 +72,7 @@ struct Launch {
     int32_t field_kind;
     int32_t g_begin, g_end;  // global step range of this launch
     int32_t g_total;         // global steps of the whole batch (max nsteps)
+    int32_t lds_cells;       // multigrid levels with at most this many cells live in LDS
 };
 
 // ------------------------------------------------------------------ layout
@@ -127,8 +129,26 @@ struct Solve {
     Level<T> lv[kMaxLevels];
 };
 
+// Dynamic LDS bytes for the levels of an nx x ny hierarchy with at most
+// `lds_cells` cells (the coarse end of the V-cycles).
 template <typename T>
-__device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny) {
+__host__ __device__ inline int64_t lds_level_bytes(int nx, int ny, int lds_cells) {
+    int64_t b = 0;
+    int lx = nx, ly = ny;
+    const int L = num_levels(ny);
+    for (int l = 0; l < L; ++l) {
+        if (lx * ly <= lds_cells) b += level_bytes<T>(lx, ly);
+        lx >>= 1; ly >>= 1;
+    }
+    return b;
+}
+
+// Binds the solve's arrays.  Levels with at most `lds_cells` cells get
+// their inner arrays in the workgroup's LDS (`lds`): they are rebuilt every
+// iteration, so nothing there has to survive a launch.
+template <typename T>
+__device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, uint8_t* lds = nullptr,
+                                  int lds_cells = 0) {
     S.nx = nx; S.ny = ny; S.n = nx * ny; S.L = num_levels(ny);
     S.h = 1.0 / ny;
     double* f = reinterpret_cast<double*>(base);
@@ -136,9 +156,12 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny) {
     S.p = f; S.c = f + n; S.cn = f + 2 * n; S.phi = f + 3 * n; S.K = f + 4 * n; S.Rp = f + 5 * n;
     S.Rc = f + 6 * n; S.pp = f + 7 * n; S.scratch = f + 8 * n;
     uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
+    uint8_t* ql = lds;
     int lx = nx, ly = ny;
     for (int l = 0; l < S.L; ++l) {
-        T* a = reinterpret_cast<T*>(q);
+        const bool in_lds = lds && lx * ly <= lds_cells;
+        T* a = reinterpret_cast<T*>(in_lds ? ql : q);
+        if (in_lds) ql += level_bytes<T>(lx, ly);
         const int m = lx * ly;
         Level<T>& v = S.lv[l];
         v.nx = lx; v.ny = ly;
@@ -727,16 +750,18 @@ __device__ void line_sweep(Level<T>& v, int col) {
     else line_sweep_m<T, kXLine, kTrans, 4>(v, col);
 }
 
-// One zebra sweep: x-lines (even rows, odd rows), then y-lines.
+// One zebra sweep in one direction: x-lines (even rows, then odd rows) or
+// y-lines (even columns, then odd columns; a one-row level has only its
+// x-line).  The transport V-cycle pre-smooths with x-lines and post-smooths
+// with y-lines, so every cycle relaxes along both directions.
 template <typename T, bool kTrans = false>
-__device__ void line_smooth(Level<T>& v, int sweeps) {
-    for (int s = 0; s < sweeps; ++s) {
+__device__ void line_smooth(Level<T>& v, bool ylines) {
+    if (ylines && v.ny > 1) {
+        line_sweep<T, false, kTrans>(v, 0);
+        line_sweep<T, false, kTrans>(v, 1);
+    } else {
         line_sweep<T, true, kTrans>(v, 0);
         line_sweep<T, true, kTrans>(v, 1);
-        if (v.ny > 1) {
-            line_sweep<T, false, kTrans>(v, 0);
-            line_sweep<T, false, kTrans>(v, 1);
-        }
     }
 }
 
@@ -748,7 +773,7 @@ __device__ void vcycle(Solve<T>& S) {
     const int L = S.L;
     for (int l = 0; l < L - 1; ++l) {
         Level<T>& v = S.lv[l];
-        if constexpr (kTransport) line_smooth<T, kTrans>(v, 1);
+        if constexpr (kTransport) line_smooth<T, kTrans>(v, false);
         else rbgs(v, 2);
         level_residual<T, kTransport, kTrans>(v);
         __syncthreads();
@@ -773,7 +798,7 @@ __device__ void vcycle(Solve<T>& S) {
         Level<T>& v = S.lv[l];
         prolong_add(S.lv[l + 1], v);
         __syncthreads();
-        if constexpr (kTransport) line_smooth<T, kTrans>(v, 1);
+        if constexpr (kTransport) line_smooth<T, kTrans>(v, true);
         else rbgs(v, 2);
     }
 }
@@ -872,12 +897,13 @@ __device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
 // ------------------------------------------------------------------ the solve kernel
 template <typename T>
 __global__ void __launch_bounds__(512) henry_solve_kernel(Launch lp) {
+    extern __shared__ __align__(256) uint8_t lds_levels[];
     __shared__ Solve<T> S;
     __shared__ double red[16];
     const SolveDesc d = lp.descs[blockIdx.x];
     const Phys& ph = lp.ph;
     if (threadIdx.x == 0) {
-        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny);
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
     }
