@@ -84,6 +84,69 @@ def cpu_baseline_sample(solves, pairs):
     return pick
 
 
+CALIB_BYTES = 512 << 20
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "henry_solve_kernel_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_07804_amd", "csrc", f)
+                  for f in ("henry_device.hpp", "henry_api.hip")]
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _read_counters(d):
+    """{(kernel name, dispatch id): value} of a rocprofv3 --pmc csv run."""
+    import csv
+    import glob
+    out = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                key = (row["Kernel_Name"], int(row["Dispatch_Id"]))
+                out[key] = out.get(key, 0.0) + float(row["Counter_Value"])
+    return out
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """HBM traffic of the solve kernel from FETCH_SIZE and WRITE_SIZE runs
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    calibration copy of CALIB_BYTES (read once, written once)."""
+    fetch, write = _read_counters(fetch_dir), _read_counters(write_dir)
+
+    def pick(cs, pat):
+        return [v for (k, _), v in sorted(cs.items(), key=lambda kv: kv[0][1]) if pat in k]
+
+    copy_f = max(pick(fetch, "copy") + pick(fetch, "Copy") + pick(fetch, "elementwise"))
+    copy_w = max(pick(write, "copy") + pick(write, "Copy") + pick(write, "elementwise"))
+    sf = CALIB_BYTES / (copy_f * 1024.0)
+    sw = CALIB_BYTES / (copy_w * 1024.0)
+    sol_f = pick(fetch, "henry_solve_kernel")
+    sol_w = pick(write, "henry_solve_kernel")
+    per_launch = (sum(sol_f) * 1024.0 * sf + sum(sol_w) * 1024.0 * sw) / len(sol_f)
+    rec = dict(kernel="henry_solve_kernel<float>", kernel_hash=kernel_hash(), launches=len(sol_f),
+               fetch_kib=sol_f, write_kib=sol_w, calib_bytes=CALIB_BYTES, calib_fetch_kib=copy_f,
+               calib_write_kib=copy_w, fetch_scale=sf, write_scale=sw, bytes_per_launch=per_launch)
+    with open(TRAFFIC_PATH, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def load_traffic():
+    """Measured HBM bytes per solve-kernel launch, if the committed record
+    was taken on the current kernel sources."""
+    try:
+        with open(TRAFFIC_PATH) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    return rec["bytes_per_launch"] if rec.get("kernel_hash") == kernel_hash() else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,7 +157,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one device copy of CALIB_BYTES before the batch (HBM-counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs into the committed traffic record and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the ensemble shards by sample across "
               "GPUs by design but this build measures a single MI355X.", file=sys.stderr)
@@ -154,6 +224,12 @@ def main():
         res = hm.autotune(ctx, grids, xi, opts)
         tuned = {f"{nx}x{nx // 2}": v[0] for (nx, _), v in res.items()}
         log(f"autotune ({time.time() - t:.1f} s): threads per solve-workgroup {tuned}")
+    if args.calib_copy:
+        src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for w in range(args.warmup):
         t = time.time()
         step()
@@ -297,7 +373,8 @@ def main():
         "nonconverged_solves": int((status_h != 0).sum()),
         "mean_outer_iters_per_step": float(iters_h.sum() / sum(s.nsteps for s in solves)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(),
+                     "algorithmic_bytes_per_launch": sum(g["alg_bytes"] for g in per_group) / len(per_group),
                      "kernel": "henry_solve_kernel<float>",
                      "per_group": [{k: v for k, v in g.items()} for g in per_group],
                      "dominant_group": f"{dom['nx']}x{dom['ny']}"},
