@@ -68,9 +68,15 @@ typedef struct {
  *             phi = phi0 (1 + 0.2 xi1 cos(pi x/2) cos(pi y)),
  *             K = k0 exp(0.5 xi2 sin(pi x/2)), q = q_in (1 + 0.2 xi3),
  *             evaluated at cell centres.
+ *   KL41:     xi[k][41]: truncated Karhunen-Loeve expansions (20 modes of a
+ *             separable squared-exponential covariance, henry_ctx_set_kl)
+ *             phi = phi0 (1 + s_phi Z_phi), log K = log k0 + s_K Z_K,
+ *             Z_phi = sum_{k<20} sqrt(lam_k) e_k xi_k, Z_K with xi_{20+k},
+ *             q = q_in (1 + 0.2 xi_41); every grid of the call needs a basis.
  *   EXPLICIT: the caller passes packed per-cell phi and log K and a
  *             per-solve recharge q[k] (m/s). */
 #define HENRY_FIELD_CLOSED3 0
+#define HENRY_FIELD_KL41 1
 #define HENRY_FIELD_EXPLICIT 2
 
 /* Inner precision of the multigrid / line-relaxation preconditioner.  The
@@ -126,6 +132,32 @@ void henry_opts_default(henry_opts_t* opts);
  * share the key, so they see the same xi (eq:A, Sec. 3). */
 int henry_sample_xi(uint64_t seed, int32_t level, int64_t first, int64_t count, int32_t dim,
                     double* out_host);
+
+/* KL basis of the separable squared-exponential covariance
+ * C = exp(-|x-x'|^2 / (2 corr_len^2)) on [0,2] x [-1,0] at the cell centres
+ * of an nx x ny grid (host-only).  1D eigenpairs by the Nystrom method with
+ * an nquad-point Gauss-Legendre rule, eigenfunctions of unit L2 norm signed
+ * positive at the first node, interpolated by the Nystrom formula; 2D modes
+ * are products ordered by decreasing eigenvalue (ties by (a+b, a)).
+ * lambda_out [nmodes], modes_out [nmodes][ny][nx] (host). */
+int henry_kl_basis(int32_t nx, int32_t ny, int32_t nmodes, double corr_len, int32_t nquad, double* lambda_out,
+                   double* modes_out);
+
+/* Build (200-point rule, 20 modes) and upload the KL basis used by
+ * HENRY_FIELD_KL41 for nx x ny grids; sigma_phi is the relative standard
+ * deviation of porosity, sigma_logk that of log K.  The context owns the
+ * device copy. */
+int henry_ctx_set_kl(henry_ctx* ctx, int32_t nx, int32_t ny, double corr_len, double sigma_phi,
+                     double sigma_logk);
+
+/* 41 coefficients per sample for HENRY_FIELD_KL41 (host-side): components
+ * 2g, 2g+1 (g < 20) are Box-Muller normals from Philox block
+ * counter = (100 + g, level, index lo, index hi), key = (seed lo, seed hi):
+ * 53-bit integers x1 (words 0,1) and x2 (words 2,3), u1 = (x1 + 1) 2^-53,
+ * u2 = x2 2^-53, r = sqrt(-2 ln u1), (r cos 2 pi u2, r sin 2 pi u2);
+ * component 40 is uniform on [-1,1) from block (200, level, ...), words
+ * (0,1), as in henry_sample_xi.  out_host [count][41]. */
+int henry_sample_xi_kl(uint64_t seed, int32_t level, int64_t first, int64_t count, double* out_host);
 
 /* Workspace (device bytes) that henry_solve_batch needs for these solves. */
 int henry_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
@@ -188,7 +220,8 @@ int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, in
  * precision) as preconditioner.  The forward pass keeps (p, c) every
  * ckpt_every steps and recomputes each segment during the reverse sweep.
  *   qoi_out   device [nsolves]
- *   dq_dxi    device [nsolves][3] (CLOSED3 only; must be NULL for EXPLICIT)
+ *   dq_dxi    device [nsolves][3] (CLOSED3) or [nsolves][41] (KL41); must be
+ *             NULL for EXPLICIT
  *   dq_dlogk  device packed per cell, dQ/d(log K), or NULL
  *   dq_dphi   device packed per cell, dQ/dphi, or NULL
  *   dq_dq     device [nsolves], dQ/dq (q in m/s), or NULL

@@ -20,13 +20,14 @@ _DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlm
 
 HENRY_OK, HENRY_EINVAL, HENRY_ENOMEM, HENRY_EHIP, HENRY_ENOCONV, HENRY_ENONFINITE = 0, -1, -2, -3, -4, -5
 STATUS_OK, STATUS_NOCONV, STATUS_NONFINITE = 0, 1, 2
-FIELD_CLOSED3, FIELD_EXPLICIT = 0, 2
+FIELD_CLOSED3, FIELD_KL41, FIELD_EXPLICIT = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 # every symbol the header declares
 EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opts_default", "henry_sample_xi",
            "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_tune_set", "henry_tune_get",
-           "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate")
+           "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
+           "henry_ctx_set_kl", "henry_sample_xi_kl")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -108,6 +109,9 @@ def lib():
                                                 ct.POINTER(ct.c_size_t)]
     L.henry_adjoint_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, ct.POINTER(Opts), i32, dbl, i32,
                                       vp, vp, vp, vp, vp, vp, vp, vp, ct.c_size_t, vp]
+    L.henry_kl_basis.argtypes = [i32, i32, i32, dbl, i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
+    L.henry_ctx_set_kl.argtypes = [vp, i32, i32, dbl, dbl, dbl]
+    L.henry_sample_xi_kl.argtypes = [ct.c_uint64, i32, i64, i64, ct.POINTER(ct.c_double)]
     L.mlmc_level_estimate.argtypes = [vp, i32, ct.POINTER(Grid), ct.POINTER(i32), ct.POINTER(vp), ct.POINTER(vp),
                                       ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), vp, vp, vp, vp]
     _lib = L
@@ -152,6 +156,25 @@ def henry_sample_xi(seed: int, level: int, first: int, count: int, dim: int = 3)
     return out
 
 
+def henry_sample_xi_kl(seed: int, level: int, first: int, count: int):
+    import numpy as np
+    out = np.empty((count, 41), np.float64)
+    _chk(lib().henry_sample_xi_kl(seed, level, first, count, out.ctypes.data_as(ct.POINTER(ct.c_double))),
+         "henry_sample_xi_kl")
+    return out
+
+
+def henry_kl_basis(nx: int, ny: int, nmodes: int = 20, corr_len: float = 0.3, nquad: int = 200):
+    """(lam[nmodes], modes[nmodes][ny][nx]) on the host."""
+    import numpy as np
+    lam = np.empty(nmodes, np.float64)
+    modes = np.empty((nmodes, ny, nx), np.float64)
+    dp = ct.POINTER(ct.c_double)
+    _chk(lib().henry_kl_basis(nx, ny, nmodes, corr_len, nquad, lam.ctypes.data_as(dp), modes.ctypes.data_as(dp)),
+         "henry_kl_basis")
+    return lam, modes
+
+
 def henry_workspace_bytes(solves, opts: Opts | None = None, ctx=None) -> int:
     g = grids(solves)
     n = ct.c_size_t()
@@ -168,6 +191,10 @@ class Context:
         p = Phys(**{name: float(phys[name]) for name, _ in Phys._fields_})
         _chk(lib().henry_ctx_create(ct.byref(self.handle), ct.byref(p), device), "henry_ctx_create")
         self.device = device
+
+    def set_kl(self, nx: int, ny: int, corr_len: float = 0.3, sigma_phi: float = 0.1, sigma_logk: float = 0.5):
+        """Upload the KL basis used by FIELD_KL41 solves on nx x ny grids."""
+        _chk(lib().henry_ctx_set_kl(self.handle, nx, ny, corr_len, sigma_phi, sigma_logk), "henry_ctx_set_kl")
 
     def close(self):
         if self.handle:
@@ -228,10 +255,18 @@ def mlmc_level_estimate(ctx: Context, fine_grids, m, c_fine, c_coarse, q_fine, q
 
 
 # ------------------------------------------------------------------ convenience layer
+def _field_of(xi):
+    if xi is None:
+        return FIELD_EXPLICIT
+    return FIELD_KL41 if xi.shape[-1] == 41 else FIELD_CLOSED3
+
+
 def solve(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, c0=None, opts: Opts | None = None,
           want_p=False, stream=None):
     """Allocate outputs/workspace with torch and run one batch.
-    solves: list of (nx, ny, nsteps).  Returns dict of device tensors."""
+    solves: list of (nx, ny, nsteps).  xi [n][3] selects the closed-form
+    fields, xi [n][41] the KL fields (Context.set_kl for every grid), no xi
+    the explicit fields.  Returns dict of device tensors."""
     import torch
     dev = torch.device("cuda", ctx.device)
     opts = opts or opts_default()
@@ -246,7 +281,7 @@ def solve(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, c0=None,
                status=torch.empty(len(solves), dtype=torch.int32, device=dev),
                iters=torch.empty(len(solves), dtype=torch.int32, device=dev))
     out["p"] = torch.empty(cells, dtype=torch.float64, device=dev) if want_p else None
-    field = FIELD_CLOSED3 if xi is not None else FIELD_EXPLICIT
+    field = _field_of(xi)
     henry_solve_batch(ctx, solves, field, xi=xi, phi=phi, logk=logk, qin=qin, c0=c0, opts=opts, c_out=out["c"],
                       p_out=out["p"], qoi_out=out["qoi"], status=out["status"], iters=out["iters"], workspace=ws,
                       stream=stream)
@@ -309,9 +344,9 @@ def adjoint(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, opts: 
     out = dict(qoi=torch.empty(ns, **f64), dq_dlogk=torch.empty(cells, **f64), dq_dphi=torch.empty(cells, **f64),
                dq_dq=torch.empty(ns, **f64), status=torch.empty(ns, dtype=torch.int32, device=dev),
                iters=torch.empty(ns, dtype=torch.int32, device=dev))
-    closed = xi is not None
-    out["dq_dxi"] = torch.empty((ns, 3), **f64) if closed else None
-    henry_adjoint_batch(ctx, solves, FIELD_CLOSED3 if closed else FIELD_EXPLICIT, xi=xi, phi=phi, logk=logk,
+    field = _field_of(xi)
+    out["dq_dxi"] = torch.empty((ns, xi.shape[-1]), **f64) if xi is not None else None
+    henry_adjoint_batch(ctx, solves, field, xi=xi, phi=phi, logk=logk,
                         qin=qin, opts=opts, ckpt_every=ckpt_every, adj_tol=adj_tol, adj_max_it=adj_max_it,
                         qoi_out=out["qoi"], dq_dxi=out["dq_dxi"], dq_dlogk=out["dq_dlogk"], dq_dphi=out["dq_dphi"],
                         dq_dq=out["dq_dq"], status=out["status"], iters=out["iters"], workspace=ws, stream=stream)

@@ -404,6 +404,24 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     }
     g1 = block_sum(g1, red);
     g2 = block_sum(g2, red);
+    if (lp.field_kind == 2 && al.dq_dxi) {
+        // KL coefficients: dphi/dxi_k = phi0 s_phi m_k, dK/dxi_{20+k} = K s_K m_k
+        for (int k = 0; k < 20; ++k) {
+            double ap = 0.0, ak = 0.0;
+            for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+                const double m = lp.kl_modes[(size_t)k * n + idx];
+                ap += A.gphi[idx] * m;
+                ak += A.gK[idx] * S.K[idx] * m;
+            }
+            ap = block_sum(ap, red);
+            ak = block_sum(ak, red);
+            if (threadIdx.x == 0) {
+                al.dq_dxi[41 * d.index + k] = ap * ph.phi0 * lp.kl_sigma_phi;
+                al.dq_dxi[41 * d.index + 20 + k] = ak * lp.kl_sigma_logk;
+            }
+        }
+        if (threadIdx.x == 0) al.dq_dxi[41 * d.index + 40] = gq * ph.q_in * 0.2;
+    }
     if (threadIdx.x == 0) {
         lp.qoi_out[d.index] = Q;
         lp.status[d.index] = status;

@@ -20,6 +20,7 @@
 #include "henry.h"
 #include "henry_adjoint.hpp"
 #include "henry_device.hpp"
+#include "henry_kl.hpp"
 #include "henry_mlmc.hpp"
 
 namespace {
@@ -38,6 +39,14 @@ struct Group {
 struct PlanKey {
     std::vector<int64_t> words;
     bool operator==(const PlanKey& o) const { return words == o.words; }
+};
+
+constexpr int kKlModes = 20;
+
+// KL basis of one grid in device memory: sqrt(lam_k) e_k at the cells.
+struct KlGrid {
+    double* modes = nullptr;  // [kKlModes][nx*ny]
+    double sigma_phi = 0.1, sigma_logk = 0.5;
 };
 
 }  // namespace
@@ -62,6 +71,8 @@ struct henry_ctx {
     // may be the legacy null stream, which cannot be captured)
     hipStream_t cap_stream = nullptr;
     hipEvent_t cap_in = nullptr, cap_out = nullptr;
+    // KL bases by grid width
+    std::map<int, KlGrid> kl;
 };
 
 namespace {
@@ -133,6 +144,12 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
+        if (l.field_kind == 2) {
+            const KlGrid& kg = ctx->kl.at(G.nx);
+            l.kl_modes = kg.modes;
+            l.kl_sigma_phi = kg.sigma_phi;
+            l.kl_sigma_logk = kg.sigma_logk;
+        }
         hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
         // lockstep time chunks: local step s of a solve with r steps runs in
         // global step s * rmax / r; one chunk when steps_per_launch == 0
@@ -247,6 +264,8 @@ void henry_ctx_destroy(henry_ctx* c) {
         (void)hipStreamDestroy(c->cap_stream);
     }
     if (c->cap_in) (void)hipEventDestroy(c->cap_in);
+    for (auto& kv : c->kl)
+        if (kv.second.modes) (void)hipFree(kv.second.modes);
     if (c->cap_out) (void)hipEventDestroy(c->cap_out);
     delete c;
 }
@@ -285,6 +304,71 @@ int henry_sample_xi(uint64_t seed, int32_t level, int64_t first, int64_t count, 
     return HENRY_OK;
 }
 
+int henry_kl_basis(int32_t nx, int32_t ny, int32_t nmodes, double corr_len, int32_t nquad, double* lambda_out,
+                   double* modes_out) {
+    if (nx < 2 || ny < 1 || nx != 2 * ny || nmodes < 1 || nmodes > 64 || !(corr_len > 0.0) || nquad < 8 ||
+        nquad > 1024 || !lambda_out || !modes_out)
+        return HENRY_EINVAL;
+    std::vector<double> lam, modes;
+    henry::kl::basis_2d(nx, ny, nmodes, corr_len, nquad, lam, modes);
+    std::memcpy(lambda_out, lam.data(), sizeof(double) * nmodes);
+    std::memcpy(modes_out, modes.data(), sizeof(double) * modes.size());
+    return HENRY_OK;
+}
+
+int henry_ctx_set_kl(henry_ctx* ctx, int32_t nx, int32_t ny, double corr_len, double sigma_phi,
+                     double sigma_logk) {
+    if (!ctx) return HENRY_EINVAL;
+    henry_grid_t g{nx, ny, 1, 0};
+    if (check_grid(g) != HENRY_OK || !(corr_len > 0.0) || !std::isfinite(sigma_phi) || !std::isfinite(sigma_logk))
+        return HENRY_EINVAL;
+    std::vector<double> lam, modes;
+    henry::kl::basis_2d(nx, ny, kKlModes, corr_len, 200, lam, modes);
+    const size_t n = (size_t)nx * ny;
+    for (int k = 0; k < kKlModes; ++k) {
+        const double s = std::sqrt(std::max(lam[k], 0.0));
+        for (size_t i = 0; i < n; ++i) modes[(size_t)k * n + i] *= s;
+    }
+    DeviceGuard dg(ctx->device);
+    KlGrid& kg = ctx->kl[nx];
+    if (!kg.modes && hipMalloc(&kg.modes, sizeof(double) * modes.size()) != hipSuccess) {
+        ctx->kl.erase(nx);
+        return HENRY_ENOMEM;
+    }
+    if (hipMemcpy(kg.modes, modes.data(), sizeof(double) * modes.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return HENRY_EHIP;
+    kg.sigma_phi = sigma_phi;
+    kg.sigma_logk = sigma_logk;
+    if (ctx->graph_exec) {  // a cached graph may refer to the old basis
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+    }
+    return HENRY_OK;
+}
+
+int henry_sample_xi_kl(uint64_t seed, int32_t level, int64_t first, int64_t count, double* out) {
+    if (!out || count < 0 || first < 0 || level < 0) return HENRY_EINVAL;
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    for (int64_t s = 0; s < count; ++s) {
+        const uint64_t index = (uint64_t)(first + s);
+        const uint32_t ilo = (uint32_t)(index & 0xffffffffu), ihi = (uint32_t)(index >> 32);
+        for (int g = 0; g < 20; ++g) {
+            uint32_t x[4] = {(uint32_t)(100 + g), (uint32_t)level, ilo, ihi};
+            philox10(x, k0, k1);
+            const uint64_t b1 = (((uint64_t)x[1] << 32) | x[0]) >> 11;
+            const uint64_t b2 = (((uint64_t)x[3] << 32) | x[2]) >> 11;
+            const double u1 = std::ldexp((double)(b1 + 1), -53), u2 = std::ldexp((double)b2, -53);
+            const double r = std::sqrt(-2.0 * std::log(u1));
+            out[s * 41 + 2 * g] = r * std::cos(2.0 * M_PI * u2);
+            out[s * 41 + 2 * g + 1] = r * std::sin(2.0 * M_PI * u2);
+        }
+        uint32_t x[4] = {200u, (uint32_t)level, ilo, ihi};
+        philox10(x, k0, k1);
+        out[s * 41 + 40] = std::ldexp((double)((((uint64_t)x[1] << 32) | x[0]) >> 11), -52) - 1.0;
+    }
+    return HENRY_OK;
+}
+
 int henry_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, const henry_opts_t* opts,
                           size_t* bytes_out) {
     (void)ctx;  // host-only computation; a context is not needed
@@ -315,6 +399,10 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     if (int rc = check_opts(o)) return rc;
     if (field == HENRY_FIELD_CLOSED3) {
         if (!xi) return HENRY_EINVAL;
+    } else if (field == HENRY_FIELD_KL41) {
+        if (!xi) return HENRY_EINVAL;
+        for (int k = 0; k < nsolves; ++k)
+            if (ctx->kl.find(solves[k].nx) == ctx->kl.end()) return HENRY_EINVAL;
     } else if (field == HENRY_FIELD_EXPLICIT) {
         if (!phi || !logk || !qin) return HENRY_EINVAL;
     } else {
@@ -389,7 +477,8 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
     lp.tol = o->tol;
     lp.max_outer = o->max_outer;
-    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : 1;
+    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : (field == HENRY_FIELD_KL41 ? 2 : 1);
+    lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
 
     const int ng = (int)order.size();
     const bool serial = o->serial_groups != 0;
@@ -466,10 +555,18 @@ int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
     if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
     if (threads == 0) {
         ctx->tuned_threads.erase((long)nx * 4 + prec);
+        if (ctx->graph_exec) {
+            (void)hipGraphExecDestroy(ctx->graph_exec);
+            ctx->graph_exec = nullptr;
+        }
         return HENRY_OK;
     }
     if (threads < 64 || threads > 512 || !pow2(threads)) return HENRY_EINVAL;
     ctx->tuned_threads[(long)nx * 4 + prec] = threads;
+    if (ctx->graph_exec) {  // the cached graph was built with the old choice
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+    }
     return HENRY_OK;
 }
 
@@ -529,6 +626,10 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     if (int rc = check_opts(o)) return rc;
     if (field == HENRY_FIELD_CLOSED3) {
         if (!xi) return HENRY_EINVAL;
+    } else if (field == HENRY_FIELD_KL41) {
+        if (!xi) return HENRY_EINVAL;
+        for (int k = 0; k < nsolves; ++k)
+            if (ctx->kl.find(solves[k].nx) == ctx->kl.end()) return HENRY_EINVAL;
     } else if (field == HENRY_FIELD_EXPLICIT) {
         if (!phi || !logk || !qin || dq_dxi) return HENRY_EINVAL;
     } else {
@@ -597,7 +698,8 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
     lp.tol = o->tol;
     lp.max_outer = o->max_outer;
-    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : 1;
+    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : (field == HENRY_FIELD_KL41 ? 2 : 1);
+    lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
     henry::AdjLaunch al{};
     al.ckpt = ckpt_every;
     al.max_it = adj_max_it;
@@ -614,6 +716,12 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
+        if (l.field_kind == 2) {
+            const KlGrid& kg = ctx->kl.at(G.nx);
+            l.kl_modes = kg.modes;
+            l.kl_sigma_phi = kg.sigma_phi;
+            l.kl_sigma_logk = kg.sigma_logk;
+        }
         hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
         l.lds_cells = kLdsCells;
         const size_t lds = (size_t)(prec == HENRY_PREC_MIXED

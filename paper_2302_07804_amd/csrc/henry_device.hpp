@@ -73,6 +73,9 @@ struct Launch {
     int32_t g_begin, g_end;  // global step range of this launch
     int32_t g_total;         // global steps of the whole batch (max nsteps)
     int32_t lds_cells;       // multigrid levels with at most this many cells live in LDS
+    int32_t xi_dim;          // coefficients per solve in xi (3 closed form, 41 KL)
+    const double* kl_modes;  // KL: sqrt(lam_k) e_k at the cells of this group's grid, [20][n]
+    double kl_sigma_phi, kl_sigma_logk;
 };
 
 // ------------------------------------------------------------------ layout
@@ -965,7 +968,22 @@ __global__ void henry_fields_kernel(Launch lp) {
     double* K = f + 4 * n;
     double* sp = f + kF64Arrays * n;
     const double h = 1.0 / ny;
-    if (lp.field_kind == 0) {
+    if (lp.field_kind == 2) {
+        // truncated KL expansions: phi = phi0 (1 + s_phi Z_phi), log K = log k0 + s_K Z_K,
+        // Z = sum_k sqrt(lam_k) e_k xi_k; recharge factor (1 + 0.2 xi_41)
+        const double* xi = lp.xi + (size_t)41 * d.index;
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            double zp = 0.0, zk = 0.0;
+            for (int k = 0; k < 20; ++k) {
+                const double m = lp.kl_modes[(size_t)k * n + idx];
+                zp += m * xi[k];
+                zk += m * xi[20 + k];
+            }
+            phi[idx] = ph.phi0 * (1.0 + lp.kl_sigma_phi * zp);
+            K[idx] = exp(log(ph.k0) + lp.kl_sigma_logk * zk);
+        }
+        if (threadIdx.x == 0) sp[0] = ph.q_in * (1.0 + 0.2 * xi[40]);
+    } else if (lp.field_kind == 0) {
         const double x1 = lp.xi[3 * d.index], x2 = lp.xi[3 * d.index + 1], x3 = lp.xi[3 * d.index + 2];
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
             const int i = idx % nx, j = idx / nx;

@@ -1,6 +1,6 @@
 """Host-side checks of the C-ABI library (no GPU needed): it loads, exports
-every symbol `include/henry.h` declares, its sample generator is bit-exact
-with the oracle's and with a Python integer reference of Philox4x32-10, and
+every symbol `include/henry.h` declares, its sample generators and KL basis agree
+with the oracle and with a Python integer reference of Philox4x32-10, and
 argument validation rejects bad grids and options before any launch."""
 import ctypes as ct
 import os
@@ -9,6 +9,7 @@ import re
 import numpy as np
 import pytest
 
+import henry_inputs as hi
 import paper_2302_07804_amd as hm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -97,3 +98,32 @@ def test_solve_batch_rejects_null_context(L):
                              0, None)
     assert rc == hm.HENRY_EINVAL
     assert hm.strerror(hm.HENRY_EINVAL) == "invalid argument"
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 8), (64, 32), (256, 128)])
+def test_kl_basis_matches_oracle(L, nx, ny):
+    from oracle import kl
+    lam, modes = hm.henry_kl_basis(nx, ny)
+    lam_o, modes_o = kl.basis(nx, ny)
+    np.testing.assert_allclose(lam, lam_o, rtol=1e-12)
+    assert np.abs(modes - modes_o).max() <= 1e-11 * np.abs(modes_o).max()
+
+
+@pytest.mark.parametrize("seed,level,first,count", [(0, 0, 0, 40), (hi.SEED, 3, (1 << 32) + 5, 9)])
+def test_sample_xi_kl_matches_oracle(L, seed, level, first, count):
+    from oracle import kl
+    a = hm.henry_sample_xi_kl(seed, level, first, count)
+    b = kl.sample_xi41(seed, level, first, count)
+    # the uniform component is exact; the normals go through libm log/cos/sin
+    assert np.array_equal(a[:, 40], b[:, 40])
+    np.testing.assert_allclose(a, b, rtol=4e-16, atol=4e-16)
+
+
+def test_kl_entry_points_reject_bad_arguments(L):
+    lam = np.empty(20); modes = np.empty((20, 8, 16))
+    dp = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_double))
+    assert L.henry_kl_basis(16, 8, 0, 0.3, 200, dp(lam), dp(modes)) == hm.HENRY_EINVAL
+    assert L.henry_kl_basis(16, 8, 20, -0.3, 200, dp(lam), dp(modes)) == hm.HENRY_EINVAL
+    assert L.henry_kl_basis(16, 9, 20, 0.3, 200, dp(lam), dp(modes)) == hm.HENRY_EINVAL
+    assert L.henry_ctx_set_kl(None, 16, 8, 0.3, 0.1, 0.5) == hm.HENRY_EINVAL
+    assert L.henry_sample_xi_kl(0, 0, 0, -1, dp(lam)) == hm.HENRY_EINVAL
