@@ -90,8 +90,11 @@ typedef struct {
     int32_t max_outer;        /* defect-correction iterations per step (>= 1)   */
     double tol;               /* stop a step when max_P |R_P| tau/(h^2 phi_P rho0)
                                  <= tol for both the fluid and the salt equation */
-    int32_t threads;          /* threads per solve-workgroup (64..512, power of
-                                 two); 0 = tuned choice                          */
+    int32_t threads;          /* threads per solve-workgroup, a power of two:
+                                 64..1024 with PREC_MIXED, 64..512 with
+                                 PREC_FP64 and in henry_adjoint_batch (a tuned
+                                 choice above 512 is clamped there); 0 = tuned
+                                 choice                                          */
     int32_t steps_per_launch; /* 0 = whole time loop in one launch per grid
                                  group; k > 0 = launches of k global steps, all
                                  captured into one hipGraph and replayed        */
@@ -191,7 +194,8 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
  * width nx at precision prec, used by henry_solve_batch and
  * henry_adjoint_batch when opts->threads == 0.  threads = 0 clears the
  * entry (back to the built-in default: 64 threads up to 128 cells, 128 up
- * to 512, 256 up to 2048, 512 above).  The measuring driver that fills it
+ * to 512, 256 up to 2048, 512 above); threads <= 1024 for PREC_MIXED and
+ * <= 512 for PREC_FP64.  The measuring driver that fills it
  * times candidate sizes on short runs of the caller's own batch (Python
  * binding: paper_2302_07804_amd.autotune). */
 int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads);

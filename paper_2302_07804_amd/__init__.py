@@ -426,7 +426,7 @@ def henry_tune_get(ctx: Context, nx: int, prec: int) -> int:
 
 
 def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int = 8, max_solves: int = 1024,
-             candidates=(64, 128, 256, 512), cache_path: str | None = None):
+             candidates=(64, 128, 256, 512, 1024), cache_path: str | None = None):
     """Choose the threads per solve-workgroup for every grid of `solves` by
     timing short runs (the first `tune_steps` steps of up to `max_solves`
     solves of that grid, each candidate twice, HIP-event group time on the
@@ -456,8 +456,9 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
         xs = xi[ks].contiguous()
         cells = nx * (nx // 2)
         times = {}
+        tmax = 1024 if prec == PREC_MIXED else 512
         for t in candidates:
-            if t > 64 and t > 2 * cells:
+            if (t > 64 and t > 2 * cells) or t > tmax:
                 continue
             o = make_opts(prec=prec, tol=opts.tol, max_outer=opts.max_outer, threads=t, profile=1)
             best = None

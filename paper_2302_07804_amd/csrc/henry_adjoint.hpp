@@ -232,8 +232,8 @@ __device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int 
             A.r_p[idx] = rp;
             A.r_c[idx] = rc;
             // norm in units of the local diagonal of each block
-            const Stencil<T> sp = pstencil(L0, i, j);
-            const Stencil<T> sc = cstencil_t(L0, i, j);
+            const Stencil<T> sp = pstencil(L0, Nb(i, j, L0.nx, L0.ny));
+            const Stencil<T> sc = cstencil_t(L0, Nb(i, j, L0.nx, L0.ny), j);
             rmax = nanmax(rmax, fabs(rp) / (double)sp.d);
             rmax = nanmax(rmax, fabs(rc) / (double)sc.d);
             L0.b[idx] = (T)(block == 0 ? rp : rc);
@@ -278,8 +278,8 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
     double bm = 0.0;
     for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
         const int i = idx % S.nx, j = idx / S.nx;
-        bm = nanmax(bm, fabs(A.b_p[idx]) / (double)pstencil(S.lv[0], i, j).d);
-        bm = nanmax(bm, fabs(A.b_c[idx]) / (double)cstencil_t(S.lv[0], i, j).d);
+        bm = nanmax(bm, fabs(A.b_p[idx]) / (double)pstencil(S.lv[0], Nb(i, j, S.nx, S.ny)).d);
+        bm = nanmax(bm, fabs(A.b_c[idx]) / (double)cstencil_t(S.lv[0], Nb(i, j, S.nx, S.ny), j).d);
     }
     bm = block_max(bm, red);
     if (!(bm == bm)) return 2;

@@ -28,7 +28,8 @@ namespace {
 constexpr int kStreams = 4;
 // Multigrid levels of at most this many cells (32 x 16 and coarser) are kept
 // in LDS: 28 KB per workgroup at FP32, 56 KB at FP64.
-constexpr int kLdsCells = 512;
+constexpr int kLdsCells = 512;  // levels of at most this many cells live in LDS
+static_assert(kLdsCells >= 2, "the coarsest level (2 x 1) must be in LDS");
 
 struct Group {
     int nx, ny, threads;
@@ -90,6 +91,11 @@ struct DeviceGuard {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Largest workgroup of the solve kernel: the FP32-inner instantiation is
+// built for 1024 threads (<= 128 VGPRs), the FP64 one for 512.
+int max_threads(int prec) { return prec == HENRY_PREC_MIXED ? 1024 : 512; }
+constexpr int kAdjMaxThreads = 512;
+
 int check_grid(const henry_grid_t& g) {
     if (g.reserved != 0) return HENRY_EINVAL;
     if (g.ny < 1 || g.ny > 128 || !pow2(g.ny) || g.nx != 2 * g.ny) return HENRY_EINVAL;
@@ -102,7 +108,8 @@ int check_opts(const henry_opts_t* o) {
     if (o->prec != HENRY_PREC_FP64 && o->prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
     if (o->max_outer < 1 || o->max_outer > 100000) return HENRY_EINVAL;
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return HENRY_EINVAL;
-    if (o->threads != 0 && (o->threads < 64 || o->threads > 512 || !pow2(o->threads))) return HENRY_EINVAL;
+    if (o->threads != 0 && (o->threads < 64 || o->threads > max_threads(o->prec) || !pow2(o->threads)))
+        return HENRY_EINVAL;
     if (o->steps_per_launch < 0) return HENRY_EINVAL;
     if (o->profile != 0 && o->profile != 1) return HENRY_EINVAL;
     if (o->serial_groups != 0 && o->serial_groups != 1) return HENRY_EINVAL;
@@ -561,7 +568,7 @@ int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
         }
         return HENRY_OK;
     }
-    if (threads < 64 || threads > 512 || !pow2(threads)) return HENRY_EINVAL;
+    if (threads < 64 || threads > max_threads(prec) || !pow2(threads)) return HENRY_EINVAL;
     ctx->tuned_threads[(long)nx * 4 + prec] = threads;
     if (ctx->graph_exec) {  // the cached graph was built with the old choice
         (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -624,6 +631,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     henry_opts_default(&def);
     const henry_opts_t* o = opts ? opts : &def;
     if (int rc = check_opts(o)) return rc;
+    if (o->threads > kAdjMaxThreads) return HENRY_EINVAL;
     if (field == HENRY_FIELD_CLOSED3) {
         if (!xi) return HENRY_EINVAL;
     } else if (field == HENRY_FIELD_KL41) {
@@ -673,7 +681,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
             auto it = ctx->tuned_threads.find((long)G.nx * 4 + prec);
             t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny);
         }
-        G.threads = t;
+        G.threads = std::min(t, kAdjMaxThreads);
     }
     DeviceGuard dg(ctx->device);
     hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);

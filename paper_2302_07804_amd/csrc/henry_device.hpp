@@ -99,10 +99,16 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
     return align256((int64_t)(kLevelArrays * nx * ny + kRowArrays * ny) * (int64_t)sizeof(T));
 }
 
-// FP64 arrays: p, c, cn, phi, K, Rp, Rc, pp (previous p), then kScratch
-// doubles of scratch ([0] recharge, [1] status, [2] outer iterations,
-// [8..] phase timers of builds with HENRY_PHASE_TIMERS).
-constexpr int kF64Arrays = 8;
+// FP64 arrays: p, c, cn, phi, K, Rp, Rc, pp (previous p), then the face
+// coefficients that depend only on the fields, set once per solve:
+//   tx, ty  east / north face K_f / mu (harmonic K; 2 K_P / mu on the
+//           seawater face; 0 above the top row),
+//   wx, wy  east / north face phi_f D (harmonic phi; 2 phi_P D on the
+//           seawater face; 0 above the top row),
+//   isc     residual scale tau / (h^2 phi_P rho0),
+// then kScratch doubles of scratch ([0] recharge, [1] status, [2] outer
+// iterations, [8..] phase timers of builds with HENRY_PHASE_TIMERS).
+constexpr int kF64Arrays = 13;
 constexpr int kScratch = 32;
 
 template <typename T>
@@ -119,16 +125,40 @@ __host__ __device__ inline int64_t solve_bytes(int nx, int ny) {
 
 template <typename T>
 struct Level {
+    using value_type = T;
     int nx, ny;
     T *x, *b, *r, *te, *tn, *acc, *mx, *my, *dx, *dy, *dl, *dr, *mr, *ml;
+};
+
+// Address-space-typed view of a level for the smoothers and transfers: AS 1
+// (global memory) or 3 (LDS) lets the compiler emit global_* / ds_*
+// instructions instead of flat ones; AS 0 keeps generic pointers.
+template <typename T, int AS> struct AsPtr { using type = T*; };
+template <typename T> struct AsPtr<T, 1> { using type = __attribute__((address_space(1))) T*; };
+template <typename T> struct AsPtr<T, 3> { using type = __attribute__((address_space(3))) T*; };
+template <int AS, typename T>
+__device__ inline typename AsPtr<T, AS>::type as_ptr(T* p) { return (typename AsPtr<T, AS>::type)p; }
+
+template <typename T, int AS>
+struct LV {
+    using value_type = T;
+    using P = typename AsPtr<T, AS>::type;
+    int nx, ny;
+    P x, b, r, te, tn, acc, mx, my, dx, dy, dl, dr, mr, ml;
+    __device__ explicit LV(const Level<T>& v)
+        : nx(v.nx), ny(v.ny), x(as_ptr<AS>(v.x)), b(as_ptr<AS>(v.b)), r(as_ptr<AS>(v.r)), te(as_ptr<AS>(v.te)),
+          tn(as_ptr<AS>(v.tn)), acc(as_ptr<AS>(v.acc)), mx(as_ptr<AS>(v.mx)), my(as_ptr<AS>(v.my)),
+          dx(as_ptr<AS>(v.dx)), dy(as_ptr<AS>(v.dy)), dl(as_ptr<AS>(v.dl)), dr(as_ptr<AS>(v.dr)),
+          mr(as_ptr<AS>(v.mr)), ml(as_ptr<AS>(v.ml)) {}
 };
 
 template <typename T>
 struct Solve {
     int nx, ny, n, nsteps, L;
+    int lds_from;  // first level whose arrays live in LDS (L if none)
     double h, tau;
     double q;  // recharge (m/s)
-    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *scratch;
+    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *tx, *ty, *wx, *wy, *isc, *scratch;
     Level<T> lv[kMaxLevels];
 };
 
@@ -148,21 +178,24 @@ __host__ __device__ inline int64_t lds_level_bytes(int nx, int ny, int lds_cells
 
 // Binds the solve's arrays.  Levels with at most `lds_cells` cells get
 // their inner arrays in the workgroup's LDS (`lds`): they are rebuilt every
-// iteration, so nothing there has to survive a launch.
+// iteration, so nothing there has to survive a launch.  lds_cells >= 2, so
+// the coarsest level (2 x 1) is always in LDS and S.lds_from < S.L.
 template <typename T>
-__device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, uint8_t* lds = nullptr,
-                                  int lds_cells = 0) {
+__device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, uint8_t* lds, int lds_cells) {
     S.nx = nx; S.ny = ny; S.n = nx * ny; S.L = num_levels(ny);
     S.h = 1.0 / ny;
     double* f = reinterpret_cast<double*>(base);
     const int n = nx * ny;
     S.p = f; S.c = f + n; S.cn = f + 2 * n; S.phi = f + 3 * n; S.K = f + 4 * n; S.Rp = f + 5 * n;
-    S.Rc = f + 6 * n; S.pp = f + 7 * n; S.scratch = f + 8 * n;
+    S.Rc = f + 6 * n; S.pp = f + 7 * n; S.tx = f + 8 * n; S.ty = f + 9 * n; S.wx = f + 10 * n;
+    S.wy = f + 11 * n; S.isc = f + 12 * n; S.scratch = f + kF64Arrays * n;
     uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
     uint8_t* ql = lds;
     int lx = nx, ly = ny;
+    S.lds_from = S.L;
     for (int l = 0; l < S.L; ++l) {
-        const bool in_lds = lds && lx * ly <= lds_cells;
+        const bool in_lds = lx * ly <= lds_cells;
+        if (in_lds && S.lds_from == S.L) S.lds_from = l;
         T* a = reinterpret_cast<T*>(in_lds ? ql : q);
         if (in_lds) ql += level_bytes<T>(lx, ly);
         const int m = lx * ly;
@@ -212,50 +245,82 @@ __device__ inline double block_sum(double v, double* red) {
     return r;
 }
 
+// Every level's nx and ny are powers of two: cell coordinates come from
+// shifts and masks instead of integer division.
+__device__ inline int log2i(int v) { return __builtin_ctz((unsigned)v); }
+
+// Division inside the FP32 inner solves uses the hardware reciprocal (about
+// 1 ulp; the solves only precondition the FP64 defect correction); the FP64
+// path divides exactly.
+template <typename T>
+__device__ inline T qdiv(T a, T b) {
+    if constexpr (sizeof(T) == 4) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+
+// ------------------------------------------------------------------ teams
+// The threads that run one multigrid operation together: the whole
+// workgroup (levels in global memory), or wavefront 0 alone (the coarse
+// levels in LDS, where barrier latency would dominate the little work).
+// Within one wavefront the lanes execute in lockstep and LDS operations of
+// the wavefront complete in issue order, so a wavefront-scope fence (which
+// keeps the compiler from moving memory operations across it) is the whole
+// synchronisation.
+struct BlockTeam {
+    __device__ static int rank() { return threadIdx.x; }
+    __device__ static int size() { return blockDim.x; }
+    __device__ static void sync() { __syncthreads(); }
+};
+struct WaveTeam {
+    __device__ static int rank() { return threadIdx.x & (kWave - 1); }
+    __device__ static int size() { return kWave; }
+    __device__ static void sync() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
 // ------------------------------------------------------------------ physics (FP64)
 __device__ inline double rho_of(const Phys& ph, double c) { return ph.rho0 + (ph.rho1 - ph.rho0) * c; }
 
-// Mass and salt flux from cell (i,j) to its east neighbour (i+1,j), per metre
-// of depth: harmonic K and phi, arithmetic rho on the face; donor cell.
+// Mass and salt flux from cell a to its east neighbour b, per metre of
+// depth: harmonic K and phi on the face (precomputed: tx = K_f/mu,
+// wx = phi_f D), arithmetic rho; donor cell.
 struct FaceFlux { double M, F, lam, dif; };
 
-__device__ inline FaceFlux flux_x(const Phys& ph, const double* p, const double* c, const double* phi,
-                                  const double* K, int a, int b) {
+__device__ inline FaceFlux flux_x(const Phys& ph, const double* p, const double* c, double kf, double wf, int a,
+                                  int b) {
     FaceFlux f;
     const double ca = c[a], cb = c[b];
     const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
-    const double Ka = K[a], Kb = K[b], pa = phi[a], pb = phi[b];
-    const double Kf = 2.0 * Ka * Kb / (Ka + Kb);
-    const double phf = 2.0 * pa * pb / (pa + pb);
-    f.lam = rf * Kf / ph.mu;
-    f.dif = rf * phf * ph.D;
+    f.lam = rf * kf;
+    f.dif = rf * wf;
     f.M = -f.lam * (p[b] - p[a]);
     f.F = f.M * (f.M >= 0.0 ? ca : cb) - f.dif * (cb - ca);
     return f;
 }
 
 // North neighbour: Darcy's law with gravity (0,-g) adds rho_f g h.
-__device__ inline FaceFlux flux_y(const Phys& ph, double h, const double* p, const double* c, const double* phi,
-                                  const double* K, int a, int b) {
+__device__ inline FaceFlux flux_y(const Phys& ph, double h, const double* p, const double* c, double kf, double wf,
+                                  int a, int b) {
     FaceFlux f;
     const double ca = c[a], cb = c[b];
     const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
-    const double Ka = K[a], Kb = K[b], pa = phi[a], pb = phi[b];
-    const double Kf = 2.0 * Ka * Kb / (Ka + Kb);
-    const double phf = 2.0 * pa * pb / (pa + pb);
-    f.lam = rf * Kf / ph.mu;
-    f.dif = rf * phf * ph.D;
+    f.lam = rf * kf;
+    f.dif = rf * wf;
     f.M = -f.lam * ((p[b] - p[a]) + rf * ph.g * h);
     f.F = f.M * (f.M >= 0.0 ? ca : cb) - f.dif * (cb - ca);
     return f;
 }
 
-// Seawater face at x = 2 (half-cell distance): p_B = -rho1 g y, c_B = 1.
-__device__ inline FaceFlux flux_right(const Phys& ph, double y, double pP, double cP, double phiP, double KP) {
+// Seawater face at x = 2 (half-cell distance): p_B = -rho1 g y, c_B = 1;
+// kf = 2 K_P / mu, wf = 2 phi_P D.
+__device__ inline FaceFlux flux_right(const Phys& ph, double y, double pP, double cP, double kf, double wf) {
     FaceFlux f;
     const double rB = 0.5 * (rho_of(ph, cP) + ph.rho1);
-    f.lam = 2.0 * rB * KP / ph.mu;
-    f.dif = 2.0 * rB * phiP * ph.D;
+    f.lam = rB * kf;
+    f.dif = rB * wf;
     f.M = -f.lam * (-ph.rho1 * ph.g * y - pP);
     f.F = f.M * (f.M >= 0.0 ? cP : 1.0) - f.dif * (1.0 - cP);
     return f;
@@ -283,28 +348,29 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
     const double h = S.h, h2t = h * h / S.tau;
     Level<T>& L0 = S.lv[0];
     double mp = 0.0, mc = 0.0;
+    const int sx = log2i(nx);
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int i = idx % nx, j = idx / nx;
+        const int i = idx & (nx - 1), j = idx >> sx;
         const double cP = S.c[idx], cnP = S.cn[idx], phiP = S.phi[idx];
         const double rP = rho_of(ph, cP), rN = rho_of(ph, cnP);
         double Rp = h2t * phiP * (rP - rN);
         double Rc = h2t * phiP * (rP * cP - rN * cnP);
         // east face
         if (i + 1 < nx) {
-            FaceFlux f = flux_x(ph, S.p, S.c, S.phi, S.K, idx, idx + 1);
+            FaceFlux f = flux_x(ph, S.p, S.c, S.tx[idx], S.wx[idx], idx, idx + 1);
             Rp += f.M; Rc += f.F;
             if (mode == 0) L0.te[idx] = (T)f.lam;
             else { L0.mx[idx] = (T)f.M; L0.dx[idx] = (T)f.dif; }
         } else {
             const double y = -1.0 + (j + 0.5) * h;
-            FaceFlux f = flux_right(ph, y, S.p[idx], cP, phiP, S.K[idx]);
+            FaceFlux f = flux_right(ph, y, S.p[idx], cP, S.tx[idx], S.wx[idx]);
             Rp += f.M; Rc += f.F;
             if (mode == 0) L0.te[idx] = (T)f.lam;
             else { L0.mx[idx] = (T)0; L0.dx[idx] = (T)0; L0.dr[j] = (T)f.dif; L0.mr[j] = (T)f.M; }
         }
         // west face
         if (i > 0) {
-            FaceFlux f = flux_x(ph, S.p, S.c, S.phi, S.K, idx - 1, idx);
+            FaceFlux f = flux_x(ph, S.p, S.c, S.tx[idx - 1], S.wx[idx - 1], idx - 1, idx);
             Rp -= f.M; Rc -= f.F;
         } else {
             FaceFlux f = flux_left(ph, h, S.q, cP, phiP);
@@ -313,7 +379,7 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
         }
         // north face (top is impermeable)
         if (j + 1 < ny) {
-            FaceFlux f = flux_y(ph, h, S.p, S.c, S.phi, S.K, idx, idx + nx);
+            FaceFlux f = flux_y(ph, h, S.p, S.c, S.ty[idx], S.wy[idx], idx, idx + nx);
             Rp += f.M; Rc += f.F;
             if (mode == 0) L0.tn[idx] = (T)f.lam;
             else { L0.my[idx] = (T)f.M; L0.dy[idx] = (T)f.dif; }
@@ -323,11 +389,11 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
         }
         // south face (bottom is impermeable)
         if (j > 0) {
-            FaceFlux f = flux_y(ph, h, S.p, S.c, S.phi, S.K, idx - nx, idx);
+            FaceFlux f = flux_y(ph, h, S.p, S.c, S.ty[idx - nx], S.wy[idx - nx], idx - nx, idx);
             Rp -= f.M; Rc -= f.F;
         }
         if (mode == 1) L0.acc[idx] = (T)(h2t * phiP * rN);
-        const double sc = S.tau / (h * h * phiP * ph.rho0);
+        const double sc = S.isc[idx];
         if (mode == 0) {
             S.Rp[idx] = Rp;
             L0.b[idx] = (T)(-Rp);
@@ -352,8 +418,9 @@ __device__ void coarsen_pressure(Solve<T>& S) {
         const Level<T>& F = S.lv[l - 1];
         Level<T>& C = S.lv[l];
         const int nc = C.nx * C.ny;
+        const int sx = log2i(C.nx);
         for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
-            const int I = idx % C.nx, J = idx / C.nx;
+            const int I = idx & (C.nx - 1), J = idx >> sx;
             const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
             C.te[idx] = (T)0.5 * (F.te[f0 + 1] + F.te[f1 + 1]);
             C.tn[idx] = (T)0.5 * (F.tn[f1] + F.tn[f1 + 1]);
@@ -368,8 +435,9 @@ __device__ void coarsen_transport(Solve<T>& S) {
         const Level<T>& F = S.lv[l - 1];
         Level<T>& C = S.lv[l];
         const int nc = C.nx * C.ny;
+        const int sx = log2i(C.nx);
         for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
-            const int I = idx % C.nx, J = idx / C.nx;
+            const int I = idx & (C.nx - 1), J = idx >> sx;
             const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
             C.acc[idx] = (F.acc[f0] + F.acc[f0 + 1]) + (F.acc[f1] + F.acc[f1 + 1]);
             // mass fluxes through the two fine faces add; diffusion
@@ -392,18 +460,32 @@ __device__ void coarsen_transport(Solve<T>& S) {
 // ------------------------------------------------------------------ stencils
 // Pressure: (A x)_P = diag x_P - sum_nb t_nb x_nb; te of the last column is
 // the seawater Dirichlet coefficient (diagonal only); tn of the top row is 0.
+// The operations below load every operand from a clamped (always valid)
+// index and zero the missing neighbours afterwards: loads under boundary
+// branches would each wait for their own round trip.
 template <typename T>
 struct Stencil { T d, w, e, s, n; };
 
-template <typename T>
-__device__ inline Stencil<T> pstencil(const Level<T>& v, int i, int j) {
-    const int idx = j * v.nx + i;
+// Neighbour indices of (i, j), clamped to the cell itself at the boundary.
+struct Nb {
+    int idx, w, e, s, n;
+    bool hw, he, hs, hn;
+    __device__ Nb(int i, int j, int nx, int ny) {
+        idx = j * nx + i;
+        hw = i > 0; he = i + 1 < nx; hs = j > 0; hn = j + 1 < ny;
+        w = hw ? idx - 1 : idx; e = he ? idx + 1 : idx;
+        s = hs ? idx - nx : idx; n = hn ? idx + nx : idx;
+    }
+};
+
+template <class V, typename T = typename V::value_type>
+__device__ inline Stencil<T> pstencil(const V& v, const Nb& q) {
     Stencil<T> st;
-    const T te = v.te[idx];
-    st.e = (i + 1 < v.nx) ? te : (T)0;
-    st.w = (i > 0) ? v.te[idx - 1] : (T)0;
-    st.n = v.tn[idx];
-    st.s = (j > 0) ? v.tn[idx - v.nx] : (T)0;
+    const T te = v.te[q.idx], tw = v.te[q.w], tn = v.tn[q.idx], ts = v.tn[q.s];
+    st.e = q.he ? te : (T)0;
+    st.w = q.hw ? tw : (T)0;
+    st.n = tn;
+    st.s = q.hs ? ts : (T)0;
     st.d = te + st.w + st.n + st.s;
     return st;
 }
@@ -415,81 +497,55 @@ __device__ inline Stencil<T> pstencil(const Level<T>& v, int i, int j) {
 template <typename T>
 __device__ inline T pos(T a) { return a > (T)0 ? a : (T)0; }
 
-template <typename T>
-__device__ inline Stencil<T> cstencil(const Level<T>& v, int i, int j) {
-    const int idx = j * v.nx + i;
+template <class V, typename T = typename V::value_type>
+__device__ inline Stencil<T> cstencil(const V& v, const Nb& q, int j) {
     Stencil<T> st;
-    T d = v.acc[idx];
-    if (i + 1 < v.nx) {
-        st.e = pos(-v.mx[idx]) + v.dx[idx];
-        d += st.e;
-    } else {
-        st.e = (T)0;
-        d += pos(-v.mr[j]) + v.dr[j];
-    }
-    if (i > 0) {
-        st.w = pos(v.mx[idx - 1]) + v.dx[idx - 1];
-        d += st.w;
-    } else {
-        st.w = (T)0;
-        d += v.dl[j] + v.ml[j];
-    }
-    if (j + 1 < v.ny) {
-        st.n = pos(-v.my[idx]) + v.dy[idx];
-        d += st.n;
-    } else st.n = (T)0;
-    if (j > 0) {
-        st.s = pos(v.my[idx - v.nx]) + v.dy[idx - v.nx];
-        d += st.s;
-    } else st.s = (T)0;
+    const T a = v.acc[q.idx];
+    const T mE = v.mx[q.idx], dE = v.dx[q.idx], mW = v.mx[q.w], dW = v.dx[q.w];
+    const T mN = v.my[q.idx], dN = v.dy[q.idx], mS = v.my[q.s], dS = v.dy[q.s];
+    const T bE = pos(-v.mr[j]) + v.dr[j], bW = v.dl[j] + v.ml[j];
+    T d = a;
+    st.e = q.he ? pos(-mE) + dE : (T)0;
+    d += q.he ? st.e : bE;
+    st.w = q.hw ? pos(mW) + dW : (T)0;
+    d += q.hw ? st.w : bW;
+    st.n = q.hn ? pos(-mN) + dN : (T)0;
+    d += st.n;
+    st.s = q.hs ? pos(mS) + dS : (T)0;
+    d += st.s;
     st.d = d;
     return st;
 }
 
 // Transpose of the transport operator (adjoint solves): a cell couples to
 // a neighbour with that neighbour's coupling to it; the diagonal is the same.
-template <typename T>
-__device__ inline Stencil<T> cstencil_t(const Level<T>& v, int i, int j) {
-    const int idx = j * v.nx + i;
+template <class V, typename T = typename V::value_type>
+__device__ inline Stencil<T> cstencil_t(const V& v, const Nb& q, int j) {
     Stencil<T> st;
-    T d = v.acc[idx];
-    if (i + 1 < v.nx) {
-        const T M = v.mx[idx], D = v.dx[idx];
-        d += pos(-M) + D;
-        st.e = pos(M) + D;
-    } else {
-        st.e = (T)0;
-        d += pos(-v.mr[j]) + v.dr[j];
-    }
-    if (i > 0) {
-        const T M = v.mx[idx - 1], D = v.dx[idx - 1];
-        d += pos(M) + D;
-        st.w = pos(-M) + D;
-    } else {
-        st.w = (T)0;
-        d += v.dl[j] + v.ml[j];
-    }
-    if (j + 1 < v.ny) {
-        const T M = v.my[idx], D = v.dy[idx];
-        d += pos(-M) + D;
-        st.n = pos(M) + D;
-    } else st.n = (T)0;
-    if (j > 0) {
-        const T M = v.my[idx - v.nx], D = v.dy[idx - v.nx];
-        d += pos(M) + D;
-        st.s = pos(-M) + D;
-    } else st.s = (T)0;
+    const T a = v.acc[q.idx];
+    const T mE = v.mx[q.idx], dE = v.dx[q.idx], mW = v.mx[q.w], dW = v.dx[q.w];
+    const T mN = v.my[q.idx], dN = v.dy[q.idx], mS = v.my[q.s], dS = v.dy[q.s];
+    const T bE = pos(-v.mr[j]) + v.dr[j], bW = v.dl[j] + v.ml[j];
+    T d = a;
+    d += q.he ? pos(-mE) + dE : bE;
+    st.e = q.he ? pos(mE) + dE : (T)0;
+    d += q.hw ? pos(mW) + dW : bW;
+    st.w = q.hw ? pos(-mW) + dW : (T)0;
+    d += q.hn ? pos(-mN) + dN : (T)0;
+    st.n = q.hn ? pos(mN) + dN : (T)0;
+    d += q.hs ? pos(mS) + dS : (T)0;
+    st.s = q.hs ? pos(-mS) + dS : (T)0;
     st.d = d;
     return st;
 }
 
-template <typename T, bool kTransport, bool kTrans = false>
-__device__ inline Stencil<T> stencil(const Level<T>& v, int i, int j) {
+template <typename T, bool kTransport, bool kTrans = false, class V>
+__device__ inline Stencil<T> stencil(const V& v, const Nb& q, int j) {
     if constexpr (kTransport) {
-        if constexpr (kTrans) return cstencil_t(v, i, j);
-        else return cstencil(v, i, j);
+        if constexpr (kTrans) return cstencil_t(v, q, j);
+        else return cstencil(v, q, j);
     } else {
-        return pstencil(v, i, j);
+        return pstencil(v, q);
     }
 }
 
@@ -497,11 +553,14 @@ __device__ inline Stencil<T> stencil(const Level<T>& v, int i, int j) {
 // Prolongation: bilinear with constant extrapolation at the boundary,
 // x_f += P x_c.  Restriction is its exact transpose (full weighting with
 // weights (1,3,3,1)/4 per direction, boundary weights folded in).
-template <typename T>
-__device__ void prolong_add(const Level<T>& C, Level<T>& F) {
+template <typename T, class Team = BlockTeam, int ASC = 0, int ASF = 0>
+__device__ void prolong_add(const Level<T>& C0, Level<T>& F0) {
+    const LV<T, ASC> C(C0);
+    const LV<T, ASF> F(F0);
     const int n = F.nx * F.ny;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int i = idx % F.nx, j = idx / F.nx;
+    const int sx = log2i(F.nx);
+    for (int idx = Team::rank(); idx < n; idx += Team::size()) {
+        const int i = idx & (F.nx - 1), j = idx >> sx;
         const int I = i >> 1, J = j >> 1;
         const int In = (i & 1) ? min(I + 1, C.nx - 1) : max(I - 1, 0);
         const int Jn = (j & 1) ? min(J + 1, C.ny - 1) : max(J - 1, 0);
@@ -520,52 +579,75 @@ __device__ inline float rweight(int I, int n, int a) {
     return w;
 }
 
-template <typename T>
-__device__ void restrict_residual(const Level<T>& F, Level<T>& C) {
+template <typename T, class Team = BlockTeam, int ASF = 0, int ASC = 0>
+__device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
+    const LV<T, ASF> F(F0);
+    const LV<T, ASC> C(C0);
     const int n = C.nx * C.ny;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int I = idx % C.nx, J = idx / C.nx;
+    const int sx = log2i(C.nx);
+    for (int idx = Team::rank(); idx < n; idx += Team::size()) {
+        const int I = idx & (C.nx - 1), J = idx >> sx;
+        // fine rows / columns outside the level get weight 0 (their load is
+        // clamped to a valid cell)
+        T rv[4][4];
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) {
+            const int jf = min(max(2 * J - 1 + bq, 0), F.ny - 1);
+#pragma unroll
+            for (int aq = 0; aq < 4; ++aq) {
+                const int ifn = min(max(2 * I - 1 + aq, 0), F.nx - 1);
+                rv[bq][aq] = F.r[jf * F.nx + ifn];
+            }
+        }
         T s = (T)0;
 #pragma unroll
         for (int bq = 0; bq < 4; ++bq) {
             const int jf = 2 * J - 1 + bq;
-            if (jf < 0 || jf >= F.ny) continue;
+            const T wb = (jf < 0 || jf >= F.ny) ? (T)0 : (T)rweight(J, C.ny, bq);
             T row = (T)0;
 #pragma unroll
             for (int aq = 0; aq < 4; ++aq) {
                 const int ifn = 2 * I - 1 + aq;
-                if (ifn < 0 || ifn >= F.nx) continue;
-                row += (T)rweight(I, C.nx, aq) * F.r[jf * F.nx + ifn];
+                const T wa = (ifn < 0 || ifn >= F.nx) ? (T)0 : (T)rweight(I, C.nx, aq);
+                row += wa * rv[bq][aq];
             }
-            s += (T)rweight(J, C.ny, bq) * row;
+            s += wb * row;
         }
         C.b[idx] = s;
         C.x[idx] = (T)0;
     }
 }
 
-// r = b - A x on one level (operands of kBatch cells gathered first).
-template <typename T, bool kTransport, bool kTrans = false>
-__device__ void level_residual(Level<T>& v) {
+// r = b - A x on one level (operands of kRBatch cells gathered first).
+constexpr int kRBatch = 2;
+template <typename T, bool kTransport, bool kTrans = false, class Team = BlockTeam, int AS = 0>
+__device__ void level_residual(Level<T>& v0) {
+    const LV<T, AS> v(v0);
     const int n = v.nx * v.ny;
-    for (int k0 = threadIdx.x; k0 < n; k0 += 4 * blockDim.x) {
-        T res[4];
+    const int ts = Team::size();
+    const int sx = log2i(v.nx);
+    for (int k0 = Team::rank(); k0 < n; k0 += kRBatch * ts) {
+        T res[kRBatch];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * blockDim.x;
+        for (int u = 0; u < kRBatch; ++u) {
+            const int k = k0 + u * ts;
             const int idx = k < n ? k : 0;
-            const int i = idx % v.nx, j = idx / v.nx;
-            const Stencil<T> st = stencil<T, kTransport, kTrans>(v, i, j);
-            T ax = st.d * v.x[idx];
-            if (i > 0) ax -= st.w * v.x[idx - 1];
-            if (i + 1 < v.nx) ax -= st.e * v.x[idx + 1];
-            if (j > 0) ax -= st.s * v.x[idx - v.nx];
-            if (j + 1 < v.ny) ax -= st.n * v.x[idx + v.nx];
-            res[u] = v.b[idx] - ax;
+            const int i = idx & (v.nx - 1), j = idx >> sx;
+            const Nb q(i, j, v.nx, v.ny);
+            const Stencil<T> st = stencil<T, kTransport, kTrans>(v, q, j);
+            const T xP = v.x[idx], xW = v.x[q.w], xE = v.x[q.e], xS = v.x[q.s], xN = v.x[q.n];
+            const T bP = v.b[idx];
+            // missing neighbours have zero couplings
+            T ax = st.d * xP;
+            ax -= st.w * xW;
+            ax -= st.e * xE;
+            ax -= st.s * xS;
+            ax -= st.n * xN;
+            res[u] = bP - ax;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (k0 + u * (int)blockDim.x < n) v.r[k0 + u * blockDim.x] = res[u];
+        for (int u = 0; u < kRBatch; ++u)
+            if (k0 + u * ts < n) v.r[k0 + u * ts] = res[u];
     }
 }
 
@@ -575,45 +657,48 @@ __device__ void level_residual(Level<T>& v) {
 // before it writes any of them, so their loads are in flight together.
 constexpr int kBatch = 4;
 
-template <typename T>
-__device__ void rbgs(Level<T>& v, int sweeps) {
+template <typename T, class Team = BlockTeam, int AS = 0>
+__device__ void rbgs(Level<T>& v0, int sweeps) {
+    const LV<T, AS> v(v0);
     const int nx = v.nx, ny = v.ny;
     const int half = nx >> 1;  // nx is even on every level
+    const int sh = log2i(half);
     const int m = half * ny;
-    const T* te = v.te;
-    const T* tn = v.tn;
-    const T* b = v.b;
-    T* x = v.x;
+    const auto te = v.te;
+    const auto tn = v.tn;
+    const auto b = v.b;
+    const auto x = v.x;
     for (int s = 0; s < sweeps; ++s)
         for (int col = 0; col < 2; ++col) {
-            for (int k0 = threadIdx.x; k0 < m; k0 += kBatch * blockDim.x) {
+            for (int k0 = Team::rank(); k0 < m; k0 += kBatch * Team::size()) {
                 T num[kBatch], den[kBatch];
                 int at[kBatch];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    const int k = k0 + u * blockDim.x;
+                    const int k = k0 + u * Team::size();
                     const int kk = k < m ? k : 0;
-                    const int j = kk / half;
-                    const int i = 2 * (kk - j * half) + ((j + col) & 1);
-                    const int idx = j * nx + i;
-                    at[u] = k < m ? idx : -1;
-                    const T tE = te[idx];
-                    const T tW = (i > 0) ? te[idx - 1] : (T)0;
-                    const T tN = tn[idx];
-                    const T tS = (j > 0) ? tn[idx - nx] : (T)0;
-                    T a = b[idx];
-                    if (i > 0) a += tW * x[idx - 1];
-                    if (i + 1 < nx) a += tE * x[idx + 1];
-                    if (j > 0) a += tS * x[idx - nx];
-                    if (j + 1 < ny) a += tN * x[idx + nx];
+                    const int j = kk >> sh;
+                    const int i = 2 * (kk & (half - 1)) + ((j + col) & 1);
+                    const Nb q(i, j, nx, ny);
+                    at[u] = k < m ? q.idx : -1;
+                    const T tE = te[q.idx], tWl = te[q.w], tN = tn[q.idx], tSl = tn[q.s];
+                    const T xW = x[q.w], xE = x[q.e], xS = x[q.s], xN = x[q.n];
+                    const T bP = b[q.idx];
+                    const T tW = q.hw ? tWl : (T)0, tS = q.hs ? tSl : (T)0;
+                    const T tEc = q.he ? tE : (T)0;  // the seawater coefficient is diagonal only
+                    T a = bP;
+                    a += tW * xW;
+                    a += tEc * xE;
+                    a += tS * xS;
+                    a += tN * xN;
                     num[u] = a;
                     den[u] = tE + tW + tN + tS;
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u)
-                    if (at[u] >= 0) x[at[u]] = num[u] / den[u];
+                    if (at[u] >= 0) x[at[u]] = qdiv(num[u], den[u]);
             }
-            __syncthreads();
+            Team::sync();
         }
 }
 
@@ -627,21 +712,23 @@ __device__ void rbgs(Level<T>& v, int sweeps) {
 // reduction across the T lanes with wavefront shuffles, then every lane
 // back-substitutes its interior rows.  All coefficients live in registers;
 // a colour of lines is one block-wide phase.
-// MS = rows per lane (a power of two); line lengths are powers of two, so
-// m = MS = max(2, len/64) rows and TL = len/m <= 64 lanes per line.
-template <typename T, bool kXLine, bool kTrans, int MS>
-__device__ void line_sweep_m(Level<T>& v, int col) {
+// MS = rows per lane (a power of two, 2 or 4, chosen by line_sweep); line
+// lengths are powers of two, so TL = len/MS <= 64 lanes per line.
+template <typename T, bool kXLine, bool kTrans, int MS, class Team, int AS>
+__device__ void line_sweep_m(Level<T>& v0, int col) {
+    const LV<T, AS> v(v0);
     const int len = kXLine ? v.nx : v.ny;
     const int other = kXLine ? v.ny : v.nx;
     const int nlines = (other - col + 1) >> 1;
     const int m = MS;                   // rows per lane
     const int TL = len / m;             // lanes per line
+    const int stl = log2i(TL);
     const int lane = threadIdx.x & (kWave - 1);
     const int t = lane & (TL - 1);
     const int need = nlines * TL;
-    for (int base = 0; base < need; base += blockDim.x) {
-        const int g = base + threadIdx.x;
-        const int li = g / TL;
+    for (int base = 0; base < need; base += Team::size()) {
+        const int g = base + Team::rank();
+        const int li = g >> stl;
         const bool active = li < nlines;
         const int fixed = col + 2 * (active ? li : 0);
         T cp[MS], y[MS], u[MS], w[MS];
@@ -652,22 +739,25 @@ __device__ void line_sweep_m(Level<T>& v, int col) {
             if (q < m) {
                 const int k = t * m + q;
                 const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
-                const int idx = j * v.nx + i;
-                const Stencil<T> st = stencil<T, true, kTrans>(v, i, j);
-                T rhs = v.b[idx];
+                const Nb nb(i, j, v.nx, v.ny);
+                const Stencil<T> st = stencil<T, true, kTrans>(v, nb, j);
+                T rhs = v.b[nb.idx];
                 T a, c;
+                // off-line neighbours; missing ones have zero couplings
                 if (kXLine) {
-                    if (j > 0) rhs += st.s * v.x[idx - v.nx];
-                    if (j + 1 < v.ny) rhs += st.n * v.x[idx + v.nx];
+                    const T xS = v.x[nb.s], xN = v.x[nb.n];
+                    rhs += st.s * xS;
+                    rhs += st.n * xN;
                     a = -st.w; c = -st.e;
                 } else {
-                    if (i > 0) rhs += st.w * v.x[idx - 1];
-                    if (i + 1 < v.nx) rhs += st.e * v.x[idx + 1];
+                    const T xW = v.x[nb.w], xE = v.x[nb.e];
+                    rhs += st.w * xW;
+                    rhs += st.e * xE;
                     a = -st.s; c = -st.n;
                 }
                 if (q < m - 1) {
                     const T den = (q > 0) ? st.d - a * cp[q > 0 ? q - 1 : 0] : st.d;
-                    const T inv = (T)1 / den;
+                    const T inv = qdiv((T)1, den);
                     const T yprev = (q > 0) ? y[q > 0 ? q - 1 : 0] : (T)0;
                     const T uprev = (q > 0) ? u[q > 0 ? q - 1 : 0] : (T)0;
                     const T wprev = (q > 0) ? w[q > 0 ? q - 1 : 0] : (T)0;
@@ -716,20 +806,20 @@ __device__ void line_sweep_m(Level<T>& v, int col) {
                     Dr = __shfl(D, r, kWave);
             T nA = (T)0, nB = B, nC = (T)0, nD = D;
             if (hasL) {
-                const T k1 = A / Bl;
+                const T k1 = qdiv(A, Bl);
                 nA = -Al * k1;
                 nB -= Cl * k1;
                 nD -= Dl * k1;
             }
             if (hasR) {
-                const T k2 = C / Br;
+                const T k2 = qdiv(C, Br);
                 nC = -Cr * k2;
                 nB -= Ar * k2;
                 nD -= Dr * k2;
             }
             A = nA; B = nB; C = nC; D = nD;
         }
-        const T iota = D / B;
+        const T iota = qdiv(D, B);
         const T left0 = __shfl(iota, t > 0 ? lane - 1 : lane, kWave);
         const T left = t > 0 ? left0 : (T)0;
         if (active) {
@@ -743,78 +833,45 @@ __device__ void line_sweep_m(Level<T>& v, int col) {
             }
         }
     }
-    __syncthreads();
+    Team::sync();
 }
 
-template <typename T, bool kXLine, bool kTrans = false>
+// Rows per lane: x-lines take the fewest rows that fit a line in one
+// wavefront; y-lines of 64 rows or more take four, so that a wavefront holds
+// two or more neighbouring columns and each of its loads touches half as many
+// (or fewer) cache lines as with one column of strided rows.
+template <typename T, bool kXLine, bool kTrans = false, class Team = BlockTeam, int AS = 0>
 __device__ void line_sweep(Level<T>& v, int col) {
     const int len = kXLine ? v.nx : v.ny;  // 2 .. 256, a power of two
-    if (len <= 128) line_sweep_m<T, kXLine, kTrans, 2>(v, col);
-    else line_sweep_m<T, kXLine, kTrans, 4>(v, col);
+    if (len > 128 || (!kXLine && len >= 64)) line_sweep_m<T, kXLine, kTrans, 4, Team, AS>(v, col);
+    else line_sweep_m<T, kXLine, kTrans, 2, Team, AS>(v, col);
 }
 
 // One zebra sweep in one direction: x-lines (even rows, then odd rows) or
 // y-lines (even columns, then odd columns; a one-row level has only its
 // x-line).  The transport V-cycle pre-smooths with x-lines and post-smooths
 // with y-lines, so every cycle relaxes along both directions.
-template <typename T, bool kTrans = false>
+template <typename T, bool kTrans = false, class Team = BlockTeam, int AS = 0>
 __device__ void line_smooth(Level<T>& v, bool ylines) {
     if (ylines && v.ny > 1) {
-        line_sweep<T, false, kTrans>(v, 0);
-        line_sweep<T, false, kTrans>(v, 1);
+        line_sweep<T, false, kTrans, Team, AS>(v, 0);
+        line_sweep<T, false, kTrans, Team, AS>(v, 1);
     } else {
-        line_sweep<T, true, kTrans>(v, 0);
-        line_sweep<T, true, kTrans>(v, 1);
+        line_sweep<T, true, kTrans, Team, AS>(v, 0);
+        line_sweep<T, true, kTrans, Team, AS>(v, 1);
     }
 }
 
-// ------------------------------------------------------------------ V-cycles
-// The coarsest level of every hierarchy has one row (ny = 1, nx = 2): the
-// system is a single x-line, solved exactly.
-template <typename T, bool kTransport, bool kTrans = false>
-__device__ void vcycle(Solve<T>& S) {
-    const int L = S.L;
-    for (int l = 0; l < L - 1; ++l) {
-        Level<T>& v = S.lv[l];
-        if constexpr (kTransport) line_smooth<T, kTrans>(v, false);
-        else rbgs(v, 2);
-        level_residual<T, kTransport, kTrans>(v);
-        __syncthreads();
-        restrict_residual(v, S.lv[l + 1]);
-        __syncthreads();
-    }
-    {
-        Level<T>& v = S.lv[L - 1];
-        if constexpr (kTransport) line_sweep<T, true, kTrans>(v, 0);
-        else {
-            // pressure coarsest (2 x 1 cells): direct solve of the 2 x 2 system
-            if (threadIdx.x == 0) {
-                const Stencil<T> s0 = pstencil(v, 0, 0), s1 = pstencil(v, 1, 0);
-                const T det = s0.d * s1.d - s0.e * s1.w;
-                v.x[0] = (v.b[0] * s1.d + s0.e * v.b[1]) / det;
-                v.x[1] = (s0.d * v.b[1] + s1.w * v.b[0]) / det;
-            }
-            __syncthreads();
-        }
-    }
-    for (int l = L - 2; l >= 0; --l) {
-        Level<T>& v = S.lv[l];
-        prolong_add(S.lv[l + 1], v);
-        __syncthreads();
-        if constexpr (kTransport) line_smooth<T, kTrans>(v, true);
-        else rbgs(v, 2);
-    }
-}
-
-// ------------------------------------------------------------------ one implicit step
 // Wall-clock accumulators of the phases of one step (builds with
 // HENRY_PHASE_TIMERS only; wall_clock64 runs at a constant 100 MHz).
+// Slots 0..7: phases of the outer iteration; 8..14 and 16..22: parts of
+// the pressure and of the transport V-cycle.
 struct PhaseClock {
 #ifdef HENRY_PHASE_TIMERS
-    uint64_t acc[8];
+    uint64_t acc[24];
     uint64_t last;
     __device__ void init() {
-        for (int k = 0; k < 8; ++k) acc[k] = 0;
+        for (int k = 0; k < 24; ++k) acc[k] = 0;
         last = wall_clock64();
     }
     __device__ void tick(int k) {
@@ -827,6 +884,77 @@ struct PhaseClock {
     __device__ void tick(int) {}
 #endif
 };
+
+// ------------------------------------------------------------------ V-cycles
+// Downward leg on level l (address space AS; level l+1 in ASN): smooth,
+// residual, restriction to level l+1.
+template <typename T, bool kTransport, bool kTrans, class Team, int AS, int ASN>
+__device__ void vdown(Solve<T>& S, int l) {
+    Level<T>& v = S.lv[l];
+    if constexpr (kTransport) line_smooth<T, kTrans, Team, AS>(v, false);
+    else rbgs<T, Team, AS>(v, 2);
+    level_residual<T, kTransport, kTrans, Team, AS>(v);
+    Team::sync();
+    restrict_residual<T, Team, AS, ASN>(v, S.lv[l + 1]);
+    Team::sync();
+}
+
+// Upward leg on level l: prolongation from level l+1, smooth.
+template <typename T, bool kTransport, bool kTrans, class Team, int AS, int ASN>
+__device__ void vup(Solve<T>& S, int l) {
+    Level<T>& v = S.lv[l];
+    prolong_add<T, Team, ASN, AS>(S.lv[l + 1], v);
+    Team::sync();
+    if constexpr (kTransport) line_smooth<T, kTrans, Team, AS>(v, true);
+    else rbgs<T, Team, AS>(v, 2);
+}
+
+// The coarsest level of every hierarchy has one row (ny = 1, nx = 2): the
+// system is a single x-line, solved exactly.
+template <typename T, bool kTransport, bool kTrans, class Team, int AS>
+__device__ void vcoarsest(Solve<T>& S) {
+    if constexpr (kTransport) line_sweep<T, true, kTrans, Team, AS>(S.lv[S.L - 1], 0);
+    else {
+        const LV<T, AS> v(S.lv[S.L - 1]);
+        // pressure coarsest (2 x 1 cells): direct solve of the 2 x 2 system
+        if (Team::rank() == 0) {
+            const Stencil<T> s0 = pstencil(v, Nb(0, 0, 2, 1)), s1 = pstencil(v, Nb(1, 0, 2, 1));
+            const T det = s0.d * s1.d - s0.e * s1.w;
+            v.x[0] = (v.b[0] * s1.d + s0.e * v.b[1]) / det;
+            v.x[1] = (s0.d * v.b[1] + s1.w * v.b[0]) / det;
+        }
+        Team::sync();
+    }
+}
+
+// One V-cycle.  Levels in global memory are run by the whole workgroup;
+// from the first level in LDS (S.lds_from; the coarsest level always is)
+// down to the coarsest and back, wavefront 0 runs the cycle alone while the
+// other wavefronts wait at one barrier.
+template <typename T, bool kTransport, bool kTrans = false>
+__device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr) {
+    const int L = S.L;
+    const int lw = S.lds_from;
+    const int t0 = kTransport ? 16 : 8;
+    if (pc) pc->tick(kTransport ? 4 : 1);
+    for (int l = 0; l < lw; ++l) {
+        if (l + 1 < lw) vdown<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
+        else vdown<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+        if (pc) pc->tick(t0 + (l == 0 ? 1 : 2));
+    }
+    if (threadIdx.x < kWave) {
+        for (int l = lw; l < L - 1; ++l) vdown<T, kTransport, kTrans, WaveTeam, 3, 3>(S, l);
+        vcoarsest<T, kTransport, kTrans, WaveTeam, 3>(S);
+        for (int l = L - 2; l >= lw; --l) vup<T, kTransport, kTrans, WaveTeam, 3, 3>(S, l);
+    }
+    __syncthreads();
+    if (pc) pc->tick(t0 + 3);
+    for (int l = lw - 1; l >= 0; --l) {
+        if (l + 1 < lw) vup<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
+        else vup<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+        if (pc) pc->tick(t0 + (l == 0 ? 6 : 4));
+    }
+}
 
 // One implicit Euler step (Sec. 2.3) from the state in S.p, S.c: saves c^n
 // in S.cn (and p^n in S.pp) and runs the defect correction until both
@@ -859,7 +987,7 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
         iters += 1.0;
         coarsen_pressure(S);
         pc.tick(1);
-        vcycle<T, false>(S);
+        vcycle<T, false>(S, &pc);
         pc.tick(2);
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.p[idx] += (double)S.lv[0].x[idx];
         __syncthreads();
@@ -867,7 +995,7 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
         pc.tick(3);
         coarsen_transport(S);
         pc.tick(4);
-        vcycle<T, true>(S);
+        vcycle<T, true>(S, &pc);
         pc.tick(5);
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.c[idx] += (double)S.lv[0].x[idx];
         __syncthreads();
@@ -899,7 +1027,7 @@ __device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
 
 // ------------------------------------------------------------------ the solve kernel
 template <typename T>
-__global__ void __launch_bounds__(512) henry_solve_kernel(Launch lp) {
+__global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kernel(Launch lp) {
     extern __shared__ __align__(256) uint8_t lds_levels[];
     __shared__ Solve<T> S;
     __shared__ double red[16];
@@ -937,7 +1065,7 @@ __global__ void __launch_bounds__(512) henry_solve_kernel(Launch lp) {
         sp[1] = (double)status;
         sp[2] = iters;
 #ifdef HENRY_PHASE_TIMERS
-        for (int k = 0; k < 8; ++k) sp[8 + k] = (double)pc.acc[k];
+        for (int k = 0; k < 24; ++k) sp[8 + k] = (double)pc.acc[k];
 #endif
     }
     if (s_end == d.nsteps) {
@@ -998,6 +1126,35 @@ __global__ void henry_fields_kernel(Launch lp) {
             K[idx] = exp(lp.logk_in[d.field_off + idx]);
         }
         if (threadIdx.x == 0) sp[0] = lp.qin_in[d.index];
+    }
+    __syncthreads();
+    // face coefficients (harmonic means) and the residual scale
+    double* tx = f + 8 * n;
+    double* ty = f + 9 * n;
+    double* wx = f + 10 * n;
+    double* wy = f + 11 * n;
+    double* isc = f + 12 * n;
+    const double tau = ph.T / d.nsteps;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const int i = idx % nx, j = idx / nx;
+        const double KP = K[idx], fP = phi[idx];
+        if (i + 1 < nx) {
+            const double KE = K[idx + 1], fE = phi[idx + 1];
+            tx[idx] = 2.0 * KP * KE / (KP + KE) / ph.mu;
+            wx[idx] = 2.0 * fP * fE / (fP + fE) * ph.D;
+        } else {
+            tx[idx] = 2.0 * KP / ph.mu;
+            wx[idx] = 2.0 * fP * ph.D;
+        }
+        if (j + 1 < ny) {
+            const double KN = K[idx + nx], fN = phi[idx + nx];
+            ty[idx] = 2.0 * KP * KN / (KP + KN) / ph.mu;
+            wy[idx] = 2.0 * fP * fN / (fP + fN) * ph.D;
+        } else {
+            ty[idx] = 0.0;
+            wy[idx] = 0.0;
+        }
+        isc[idx] = tau / (h * h * fP * ph.rho0);
     }
 }
 

@@ -249,11 +249,12 @@ def test_autotune_picks_a_candidate_and_threads_do_not_change_the_solution(torch
     xi = torch.tensor(hm.henry_sample_xi(0, 1, 0, len(solves), 3), dtype=torch.float64, device="cuda")
     res = hm.autotune(ctx, solves, xi, hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60), tune_steps=4)
     for (nx, prec), (t, times) in res.items():
-        assert t in (64, 128, 256, 512) and hm.henry_tune_get(ctx, nx, prec) == t
+        assert t in (64, 128, 256, 512, 1024) and hm.henry_tune_get(ctx, nx, prec) == t
     outs = [hm.solve(ctx, solves, xi=xi, opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60,
-                                                           threads=t)) for t in (64, 256)]
+                                                           threads=t)) for t in (64, 256, 1024)]
     torch.cuda.synchronize()
-    assert torch.equal(outs[0]["c"], outs[1]["c"])
-    assert torch.allclose(outs[0]["qoi"], outs[1]["qoi"], rtol=1e-14, atol=0)
+    for o in outs[1:]:
+        assert torch.equal(outs[0]["c"], o["c"])
+        assert torch.allclose(outs[0]["qoi"], o["qoi"], rtol=1e-14, atol=0)
     for nx in (16, 32):
         hm.henry_tune_set(ctx, nx, hm.PREC_MIXED, 0)
