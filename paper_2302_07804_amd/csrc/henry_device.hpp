@@ -281,6 +281,18 @@ struct WaveTeam {
     }
 };
 
+// Neighbour indices of (i, j), clamped to the cell itself at the boundary.
+struct Nb {
+    int idx, w, e, s, n;
+    bool hw, he, hs, hn;
+    __device__ Nb(int i, int j, int nx, int ny) {
+        idx = j * nx + i;
+        hw = i > 0; he = i + 1 < nx; hs = j > 0; hn = j + 1 < ny;
+        w = hw ? idx - 1 : idx; e = he ? idx + 1 : idx;
+        s = hs ? idx - nx : idx; n = hn ? idx + nx : idx;
+    }
+};
+
 // ------------------------------------------------------------------ physics (FP64)
 __device__ inline double rho_of(const Phys& ph, double c) { return ph.rho0 + (ph.rho1 - ph.rho0) * c; }
 
@@ -289,27 +301,15 @@ __device__ inline double rho_of(const Phys& ph, double c) { return ph.rho0 + (ph
 // wx = phi_f D), arithmetic rho; donor cell.
 struct FaceFlux { double M, F, lam, dif; };
 
-__device__ inline FaceFlux flux_x(const Phys& ph, const double* p, const double* c, double kf, double wf, int a,
-                                  int b) {
+// Interior face a|b (b east or north of a); `buoy` = 1 on a north face,
+// where Darcy's law with gravity (0,-g) adds rho_f g h, 0 on an east face.
+__device__ inline FaceFlux flux_face(const Phys& ph, double h, double pa, double pb, double ca, double cb, double kf,
+                                     double wf, double buoy) {
     FaceFlux f;
-    const double ca = c[a], cb = c[b];
     const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
     f.lam = rf * kf;
     f.dif = rf * wf;
-    f.M = -f.lam * (p[b] - p[a]);
-    f.F = f.M * (f.M >= 0.0 ? ca : cb) - f.dif * (cb - ca);
-    return f;
-}
-
-// North neighbour: Darcy's law with gravity (0,-g) adds rho_f g h.
-__device__ inline FaceFlux flux_y(const Phys& ph, double h, const double* p, const double* c, double kf, double wf,
-                                  int a, int b) {
-    FaceFlux f;
-    const double ca = c[a], cb = c[b];
-    const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
-    f.lam = rf * kf;
-    f.dif = rf * wf;
-    f.M = -f.lam * ((p[b] - p[a]) + rf * ph.g * h);
+    f.M = -f.lam * ((pb - pa) + buoy * (rf * ph.g * h));
     f.F = f.M * (f.M >= 0.0 ? ca : cb) - f.dif * (cb - ca);
     return f;
 }
@@ -351,55 +351,52 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
     const int sx = log2i(nx);
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
         const int i = idx & (nx - 1), j = idx >> sx;
-        const double cP = S.c[idx], cnP = S.cn[idx], phiP = S.phi[idx];
+        // every operand from a clamped index first (no loads under boundary
+        // branches); both the interior and the boundary flux of a face are
+        // formed and the applicable one selected
+        const Nb q(i, j, nx, ny);
+        const double cP = S.c[idx], cnP = S.cn[idx], phiP = S.phi[idx], pP = S.p[idx];
+        const double cE = S.c[q.e], pE = S.p[q.e], cW = S.c[q.w], pW = S.p[q.w];
+        const double cN = S.c[q.n], pN = S.p[q.n], cS = S.c[q.s], pS = S.p[q.s];
+        const double txP = S.tx[idx], wxP = S.wx[idx], txW = S.tx[q.w], wxW = S.wx[q.w];
+        const double tyP = S.ty[idx], wyP = S.wy[idx], tyS = S.ty[q.s], wyS = S.wy[q.s];
+        const double sc = S.isc[idx];
         const double rP = rho_of(ph, cP), rN = rho_of(ph, cnP);
         double Rp = h2t * phiP * (rP - rN);
         double Rc = h2t * phiP * (rP * cP - rN * cnP);
-        // east face
-        if (i + 1 < nx) {
-            FaceFlux f = flux_x(ph, S.p, S.c, S.tx[idx], S.wx[idx], idx, idx + 1);
-            Rp += f.M; Rc += f.F;
-            if (mode == 0) L0.te[idx] = (T)f.lam;
-            else { L0.mx[idx] = (T)f.M; L0.dx[idx] = (T)f.dif; }
-        } else {
-            const double y = -1.0 + (j + 0.5) * h;
-            FaceFlux f = flux_right(ph, y, S.p[idx], cP, S.tx[idx], S.wx[idx]);
-            Rp += f.M; Rc += f.F;
-            if (mode == 0) L0.te[idx] = (T)f.lam;
-            else { L0.mx[idx] = (T)0; L0.dx[idx] = (T)0; L0.dr[j] = (T)f.dif; L0.mr[j] = (T)f.M; }
-        }
-        // west face
-        if (i > 0) {
-            FaceFlux f = flux_x(ph, S.p, S.c, S.tx[idx - 1], S.wx[idx - 1], idx - 1, idx);
-            Rp -= f.M; Rc -= f.F;
-        } else {
-            FaceFlux f = flux_left(ph, h, S.q, cP, phiP);
-            Rp += f.M; Rc += f.F;
-            if (mode == 1) { L0.dl[j] = (T)f.dif; L0.ml[j] = (T)(-f.M); }
-        }
-        // north face (top is impermeable)
-        if (j + 1 < ny) {
-            FaceFlux f = flux_y(ph, h, S.p, S.c, S.ty[idx], S.wy[idx], idx, idx + nx);
-            Rp += f.M; Rc += f.F;
-            if (mode == 0) L0.tn[idx] = (T)f.lam;
-            else { L0.my[idx] = (T)f.M; L0.dy[idx] = (T)f.dif; }
-        } else {
-            if (mode == 0) L0.tn[idx] = (T)0;
-            else { L0.my[idx] = (T)0; L0.dy[idx] = (T)0; }
-        }
-        // south face (bottom is impermeable)
-        if (j > 0) {
-            FaceFlux f = flux_y(ph, h, S.p, S.c, S.ty[idx - nx], S.wy[idx - nx], idx - nx, idx);
-            Rp -= f.M; Rc -= f.F;
-        }
-        if (mode == 1) L0.acc[idx] = (T)(h2t * phiP * rN);
-        const double sc = S.isc[idx];
+        // east face: interior, or the seawater boundary
+        const FaceFlux fe = flux_face(ph, h, pP, pE, cP, cE, txP, wxP, 0.0);
+        const FaceFlux fr = flux_right(ph, -1.0 + (j + 0.5) * h, pP, cP, txP, wxP);
+        Rp += q.he ? fe.M : fr.M;
+        Rc += q.he ? fe.F : fr.F;
+        // west face: interior (flux out of the west neighbour), or recharge
+        const FaceFlux fw = flux_face(ph, h, pW, pP, cW, cP, txW, wxW, 0.0);
+        const FaceFlux fl = flux_left(ph, h, S.q, cP, phiP);
+        Rp += q.hw ? -fw.M : fl.M;
+        Rc += q.hw ? -fw.F : fl.F;
+        // north face (the top is impermeable)
+        const FaceFlux fn = flux_face(ph, h, pP, pN, cP, cN, tyP, wyP, 1.0);
+        Rp += q.hn ? fn.M : 0.0;
+        Rc += q.hn ? fn.F : 0.0;
+        // south face (the bottom is impermeable)
+        const FaceFlux fs = flux_face(ph, h, pS, pP, cS, cP, tyS, wyS, 1.0);
+        Rp -= q.hs ? fs.M : 0.0;
+        Rc -= q.hs ? fs.F : 0.0;
         if (mode == 0) {
+            L0.te[idx] = (T)(q.he ? fe.lam : fr.lam);
+            L0.tn[idx] = (T)(q.hn ? fn.lam : 0.0);
             S.Rp[idx] = Rp;
             L0.b[idx] = (T)(-Rp);
             L0.x[idx] = (T)0;
             mp = nanmax(mp, fabs(Rp * sc));
         } else {
+            L0.mx[idx] = (T)(q.he ? fe.M : 0.0);
+            L0.dx[idx] = (T)(q.he ? fe.dif : 0.0);
+            L0.my[idx] = (T)(q.hn ? fn.M : 0.0);
+            L0.dy[idx] = (T)(q.hn ? fn.dif : 0.0);
+            if (!q.he) { L0.dr[j] = (T)fr.dif; L0.mr[j] = (T)fr.M; }
+            if (!q.hw) { L0.dl[j] = (T)fl.dif; L0.ml[j] = (T)(-fl.M); }
+            L0.acc[idx] = (T)(h2t * phiP * rN);
             L0.b[idx] = (T)(-(Rc - cP * Rp));
             L0.x[idx] = (T)0;
         }
@@ -466,17 +463,6 @@ __device__ void coarsen_transport(Solve<T>& S) {
 template <typename T>
 struct Stencil { T d, w, e, s, n; };
 
-// Neighbour indices of (i, j), clamped to the cell itself at the boundary.
-struct Nb {
-    int idx, w, e, s, n;
-    bool hw, he, hs, hn;
-    __device__ Nb(int i, int j, int nx, int ny) {
-        idx = j * nx + i;
-        hw = i > 0; he = i + 1 < nx; hs = j > 0; hn = j + 1 < ny;
-        w = hw ? idx - 1 : idx; e = he ? idx + 1 : idx;
-        s = hs ? idx - nx : idx; n = hn ? idx + nx : idx;
-    }
-};
 
 template <class V, typename T = typename V::value_type>
 __device__ inline Stencil<T> pstencil(const V& v, const Nb& q) {
