@@ -98,7 +98,7 @@ constexpr int kAdjMaxThreads = 512;
 
 int check_grid(const henry_grid_t& g) {
     if (g.reserved != 0) return HENRY_EINVAL;
-    if (g.ny < 1 || g.ny > 128 || !pow2(g.ny) || g.nx != 2 * g.ny) return HENRY_EINVAL;
+    if (g.ny < 1 || g.ny > 512 || !pow2(g.ny) || g.nx != 2 * g.ny) return HENRY_EINVAL;
     if (g.nsteps < 1) return HENRY_EINVAL;
     return HENRY_OK;
 }
@@ -558,7 +558,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
 }
 
 int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
-    if (!ctx || nx < 2 || nx > 256 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
+    if (!ctx || nx < 2 || nx > 1024 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
     if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
     if (threads == 0) {
         ctx->tuned_threads.erase((long)nx * 4 + prec);
@@ -578,7 +578,7 @@ int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
 }
 
 int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads) {
-    if (!ctx || !threads || nx < 2 || nx > 256 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
+    if (!ctx || !threads || nx < 2 || nx > 1024 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
     if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
     auto it = ctx->tuned_threads.find((long)nx * 4 + prec);
     *threads = it != ctx->tuned_threads.end() ? it->second : default_threads(nx, nx / 2);

@@ -30,12 +30,14 @@
 // lanes of a wavefront.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace henry {
 
-constexpr int kMaxLevels = 12;  // ny <= 128 -> at most 8 multigrid levels
+constexpr int kMaxLevels = 12;  // ny <= 512 -> at most 10 multigrid levels
 constexpr int kWave = 64;
 
 struct Phys {
@@ -700,8 +702,10 @@ __device__ void rbgs(Level<T>& v0, int sweeps) {
 // a colour of lines is one block-wide phase.
 // MS = rows per lane (a power of two, 2 or 4, chosen by line_sweep); line
 // lengths are powers of two, so TL = len/MS <= 64 lanes per line.
+// Each instantiation is its own function, so the register budget of the
+// long-line variants does not weigh on the short ones.
 template <typename T, bool kXLine, bool kTrans, int MS, class Team, int AS>
-__device__ void line_sweep_m(Level<T>& v0, int col) {
+__device__ __attribute__((noinline)) void line_sweep_m(Level<T>& v0, int col) {
     const LV<T, AS> v(v0);
     const int len = kXLine ? v.nx : v.ny;
     const int other = kXLine ? v.ny : v.nx;
@@ -822,15 +826,27 @@ __device__ void line_sweep_m(Level<T>& v0, int col) {
     Team::sync();
 }
 
-// Rows per lane: x-lines take the fewest rows that fit a line in one
-// wavefront; y-lines of 64 rows or more take four, so that a wavefront holds
-// two or more neighbouring columns and each of its loads touches half as many
-// (or fewer) cache lines as with one column of strided rows.
+// Rows per lane: x-lines take the fewest rows (at least two) that fit a
+// line in one wavefront; y-lines of 64 to 256 rows take four, so that a
+// wavefront holds two or more neighbouring columns and each of its loads
+// touches half as many (or fewer) cache lines as with one column of strided
+// rows.  The wavefront-team levels (at most 512 cells) have lines of at most
+// 32 cells: two rows per lane.
 template <typename T, bool kXLine, bool kTrans = false, class Team = BlockTeam, int AS = 0>
 __device__ void line_sweep(Level<T>& v, int col) {
-    const int len = kXLine ? v.nx : v.ny;  // 2 .. 256, a power of two
-    if (len > 128 || (!kXLine && len >= 64)) line_sweep_m<T, kXLine, kTrans, 4, Team, AS>(v, col);
-    else line_sweep_m<T, kXLine, kTrans, 2, Team, AS>(v, col);
+    const int len = kXLine ? v.nx : v.ny;  // 2 .. 1024, a power of two
+    if constexpr (std::is_same<Team, WaveTeam>::value) {
+        line_sweep_m<T, kXLine, kTrans, 2, Team, AS>(v, col);
+    } else if constexpr (kXLine) {
+        if (len <= 128) line_sweep_m<T, kXLine, kTrans, 2, Team, AS>(v, col);
+        else if (len == 256) line_sweep_m<T, kXLine, kTrans, 4, Team, AS>(v, col);
+        else if (len == 512) line_sweep_m<T, kXLine, kTrans, 8, Team, AS>(v, col);
+        else line_sweep_m<T, kXLine, kTrans, 16, Team, AS>(v, col);
+    } else {
+        if (len < 64) line_sweep_m<T, kXLine, kTrans, 2, Team, AS>(v, col);
+        else if (len <= 256) line_sweep_m<T, kXLine, kTrans, 4, Team, AS>(v, col);
+        else line_sweep_m<T, kXLine, kTrans, 8, Team, AS>(v, col);
+    }
 }
 
 // One zebra sweep in one direction: x-lines (even rows, then odd rows) or

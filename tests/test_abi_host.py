@@ -69,12 +69,12 @@ def test_sample_xi_bit_exact(L, seed, level, first, count, dim):
 
 
 def test_workspace_validation(L):
-    ok = [(16, 8, 50), (256, 128, 800)]
+    ok = [(16, 8, 50), (256, 128, 800), (1024, 512, 3200)]
     assert hm.henry_workspace_bytes(ok) > 0
     mixed = hm.make_opts(prec=hm.PREC_MIXED)
     fp64 = hm.make_opts(prec=hm.PREC_FP64)
     assert hm.henry_workspace_bytes(ok, fp64) > hm.henry_workspace_bytes(ok, mixed)
-    for bad in [[(16, 16, 50)], [(24, 12, 50)], [(16, 8, 0)], [(512, 256, 10)], [(0, 0, 5)]]:
+    for bad in [[(16, 16, 50)], [(24, 12, 50)], [(16, 8, 0)], [(2048, 1024, 10)], [(0, 0, 5)]]:
         with pytest.raises(hm.HenryError) as e:
             hm.henry_workspace_bytes(bad)
         assert e.value.code == hm.HENRY_EINVAL
