@@ -194,9 +194,9 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
 /* Tuning cache of a context: threads per solve-workgroup for grids of
  * width nx at precision prec, used by henry_solve_batch and
  * henry_adjoint_batch when opts->threads == 0.  threads = 0 clears the
- * entry (back to the built-in default: 64 threads up to 128 cells, 128 up
- * to 512, 256 up to 2048, 512 above); threads <= 1024 for PREC_MIXED and
- * <= 512 for PREC_FP64.  The measuring driver that fills it
+ * entry (back to the built-in default: 128 threads up to 128 cells, 256 up
+ * to 512, 512 up to 2048, above that 1024 with PREC_MIXED and 512 with
+ * PREC_FP64); threads <= 1024 for PREC_MIXED and <= 512 for PREC_FP64.  The measuring driver that fills it
  * times candidate sizes on short runs of the caller's own batch (Python
  * binding: paper_2302_07804_amd.autotune). */
 int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads);

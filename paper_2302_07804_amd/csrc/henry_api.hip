@@ -120,12 +120,15 @@ int64_t solve_bytes(int nx, int ny, int prec) {
     return prec == HENRY_PREC_MIXED ? henry::solve_bytes<float>(nx, ny) : henry::solve_bytes<double>(nx, ny);
 }
 
-int default_threads(int nx, int ny) {
+// Built-in workgroup size (the choices the measuring autotuner makes on the
+// MLMC hierarchy): twice the cells up to 512 threads, then the largest size
+// the precision's kernel is built for.
+int default_threads(int nx, int ny, int prec) {
     const int cells = nx * ny;
-    if (cells <= 128) return 64;
-    if (cells <= 512) return 128;
-    if (cells <= 2048) return 256;
-    return 512;
+    if (cells <= 128) return 128;
+    if (cells <= 512) return 256;
+    if (cells <= 2048) return 512;
+    return max_threads(prec);
 }
 
 int64_t desc_bytes(int nsolves) { return henry::align256((int64_t)nsolves * (int64_t)sizeof(henry::SolveDesc)); }
@@ -453,7 +456,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
         int t = o->threads;
         if (t == 0) {
             auto it = ctx->tuned_threads.find((long)G.nx * 4 + prec);
-            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny);
+            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny, prec);
         }
         G.threads = t;
     }
@@ -581,7 +584,7 @@ int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads) {
     if (!ctx || !threads || nx < 2 || nx > 1024 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
     if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
     auto it = ctx->tuned_threads.find((long)nx * 4 + prec);
-    *threads = it != ctx->tuned_threads.end() ? it->second : default_threads(nx, nx / 2);
+    *threads = it != ctx->tuned_threads.end() ? it->second : default_threads(nx, nx / 2, prec);
     return HENRY_OK;
 }
 
@@ -679,7 +682,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
         int t = o->threads;
         if (t == 0) {
             auto it = ctx->tuned_threads.find((long)G.nx * 4 + prec);
-            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny);
+            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny, prec);
         }
         G.threads = std::min(t, kAdjMaxThreads);
     }
