@@ -108,9 +108,10 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
 //   wx, wy  east / north face phi_f D (harmonic phi; 2 phi_P D on the
 //           seawater face; 0 above the top row),
 //   isc     residual scale tau / (h^2 phi_P rho0),
-// then kScratch doubles of scratch ([0] recharge, [1] status, [2] outer
+// then the two older states c2, p2 (u^{n-2}) and c3, p3 (u^{n-3}) of the
+// extrapolated initial guess, then kScratch doubles of scratch ([0] recharge, [1] status, [2] outer
 // iterations, [8..] phase timers of builds with HENRY_PHASE_TIMERS).
-constexpr int kF64Arrays = 13;
+constexpr int kF64Arrays = 17;
 constexpr int kScratch = 32;
 
 template <typename T>
@@ -160,7 +161,7 @@ struct Solve {
     int lds_from;  // first level whose arrays live in LDS (L if none)
     double h, tau;
     double q;  // recharge (m/s)
-    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *tx, *ty, *wx, *wy, *isc, *scratch;
+    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *scratch;
     Level<T> lv[kMaxLevels];
 };
 
@@ -190,7 +191,8 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, ui
     const int n = nx * ny;
     S.p = f; S.c = f + n; S.cn = f + 2 * n; S.phi = f + 3 * n; S.K = f + 4 * n; S.Rp = f + 5 * n;
     S.Rc = f + 6 * n; S.pp = f + 7 * n; S.tx = f + 8 * n; S.ty = f + 9 * n; S.wx = f + 10 * n;
-    S.wy = f + 11 * n; S.isc = f + 12 * n; S.scratch = f + kF64Arrays * n;
+    S.wy = f + 11 * n; S.isc = f + 12 * n; S.c2 = f + 13 * n; S.p2 = f + 14 * n; S.c3 = f + 15 * n;
+    S.p3 = f + 16 * n; S.scratch = f + kF64Arrays * n;
     uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
     uint8_t* ql = lds;
     int lx = nx, ly = ny;
@@ -958,25 +960,41 @@ __device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr) {
     }
 }
 
-// One implicit Euler step (Sec. 2.3) from the state in S.p, S.c: saves c^n
-// in S.cn (and p^n in S.pp) and runs the defect correction until both
-// scaled residual max norms are <= tol.  With `extrap` the iteration
-// starts from the linear extrapolation 2 u^n - u^{n-1} of the two previous
-// states (S.cn, S.pp hold u^{n-1} on entry).  Returns 0 converged,
-// 1 max_outer reached, 2 non-finite residual; adds the iterations used to
-// `iters`.
+// One implicit Euler step (Sec. 2.3) from the state u^n = (S.p, S.c):
+// saves u^n in S.cn / S.pp (c^n is the previous time level of the
+// residual), shifts the older states, and runs the defect correction until
+// both scaled residual max norms are <= tol.  The iteration starts from the
+// polynomial extrapolation of order `order` (0..3) through the last
+// order + 1 states (backward differences: u^n; 2u^n - u^{n-1};
+// 3u^n - 3u^{n-1} + u^{n-2}; 4u^n - 6u^{n-1} + 4u^{n-2} - u^{n-3}); on
+// entry S.cn/pp, c2/p2, c3/p3 hold u^{n-1}, u^{n-2}, u^{n-3}.  The start
+// only changes how many iterations a step takes, not what it converges to.
+// Returns 0 converged, 1 max_outer reached, 2 non-finite residual; adds the
+// iterations used to `iters`.
 template <typename T>
 __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_outer, double tol, double& iters,
-                             PhaseClock& pc, bool extrap = false) {
+                             PhaseClock& pc, int order = 0) {
     const int n = S.n;
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const double c1 = S.c[idx], p1 = S.p[idx];
-        if (extrap) {
-            S.c[idx] = 2.0 * c1 - S.cn[idx];
-            S.p[idx] = 2.0 * p1 - S.pp[idx];
+        const double c0 = S.c[idx], p0 = S.p[idx];
+        const double c1 = S.cn[idx], p1 = S.pp[idx];
+        const double c2 = S.c2[idx], p2 = S.p2[idx];
+        if (order == 1) {
+            S.c[idx] = 2.0 * c0 - c1;
+            S.p[idx] = 2.0 * p0 - p1;
+        } else if (order == 2) {
+            S.c[idx] = 3.0 * c0 - 3.0 * c1 + c2;
+            S.p[idx] = 3.0 * p0 - 3.0 * p1 + p2;
+        } else if (order == 3) {
+            S.c[idx] = 4.0 * c0 - 6.0 * c1 + 4.0 * c2 - S.c3[idx];
+            S.p[idx] = 4.0 * p0 - 6.0 * p1 + 4.0 * p2 - S.p3[idx];
         }
-        S.cn[idx] = c1;
-        S.pp[idx] = p1;
+        S.c3[idx] = c2;
+        S.p3[idx] = p2;
+        S.c2[idx] = c1;
+        S.p2[idx] = p1;
+        S.cn[idx] = c0;
+        S.pp[idx] = p0;
     }
     __syncthreads();
     pc.tick(7);
@@ -1047,23 +1065,31 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
     const int s_begin = (int)(((int64_t)lp.g_begin * d.nsteps) / lp.g_total);
     const int s_end = (int)(((int64_t)lp.g_end * d.nsteps) / lp.g_total);
     if (s_begin >= s_end) return;
-    double* sp = S.scratch;  // [0] = q, [1] = status, [2] = iterations
+    // scratch: [0] = q, [1] = status, [2] = iterations, [3] = converged
+    // states in a row (the initial state counts as one)
+    double* sp = S.scratch;
     if (s_begin == 0) {
         initial_state(ph, S, lp.c0 ? lp.c0 + d.field_off : nullptr);
-        if (threadIdx.x == 0) { sp[1] = 0.0; sp[2] = 0.0; }
+        if (threadIdx.x == 0) { sp[1] = 0.0; sp[2] = 0.0; sp[3] = 1.0; }
     }
     if (threadIdx.x == 0) S.q = sp[0];
     __syncthreads();
     int status = (int)sp[1];
     double iters = sp[2];
+    int good = (int)sp[3];
     PhaseClock pc;
     pc.init();
     for (int s = s_begin; s < s_end && status != 2; ++s) {
-        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, iters, pc, s > 0);
+        // extrapolate only through converged states: a step that stopped at
+        // max_outer restarts the history
+        const int order = good - 1 < 3 ? (good - 1 > 0 ? good - 1 : 0) : 3;
+        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, iters, pc, order);
         if (st == 2) status = 2;
         else if (st == 1 && status == 0) status = 1;
+        good = st == 0 ? (good < 4 ? good + 1 : 4) : 0;
     }
     if (threadIdx.x == 0) {
+        sp[3] = (double)good;
         sp[1] = (double)status;
         sp[2] = iters;
 #ifdef HENRY_PHASE_TIMERS
