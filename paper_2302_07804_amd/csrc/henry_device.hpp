@@ -346,70 +346,93 @@ __device__ inline FaceFlux flux_left(const Phys& ph, double h, double q, double 
 }
 
 // ------------------------------------------------------------------ FP64 residual
+// Operands of one cell's residual, loaded from clamped indices before any
+// arithmetic (no loads under boundary branches).
+struct ResIn {
+    double cP, cnP, phiP, pP, cE, pE, cW, pW, cN, pN, cS, pS;
+    double txP, wxP, txW, wxW, tyP, wyP, tyS, wyS, sc;
+};
+
+template <typename T>
+__device__ inline ResIn res_load(const Solve<T>& S, int idx, const Nb& q) {
+    ResIn a;
+    a.cP = S.c[idx]; a.cnP = S.cn[idx]; a.phiP = S.phi[idx]; a.pP = S.p[idx];
+    a.cE = S.c[q.e]; a.pE = S.p[q.e]; a.cW = S.c[q.w]; a.pW = S.p[q.w];
+    a.cN = S.c[q.n]; a.pN = S.p[q.n]; a.cS = S.c[q.s]; a.pS = S.p[q.s];
+    a.txP = S.tx[idx]; a.wxP = S.wx[idx]; a.txW = S.tx[q.w]; a.wxW = S.wx[q.w];
+    a.tyP = S.ty[idx]; a.wyP = S.wy[idx]; a.tyS = S.ty[q.s]; a.wyS = S.wy[q.s];
+    a.sc = S.isc[idx];
+    return a;
+}
+
+// The residual of one cell from its operands; both the interior and the
+// boundary flux of a face are formed and the applicable one selected.
+// Writes the level-0 inner arrays of `mode` and returns the scaled |R^p|,
+// |R^c| through mp, mc.
+template <typename T>
+__device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, int j, const Nb& q, const ResIn& a,
+                                double& mp, double& mc) {
+    const double h = S.h, h2t = h * h / S.tau;
+    Level<T>& L0 = S.lv[0];
+    const double rP = rho_of(ph, a.cP), rN = rho_of(ph, a.cnP);
+    double Rp = h2t * a.phiP * (rP - rN);
+    double Rc = h2t * a.phiP * (rP * a.cP - rN * a.cnP);
+    // east face: interior, or the seawater boundary
+    const FaceFlux fe = flux_face(ph, h, a.pP, a.pE, a.cP, a.cE, a.txP, a.wxP, 0.0);
+    const FaceFlux fr = flux_right(ph, -1.0 + (j + 0.5) * h, a.pP, a.cP, a.txP, a.wxP);
+    Rp += q.he ? fe.M : fr.M;
+    Rc += q.he ? fe.F : fr.F;
+    // west face: interior (flux out of the west neighbour), or recharge
+    const FaceFlux fw = flux_face(ph, h, a.pW, a.pP, a.cW, a.cP, a.txW, a.wxW, 0.0);
+    const FaceFlux fl = flux_left(ph, h, S.q, a.cP, a.phiP);
+    Rp += q.hw ? -fw.M : fl.M;
+    Rc += q.hw ? -fw.F : fl.F;
+    // north face (the top is impermeable)
+    const FaceFlux fn = flux_face(ph, h, a.pP, a.pN, a.cP, a.cN, a.tyP, a.wyP, 1.0);
+    Rp += q.hn ? fn.M : 0.0;
+    Rc += q.hn ? fn.F : 0.0;
+    // south face (the bottom is impermeable)
+    const FaceFlux fs = flux_face(ph, h, a.pS, a.pP, a.cS, a.cP, a.tyS, a.wyS, 1.0);
+    Rp -= q.hs ? fs.M : 0.0;
+    Rc -= q.hs ? fs.F : 0.0;
+    if (mode == 0) {
+        L0.te[idx] = (T)(q.he ? fe.lam : fr.lam);
+        L0.tn[idx] = (T)(q.hn ? fn.lam : 0.0);
+        S.Rp[idx] = Rp;
+        L0.b[idx] = (T)(-Rp);
+        L0.x[idx] = (T)0;
+        mp = nanmax(mp, fabs(Rp * a.sc));
+    } else {
+        L0.mx[idx] = (T)(q.he ? fe.M : 0.0);
+        L0.dx[idx] = (T)(q.he ? fe.dif : 0.0);
+        L0.my[idx] = (T)(q.hn ? fn.M : 0.0);
+        L0.dy[idx] = (T)(q.hn ? fn.dif : 0.0);
+        if (!q.he) { L0.dr[j] = (T)fr.dif; L0.mr[j] = (T)fr.M; }
+        if (!q.hw) { L0.dl[j] = (T)fl.dif; L0.ml[j] = (T)(-fl.M); }
+        L0.acc[idx] = (T)(h2t * a.phiP * rN);
+        L0.b[idx] = (T)(-(Rc - a.cP * Rp));
+        L0.x[idx] = (T)0;
+    }
+    S.Rc[idx] = Rc;
+    mc = nanmax(mc, fabs(Rc * a.sc));
+}
+
 // mode 0: R^p and R^c, pressure coefficients te/tn at level 0, and the
-//         scaled max norms (returned through red-based block max).
+//         scaled max norms (block max).
 // mode 1: the salt defect S = R^c - c R^p with the transport coefficients
 //         at level 0.
+// (Two cells per thread and round spill registers at 1024 threads and run
+// slower; one cell per round it is.)
 template <typename T>
 __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out) {
     const int nx = S.nx, ny = S.ny, n = S.n;
-    const double h = S.h, h2t = h * h / S.tau;
-    Level<T>& L0 = S.lv[0];
     double mp = 0.0, mc = 0.0;
     const int sx = log2i(nx);
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int i = idx & (nx - 1), j = idx >> sx;
-        // every operand from a clamped index first (no loads under boundary
-        // branches); both the interior and the boundary flux of a face are
-        // formed and the applicable one selected
-        const Nb q(i, j, nx, ny);
-        const double cP = S.c[idx], cnP = S.cn[idx], phiP = S.phi[idx], pP = S.p[idx];
-        const double cE = S.c[q.e], pE = S.p[q.e], cW = S.c[q.w], pW = S.p[q.w];
-        const double cN = S.c[q.n], pN = S.p[q.n], cS = S.c[q.s], pS = S.p[q.s];
-        const double txP = S.tx[idx], wxP = S.wx[idx], txW = S.tx[q.w], wxW = S.wx[q.w];
-        const double tyP = S.ty[idx], wyP = S.wy[idx], tyS = S.ty[q.s], wyS = S.wy[q.s];
-        const double sc = S.isc[idx];
-        const double rP = rho_of(ph, cP), rN = rho_of(ph, cnP);
-        double Rp = h2t * phiP * (rP - rN);
-        double Rc = h2t * phiP * (rP * cP - rN * cnP);
-        // east face: interior, or the seawater boundary
-        const FaceFlux fe = flux_face(ph, h, pP, pE, cP, cE, txP, wxP, 0.0);
-        const FaceFlux fr = flux_right(ph, -1.0 + (j + 0.5) * h, pP, cP, txP, wxP);
-        Rp += q.he ? fe.M : fr.M;
-        Rc += q.he ? fe.F : fr.F;
-        // west face: interior (flux out of the west neighbour), or recharge
-        const FaceFlux fw = flux_face(ph, h, pW, pP, cW, cP, txW, wxW, 0.0);
-        const FaceFlux fl = flux_left(ph, h, S.q, cP, phiP);
-        Rp += q.hw ? -fw.M : fl.M;
-        Rc += q.hw ? -fw.F : fl.F;
-        // north face (the top is impermeable)
-        const FaceFlux fn = flux_face(ph, h, pP, pN, cP, cN, tyP, wyP, 1.0);
-        Rp += q.hn ? fn.M : 0.0;
-        Rc += q.hn ? fn.F : 0.0;
-        // south face (the bottom is impermeable)
-        const FaceFlux fs = flux_face(ph, h, pS, pP, cS, cP, tyS, wyS, 1.0);
-        Rp -= q.hs ? fs.M : 0.0;
-        Rc -= q.hs ? fs.F : 0.0;
-        if (mode == 0) {
-            L0.te[idx] = (T)(q.he ? fe.lam : fr.lam);
-            L0.tn[idx] = (T)(q.hn ? fn.lam : 0.0);
-            S.Rp[idx] = Rp;
-            L0.b[idx] = (T)(-Rp);
-            L0.x[idx] = (T)0;
-            mp = nanmax(mp, fabs(Rp * sc));
-        } else {
-            L0.mx[idx] = (T)(q.he ? fe.M : 0.0);
-            L0.dx[idx] = (T)(q.he ? fe.dif : 0.0);
-            L0.my[idx] = (T)(q.hn ? fn.M : 0.0);
-            L0.dy[idx] = (T)(q.hn ? fn.dif : 0.0);
-            if (!q.he) { L0.dr[j] = (T)fr.dif; L0.mr[j] = (T)fr.M; }
-            if (!q.hw) { L0.dl[j] = (T)fl.dif; L0.ml[j] = (T)(-fl.M); }
-            L0.acc[idx] = (T)(h2t * phiP * rN);
-            L0.b[idx] = (T)(-(Rc - cP * Rp));
-            L0.x[idx] = (T)0;
-        }
-        S.Rc[idx] = Rc;
-        mc = nanmax(mc, fabs(Rc * sc));
+        const int j = idx >> sx;
+        const Nb q(idx & (nx - 1), j, nx, ny);
+        const ResIn a = res_load(S, idx, q);
+        res_cell(ph, S, mode, idx, j, q, a, mp, mc);
     }
     np_out = block_max(mp, red);
     nc_out = block_max(mc, red);
