@@ -73,6 +73,20 @@ def test_single_level0_solve(torch_cuda, ctx, prec, bar):
 
 
 @pytest.mark.parametrize("prec,bar", [(hm.PREC_FP64, 1e-8), (hm.PREC_MIXED, 1e-5)])
+def test_degenerate_grids_and_single_steps(torch_cuda, ctx, prec, bar):
+    """The smallest hierarchies (2x1: one level; 4x2, 8x4), single-step and
+    two-step solves (no extrapolation, linear only) with time steps up to
+    the whole horizon T, against the oracle.  (A single step of T on 32x16
+    or finer is beyond the block iteration: it reports NOCONV.)"""
+    solves = [(2, 1, 3), (4, 2, 5), (8, 4, 1), (16, 8, 1), (16, 8, 2), (32, 16, 2), (2, 1, 1)]
+    xi = hm.henry_sample_xi(0, 5, 0, len(solves), 3)
+    out = run(torch_cuda, ctx, solves, xi, prec, max_outer=400)
+    refs = oracle_jobs(solves, xi)
+    worst = check_against(out, solves, refs, bar)
+    print(f"degenerate grids prec={prec}: worst rel err {worst:.3e}")
+
+
+@pytest.mark.parametrize("prec,bar", [(hm.PREC_FP64, 1e-8), (hm.PREC_MIXED, 1e-5)])
 def test_ragged_batch_several_grids(torch_cuda, ctx, prec, bar):
     """Solves of three grids and step counts share one call (several tiles
     per line at 64x32, odd sample counts per grid)."""
