@@ -353,18 +353,6 @@ struct ResIn {
     double txP, wxP, txW, wxW, tyP, wyP, tyS, wyS, sc;
 };
 
-template <typename T>
-__device__ inline ResIn res_load(const Solve<T>& S, int idx, const Nb& q) {
-    ResIn a;
-    a.cP = S.c[idx]; a.cnP = S.cn[idx]; a.phiP = S.phi[idx]; a.pP = S.p[idx];
-    a.cE = S.c[q.e]; a.pE = S.p[q.e]; a.cW = S.c[q.w]; a.pW = S.p[q.w];
-    a.cN = S.c[q.n]; a.pN = S.p[q.n]; a.cS = S.c[q.s]; a.pS = S.p[q.s];
-    a.txP = S.tx[idx]; a.wxP = S.wx[idx]; a.txW = S.tx[q.w]; a.wxW = S.wx[q.w];
-    a.tyP = S.ty[idx]; a.wyP = S.wy[idx]; a.tyS = S.ty[q.s]; a.wyS = S.wy[q.s];
-    a.sc = S.isc[idx];
-    return a;
-}
-
 // The residual of one cell from its operands; both the interior and the
 // boundary flux of a face are formed and the applicable one selected.
 // Writes the level-0 inner arrays of `mode` and returns the scaled |R^p|,
@@ -421,18 +409,61 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
 //         scaled max norms (block max).
 // mode 1: the salt defect S = R^c - c R^p with the transport coefficients
 //         at level 0.
-// (Two cells per thread and round spill registers at 1024 threads and run
-// slower; one cell per round it is.)
+// Thread layout: lanes along x (cw = min(nx, blockDim) columns), the
+// blockDim / cw row groups each march up their own band of rows.  A cell
+// takes p and c of the rows below and above from the registers of the
+// previous row and a load of the next one, and its east and west
+// neighbours' values from the adjacent lanes (one-lane loads only at the
+// ends of a wavefront): 9 full loads per cell instead of 21.
 template <typename T>
 __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out) {
-    const int nx = S.nx, ny = S.ny, n = S.n;
+    const int nx = S.nx, ny = S.ny;
+    const int bs = blockDim.x;
+    const int cw = nx < bs ? nx : bs;  // both powers of two
+    const int G = bs / cw;
+    const int band = (ny + G - 1) / G;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = threadIdx.x / cw, ci = threadIdx.x - g * cw;
+    const int j0 = g * band;
     double mp = 0.0, mc = 0.0;
-    const int sx = log2i(nx);
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int j = idx >> sx;
-        const Nb q(idx & (nx - 1), j, nx, ny);
-        const ResIn a = res_load(S, idx, q);
-        res_cell(ph, S, mode, idx, j, q, a, mp, mc);
+    for (int cx = 0; cx < nx; cx += cw) {
+        const int i = cx + ci;
+        // rows below and at the start of the band (clamped into the grid)
+        const int jb = j0 < ny ? j0 : ny - 1;
+        const int js = jb > 0 ? jb - 1 : jb;
+        double pS = S.p[js * nx + i], cS = S.c[js * nx + i];
+        double tyS = S.ty[js * nx + i], wyS = S.wy[js * nx + i];
+        double pP = S.p[jb * nx + i], cP = S.c[jb * nx + i];
+        for (int t = 0; t < band; ++t) {  // the same trip count in every lane (shuffles)
+            const int j = j0 + t;
+            const bool active = j < ny;
+            const int jc = active ? j : ny - 1;
+            const Nb q(i, jc, nx, ny);
+            const int idx = q.idx;
+            ResIn a;
+            a.pP = pP; a.cP = cP; a.pS = pS; a.cS = cS; a.tyS = tyS; a.wyS = wyS;
+            a.pN = S.p[q.n]; a.cN = S.c[q.n];
+            a.cnP = S.cn[idx]; a.phiP = S.phi[idx];
+            a.txP = S.tx[idx]; a.wxP = S.wx[idx]; a.tyP = S.ty[idx]; a.wyP = S.wy[idx];
+            a.sc = S.isc[idx];
+            // neighbours in x: adjacent lanes, or memory at the wavefront's ends
+            double pEm = 0.0, cEm = 0.0, pWm = 0.0, cWm = 0.0, txWm = 0.0, wxWm = 0.0;
+            if (lane == kWave - 1) { pEm = S.p[q.e]; cEm = S.c[q.e]; }
+            if (lane == 0) { pWm = S.p[q.w]; cWm = S.c[q.w]; txWm = S.tx[q.w]; wxWm = S.wx[q.w]; }
+            const double pEs = __shfl_down(pP, 1, kWave), cEs = __shfl_down(cP, 1, kWave);
+            const double pWs = __shfl_up(pP, 1, kWave), cWs = __shfl_up(cP, 1, kWave);
+            const double txWs = __shfl_up(a.txP, 1, kWave), wxWs = __shfl_up(a.wxP, 1, kWave);
+            a.pE = lane == kWave - 1 ? pEm : pEs;
+            a.cE = lane == kWave - 1 ? cEm : cEs;
+            a.pW = lane == 0 ? pWm : pWs;
+            a.cW = lane == 0 ? cWm : cWs;
+            a.txW = lane == 0 ? txWm : txWs;
+            a.wxW = lane == 0 ? wxWm : wxWs;
+            if (active) res_cell(ph, S, mode, idx, j, q, a, mp, mc);
+            // carry up one row
+            pS = pP; cS = cP; tyS = a.tyP; wyS = a.wyP;
+            pP = a.pN; cP = a.cN;
+        }
     }
     np_out = block_max(mp, red);
     nc_out = block_max(mc, red);
