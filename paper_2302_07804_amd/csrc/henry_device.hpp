@@ -471,50 +471,78 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
 }
 
 // ------------------------------------------------------------------ coefficient coarsening
-template <typename T>
-__device__ void coarsen_pressure(Solve<T>& S) {
-    for (int l = 1; l < S.L; ++l) {
-        const Level<T>& F = S.lv[l - 1];
-        Level<T>& C = S.lv[l];
-        const int nc = C.nx * C.ny;
-        const int sx = log2i(C.nx);
-        for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
-            const int I = idx & (C.nx - 1), J = idx >> sx;
-            const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
-            C.te[idx] = (T)0.5 * (F.te[f0 + 1] + F.te[f1 + 1]);
-            C.tn[idx] = (T)0.5 * (F.tn[f1] + F.tn[f1 + 1]);
-        }
-        __syncthreads();
+// One level of each hierarchy from the level below it (Team loops; the
+// team synchronises after the level).
+template <typename T, class Team, int ASF, int ASC>
+__device__ void coarsen_pressure_level(const Level<T>& F0, Level<T>& C0) {
+    const LV<T, ASF> F(F0);
+    const LV<T, ASC> C(C0);
+    const int nc = C.nx * C.ny;
+    const int sx = log2i(C.nx);
+    for (int idx = Team::rank(); idx < nc; idx += Team::size()) {
+        const int I = idx & (C.nx - 1), J = idx >> sx;
+        const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
+        C.te[idx] = (T)0.5 * (F.te[f0 + 1] + F.te[f1 + 1]);
+        C.tn[idx] = (T)0.5 * (F.tn[f1] + F.tn[f1 + 1]);
     }
+    Team::sync();
+}
+
+template <typename T, class Team, int ASF, int ASC>
+__device__ void coarsen_transport_level(const Level<T>& F0, Level<T>& C0) {
+    const LV<T, ASF> F(F0);
+    const LV<T, ASC> C(C0);
+    const int nc = C.nx * C.ny;
+    const int sx = log2i(C.nx);
+    for (int idx = Team::rank(); idx < nc; idx += Team::size()) {
+        const int I = idx & (C.nx - 1), J = idx >> sx;
+        const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
+        C.acc[idx] = (F.acc[f0] + F.acc[f0 + 1]) + (F.acc[f1] + F.acc[f1 + 1]);
+        // mass fluxes through the two fine faces add; diffusion
+        // transmissibilities (length/distance = 1 on every level) average
+        C.mx[idx] = (I + 1 < C.nx) ? F.mx[f0 + 1] + F.mx[f1 + 1] : (T)0;
+        C.dx[idx] = (I + 1 < C.nx) ? (T)0.5 * (F.dx[f0 + 1] + F.dx[f1 + 1]) : (T)0;
+        C.my[idx] = (J + 1 < C.ny) ? F.my[f1] + F.my[f1 + 1] : (T)0;
+        C.dy[idx] = (J + 1 < C.ny) ? (T)0.5 * (F.dy[f1] + F.dy[f1 + 1]) : (T)0;
+    }
+    for (int J = Team::rank(); J < C.ny; J += Team::size()) {
+        C.dl[J] = (T)0.5 * (F.dl[2 * J] + F.dl[2 * J + 1]);
+        C.dr[J] = (T)0.5 * (F.dr[2 * J] + F.dr[2 * J + 1]);
+        C.mr[J] = F.mr[2 * J] + F.mr[2 * J + 1];
+        C.ml[J] = F.ml[2 * J] + F.ml[2 * J + 1];
+    }
+    Team::sync();
+}
+
+// Re-discretised coarse coefficients of every level: the workgroup forms
+// the levels whose finer neighbour is in global memory; wavefront 0 alone
+// forms the rest (LDS levels, from LDS levels).
+template <typename T, bool kTransport>
+__device__ void coarsen(Solve<T>& S) {
+    const int lw = S.lds_from;
+    for (int l = 1; l < S.L && l <= lw; ++l) {
+        if (l < lw) {
+            if constexpr (kTransport) coarsen_transport_level<T, BlockTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
+            else coarsen_pressure_level<T, BlockTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
+        } else {
+            if constexpr (kTransport) coarsen_transport_level<T, BlockTeam, 1, 3>(S.lv[l - 1], S.lv[l]);
+            else coarsen_pressure_level<T, BlockTeam, 1, 3>(S.lv[l - 1], S.lv[l]);
+        }
+    }
+    if (threadIdx.x < kWave) {
+        for (int l = lw + 1; l < S.L; ++l) {
+            if constexpr (kTransport) coarsen_transport_level<T, WaveTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
+            else coarsen_pressure_level<T, WaveTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
+        }
+    }
+    __syncthreads();
 }
 
 template <typename T>
-__device__ void coarsen_transport(Solve<T>& S) {
-    for (int l = 1; l < S.L; ++l) {
-        const Level<T>& F = S.lv[l - 1];
-        Level<T>& C = S.lv[l];
-        const int nc = C.nx * C.ny;
-        const int sx = log2i(C.nx);
-        for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
-            const int I = idx & (C.nx - 1), J = idx >> sx;
-            const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
-            C.acc[idx] = (F.acc[f0] + F.acc[f0 + 1]) + (F.acc[f1] + F.acc[f1 + 1]);
-            // mass fluxes through the two fine faces add; diffusion
-            // transmissibilities (length/distance = 1 on every level) average
-            C.mx[idx] = (I + 1 < C.nx) ? F.mx[f0 + 1] + F.mx[f1 + 1] : (T)0;
-            C.dx[idx] = (I + 1 < C.nx) ? (T)0.5 * (F.dx[f0 + 1] + F.dx[f1 + 1]) : (T)0;
-            C.my[idx] = (J + 1 < C.ny) ? F.my[f1] + F.my[f1 + 1] : (T)0;
-            C.dy[idx] = (J + 1 < C.ny) ? (T)0.5 * (F.dy[f1] + F.dy[f1 + 1]) : (T)0;
-        }
-        for (int J = threadIdx.x; J < C.ny; J += blockDim.x) {
-            C.dl[J] = (T)0.5 * (F.dl[2 * J] + F.dl[2 * J + 1]);
-            C.dr[J] = (T)0.5 * (F.dr[2 * J] + F.dr[2 * J + 1]);
-            C.mr[J] = F.mr[2 * J] + F.mr[2 * J + 1];
-            C.ml[J] = F.ml[2 * J] + F.ml[2 * J + 1];
-        }
-        __syncthreads();
-    }
-}
+__device__ void coarsen_pressure(Solve<T>& S) { coarsen<T, false>(S); }
+
+template <typename T>
+__device__ void coarsen_transport(Solve<T>& S) { coarsen<T, true>(S); }
 
 // ------------------------------------------------------------------ stencils
 // Pressure: (A x)_P = diag x_P - sum_nb t_nb x_nb; te of the last column is
