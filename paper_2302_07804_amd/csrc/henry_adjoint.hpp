@@ -232,12 +232,14 @@ __device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int 
             A.r_p[idx] = rp;
             A.r_c[idx] = rc;
             // norm in units of the local diagonal of each block
-            const Stencil<T> sp = pstencil(L0, Nb(i, j, L0.nx, L0.ny));
+            const Stencil<T> sp = pstencil(L0, NbS(i, j, L0.nx, L0.ny));
             const Stencil<T> sc = cstencil_t(L0, Nb(i, j, L0.nx, L0.ny), j);
             rmax = nanmax(rmax, fabs(rp) / (double)sp.d);
             rmax = nanmax(rmax, fabs(rc) / (double)sc.d);
-            L0.b[idx] = (T)(block == 0 ? rp : rc);
-            L0.x[idx] = (T)0;
+            // the pressure cycle's arrays are colour-split, the transport's natural
+            const int at = block == 0 ? pidx(i, j, nx) : idx;
+            L0.b[at] = (T)(block == 0 ? rp : rc);
+            L0.x[at] = (T)0;
         } else {
             A.gK[idx] -= gK;
             A.gphi[idx] -= gf;
@@ -278,7 +280,7 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
     double bm = 0.0;
     for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
         const int i = idx % S.nx, j = idx / S.nx;
-        bm = nanmax(bm, fabs(A.b_p[idx]) / (double)pstencil(S.lv[0], Nb(i, j, S.nx, S.ny)).d);
+        bm = nanmax(bm, fabs(A.b_p[idx]) / (double)pstencil(S.lv[0], NbS(i, j, S.nx, S.ny)).d);
         bm = nanmax(bm, fabs(A.b_c[idx]) / (double)cstencil_t(S.lv[0], Nb(i, j, S.nx, S.ny), j).d);
     }
     bm = block_max(bm, red);
@@ -296,7 +298,8 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
         lam_from_mu(S, A);
         jt_pass(ph, S, A, red, 0, 0);
         vcycle<T, false>(S);
-        for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) A.mu_p[idx] += (double)S.lv[0].x[idx];
+        for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x)
+            A.mu_p[idx] += (double)S.lv[0].x[pidx(idx % S.nx, idx / S.nx, S.nx)];
         __syncthreads();
     }
     lam_from_mu(S, A);

@@ -301,6 +301,34 @@ struct Nb {
     }
 };
 
+// Layout of the pressure cycle's level arrays (x, b, r, te, tn while the
+// pressure V-cycle runs): every row stores its red cells ((i + j) even)
+// first and its black cells after them, each in order of i, so that a
+// red-black half-sweep reads and writes whole cache lines.  The transport
+// cycle keeps the natural row-major order.
+__device__ inline int pidx(int i, int j, int nx) { return j * nx + (((i + j) & 1) ? (nx >> 1) : 0) + (i >> 1); }
+
+// Cell (i, j) at storage position s of the colour-split layout (nx = 2^sx).
+__device__ inline void pcell(int s, int nx, int sx, int& i, int& j) {
+    j = s >> sx;
+    const int r = s & (nx - 1), half = nx >> 1;
+    const int col = r >= half ? 1 : 0;
+    i = 2 * (r - col * half) + ((j + col) & 1);
+}
+
+// Neighbour storage positions of (i, j) in the colour-split layout,
+// clamped to the cell itself at the boundary.
+struct NbS {
+    int idx, w, e, s, n;
+    bool hw, he, hs, hn;
+    __device__ NbS(int i, int j, int nx, int ny) {
+        hw = i > 0; he = i + 1 < nx; hs = j > 0; hn = j + 1 < ny;
+        idx = pidx(i, j, nx);
+        w = hw ? pidx(i - 1, j, nx) : idx; e = he ? pidx(i + 1, j, nx) : idx;
+        s = hs ? pidx(i, j - 1, nx) : idx; n = hn ? pidx(i, j + 1, nx) : idx;
+    }
+};
+
 // ------------------------------------------------------------------ physics (FP64)
 __device__ inline double rho_of(const Phys& ph, double c) { return ph.rho0 + (ph.rho1 - ph.rho0) * c; }
 
@@ -384,11 +412,12 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
     Rp -= q.hs ? fs.M : 0.0;
     Rc -= q.hs ? fs.F : 0.0;
     if (mode == 0) {
-        L0.te[idx] = (T)(q.he ? fe.lam : fr.lam);
-        L0.tn[idx] = (T)(q.hn ? fn.lam : 0.0);
+        const int ps = pidx(idx - j * S.nx, j, S.nx);  // pressure cycle: colour-split
+        L0.te[ps] = (T)(q.he ? fe.lam : fr.lam);
+        L0.tn[ps] = (T)(q.hn ? fn.lam : 0.0);
         S.Rp[idx] = Rp;
-        L0.b[idx] = (T)(-Rp);
-        L0.x[idx] = (T)0;
+        L0.b[ps] = (T)(-Rp);
+        L0.x[ps] = (T)0;
         mp = nanmax(mp, fabs(Rp * a.sc));
     } else {
         L0.mx[idx] = (T)(q.he ? fe.M : 0.0);
@@ -480,10 +509,10 @@ __device__ void coarsen_pressure_level(const Level<T>& F0, Level<T>& C0) {
     const int nc = C.nx * C.ny;
     const int sx = log2i(C.nx);
     for (int idx = Team::rank(); idx < nc; idx += Team::size()) {
-        const int I = idx & (C.nx - 1), J = idx >> sx;
-        const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
-        C.te[idx] = (T)0.5 * (F.te[f0 + 1] + F.te[f1 + 1]);
-        C.tn[idx] = (T)0.5 * (F.tn[f1] + F.tn[f1 + 1]);
+        int I, J;  // colour-split layout on both levels
+        pcell(idx, C.nx, sx, I, J);
+        C.te[idx] = (T)0.5 * (F.te[pidx(2 * I + 1, 2 * J, F.nx)] + F.te[pidx(2 * I + 1, 2 * J + 1, F.nx)]);
+        C.tn[idx] = (T)0.5 * (F.tn[pidx(2 * I, 2 * J + 1, F.nx)] + F.tn[pidx(2 * I + 1, 2 * J + 1, F.nx)]);
     }
     Team::sync();
 }
@@ -554,8 +583,8 @@ template <typename T>
 struct Stencil { T d, w, e, s, n; };
 
 
-template <class V, typename T = typename V::value_type>
-__device__ inline Stencil<T> pstencil(const V& v, const Nb& q) {
+template <class V, class Q, typename T = typename V::value_type>
+__device__ inline Stencil<T> pstencil(const V& v, const Q& q) {
     Stencil<T> st;
     const T te = v.te[q.idx], tw = v.te[q.w], tn = v.tn[q.idx], ts = v.tn[q.s];
     st.e = q.he ? te : (T)0;
@@ -615,8 +644,8 @@ __device__ inline Stencil<T> cstencil_t(const V& v, const Nb& q, int j) {
     return st;
 }
 
-template <typename T, bool kTransport, bool kTrans = false, class V>
-__device__ inline Stencil<T> stencil(const V& v, const Nb& q, int j) {
+template <typename T, bool kTransport, bool kTrans = false, class V, class Q>
+__device__ inline Stencil<T> stencil(const V& v, const Q& q, int j) {
     if constexpr (kTransport) {
         if constexpr (kTrans) return cstencil_t(v, q, j);
         else return cstencil(v, q, j);
@@ -629,19 +658,23 @@ __device__ inline Stencil<T> stencil(const V& v, const Nb& q, int j) {
 // Prolongation: bilinear with constant extrapolation at the boundary,
 // x_f += P x_c.  Restriction is its exact transpose (full weighting with
 // weights (1,3,3,1)/4 per direction, boundary weights folded in).
-template <typename T, class Team = BlockTeam, int ASC = 0, int ASF = 0>
+// kSplit: both levels in the colour-split layout (pressure cycle).
+template <typename T, class Team = BlockTeam, int ASC = 0, int ASF = 0, bool kSplit = false>
 __device__ void prolong_add(const Level<T>& C0, Level<T>& F0) {
     const LV<T, ASC> C(C0);
     const LV<T, ASF> F(F0);
     const int n = F.nx * F.ny;
     const int sx = log2i(F.nx);
+    auto cat = [&](int I, int J) { return kSplit ? pidx(I, J, C.nx) : J * C.nx + I; };
     for (int idx = Team::rank(); idx < n; idx += Team::size()) {
-        const int i = idx & (F.nx - 1), j = idx >> sx;
+        int i, j;
+        if constexpr (kSplit) pcell(idx, F.nx, sx, i, j);
+        else { i = idx & (F.nx - 1); j = idx >> sx; }
         const int I = i >> 1, J = j >> 1;
         const int In = (i & 1) ? min(I + 1, C.nx - 1) : max(I - 1, 0);
         const int Jn = (j & 1) ? min(J + 1, C.ny - 1) : max(J - 1, 0);
-        const T v = (T)0.5625 * C.x[J * C.nx + I] + (T)0.1875 * (C.x[J * C.nx + In] + C.x[Jn * C.nx + I]) +
-                    (T)0.0625 * C.x[Jn * C.nx + In];
+        const T v = (T)0.5625 * C.x[cat(I, J)] + (T)0.1875 * (C.x[cat(In, J)] + C.x[cat(I, Jn)]) +
+                    (T)0.0625 * C.x[cat(In, Jn)];
         F.x[idx] += v;
     }
 }
@@ -655,14 +688,16 @@ __device__ inline float rweight(int I, int n, int a) {
     return w;
 }
 
-template <typename T, class Team = BlockTeam, int ASF = 0, int ASC = 0>
+template <typename T, class Team = BlockTeam, int ASF = 0, int ASC = 0, bool kSplit = false>
 __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
     const LV<T, ASF> F(F0);
     const LV<T, ASC> C(C0);
     const int n = C.nx * C.ny;
     const int sx = log2i(C.nx);
     for (int idx = Team::rank(); idx < n; idx += Team::size()) {
-        const int I = idx & (C.nx - 1), J = idx >> sx;
+        int I, J;
+        if constexpr (kSplit) pcell(idx, C.nx, sx, I, J);
+        else { I = idx & (C.nx - 1); J = idx >> sx; }
         // fine rows / columns outside the level get weight 0 (their load is
         // clamped to a valid cell)
         T rv[4][4];
@@ -672,7 +707,7 @@ __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
 #pragma unroll
             for (int aq = 0; aq < 4; ++aq) {
                 const int ifn = min(max(2 * I - 1 + aq, 0), F.nx - 1);
-                rv[bq][aq] = F.r[jf * F.nx + ifn];
+                rv[bq][aq] = F.r[kSplit ? pidx(ifn, jf, F.nx) : jf * F.nx + ifn];
             }
         }
         T s = (T)0;
@@ -708,8 +743,12 @@ __device__ void level_residual(Level<T>& v0) {
         for (int u = 0; u < kRBatch; ++u) {
             const int k = k0 + u * ts;
             const int idx = k < n ? k : 0;
-            const int i = idx & (v.nx - 1), j = idx >> sx;
-            const Nb q(i, j, v.nx, v.ny);
+            // pressure: colour-split storage; transport: natural order
+            int i, j;
+            if constexpr (kTransport) { i = idx & (v.nx - 1); j = idx >> sx; }
+            else pcell(idx, v.nx, sx, i, j);
+            using Q = typename std::conditional<kTransport, Nb, NbS>::type;
+            const Q q(i, j, v.nx, v.ny);
             const Stencil<T> st = stencil<T, kTransport, kTrans>(v, q, j);
             const T xP = v.x[idx], xW = v.x[q.w], xE = v.x[q.e], xS = v.x[q.s], xN = v.x[q.n];
             const T bP = v.b[idx];
@@ -755,7 +794,7 @@ __device__ void rbgs(Level<T>& v0, int sweeps) {
                     const int kk = k < m ? k : 0;
                     const int j = kk >> sh;
                     const int i = 2 * (kk & (half - 1)) + ((j + col) & 1);
-                    const Nb q(i, j, nx, ny);
+                    const NbS q(i, j, nx, ny);  // q.idx = j nx + col half + (kk mod half)
                     at[u] = k < m ? q.idx : -1;
                     const T tE = te[q.idx], tWl = te[q.w], tN = tn[q.idx], tSl = tn[q.s];
                     const T xW = x[q.w], xE = x[q.e], xS = x[q.s], xN = x[q.n];
@@ -986,7 +1025,7 @@ __device__ void vdown(Solve<T>& S, int l) {
     else rbgs<T, Team, AS>(v, 2);
     level_residual<T, kTransport, kTrans, Team, AS>(v);
     Team::sync();
-    restrict_residual<T, Team, AS, ASN>(v, S.lv[l + 1]);
+    restrict_residual<T, Team, AS, ASN, !kTransport>(v, S.lv[l + 1]);
     Team::sync();
 }
 
@@ -999,7 +1038,7 @@ __device__ void vdown(Solve<T>& S, int l) {
 template <typename T, bool kTransport, bool kTrans, class Team, int AS, int ASN>
 __device__ void vup(Solve<T>& S, int l) {
     Level<T>& v = S.lv[l];
-    prolong_add<T, Team, ASN, AS>(S.lv[l + 1], v);
+    prolong_add<T, Team, ASN, AS, !kTransport>(S.lv[l + 1], v);
     Team::sync();
     if constexpr (kTransport) line_smooth<T, kTrans, Team, AS>(v, AS == 3);
     else rbgs<T, Team, AS>(v, 2);
@@ -1014,7 +1053,7 @@ __device__ void vcoarsest(Solve<T>& S) {
         const LV<T, AS> v(S.lv[S.L - 1]);
         // pressure coarsest (2 x 1 cells): direct solve of the 2 x 2 system
         if (Team::rank() == 0) {
-            const Stencil<T> s0 = pstencil(v, Nb(0, 0, 2, 1)), s1 = pstencil(v, Nb(1, 0, 2, 1));
+            const Stencil<T> s0 = pstencil(v, NbS(0, 0, 2, 1)), s1 = pstencil(v, NbS(1, 0, 2, 1));
             const T det = s0.d * s1.d - s0.e * s1.w;
             v.x[0] = (v.b[0] * s1.d + s0.e * v.b[1]) / det;
             v.x[1] = (s0.d * v.b[1] + s1.w * v.b[0]) / det;
@@ -1101,7 +1140,10 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
         pc.tick(1);
         vcycle<T, false>(S, &pc);
         pc.tick(2);
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.p[idx] += (double)S.lv[0].x[idx];
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            const int j = idx >> log2i(S.nx);
+            S.p[idx] += (double)S.lv[0].x[pidx(idx - j * S.nx, j, S.nx)];
+        }
         __syncthreads();
         residual_pass(ph, S, 1, red, np, nc);
         pc.tick(3);
