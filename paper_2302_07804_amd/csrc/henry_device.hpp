@@ -700,6 +700,10 @@ __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
         else { I = idx & (C.nx - 1); J = idx >> sx; }
         // fine rows / columns outside the level get weight 0 (their load is
         // clamped to a valid cell)
+        // fine cells whose residual the level residual left out (zero):
+        // black cells (aq + bq odd) in the pressure cycle, odd rows (bq even)
+        // in the transport cycle
+        auto live = [](int aq, int bq) { return kSplit ? ((aq + bq) & 1) == 0 : (bq & 1) == 1; };
         T rv[4][4];
 #pragma unroll
         for (int bq = 0; bq < 4; ++bq) {
@@ -707,7 +711,7 @@ __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
 #pragma unroll
             for (int aq = 0; aq < 4; ++aq) {
                 const int ifn = min(max(2 * I - 1 + aq, 0), F.nx - 1);
-                rv[bq][aq] = F.r[kSplit ? pidx(ifn, jf, F.nx) : jf * F.nx + ifn];
+                rv[bq][aq] = live(aq, bq) ? F.r[kSplit ? pidx(ifn, jf, F.nx) : jf * F.nx + ifn] : (T)0;
             }
         }
         T s = (T)0;
@@ -729,24 +733,39 @@ __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
     }
 }
 
-// r = b - A x on one level (operands of kRBatch cells gathered first).
+// r = b - A x on one level after the pre-smoothing (operands of kRBatch
+// cells gathered first), on the cells smoothed first only: the cells the
+// smoother updated last (black cells of the red-black sweep, odd rows of the
+// zebra x-line sweep) satisfy their equations with the current neighbours,
+// so their residual is zero to rounding, and the restriction skips them.
+// Pressure: red cells, the first half of each row of the colour-split
+// layout; transport: the even rows.
 constexpr int kRBatch = 2;
 template <typename T, bool kTransport, bool kTrans = false, class Team = BlockTeam, int AS = 0>
 __device__ void level_residual(Level<T>& v0) {
     const LV<T, AS> v(v0);
-    const int n = v.nx * v.ny;
+    const int half = v.nx >> 1;
+    const int n = kTransport ? v.nx * ((v.ny + 1) >> 1) : half * v.ny;  // live cells
     const int ts = Team::size();
     const int sx = log2i(v.nx);
     for (int k0 = Team::rank(); k0 < n; k0 += kRBatch * ts) {
         T res[kRBatch];
+        int at[kRBatch];
 #pragma unroll
         for (int u = 0; u < kRBatch; ++u) {
             const int k = k0 + u * ts;
-            const int idx = k < n ? k : 0;
-            // pressure: colour-split storage; transport: natural order
-            int i, j;
-            if constexpr (kTransport) { i = idx & (v.nx - 1); j = idx >> sx; }
-            else pcell(idx, v.nx, sx, i, j);
+            const int kk = k < n ? k : 0;
+            int i, j, idx;
+            if constexpr (kTransport) {
+                i = kk & (v.nx - 1); j = 2 * (kk >> sx);
+                idx = j * v.nx + i;
+            } else {
+                j = kk >> (sx - 1);
+                const int kr = kk & (half - 1);
+                i = 2 * kr + (j & 1);
+                idx = j * v.nx + kr;
+            }
+            at[u] = idx;
             using Q = typename std::conditional<kTransport, Nb, NbS>::type;
             const Q q(i, j, v.nx, v.ny);
             const Stencil<T> st = stencil<T, kTransport, kTrans>(v, q, j);
@@ -762,7 +781,7 @@ __device__ void level_residual(Level<T>& v0) {
         }
 #pragma unroll
         for (int u = 0; u < kRBatch; ++u)
-            if (k0 + u * ts < n) v.r[k0 + u * ts] = res[u];
+            if (k0 + u * ts < n) v.r[at[u]] = res[u];
     }
 }
 
