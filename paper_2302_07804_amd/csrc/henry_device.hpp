@@ -714,19 +714,22 @@ __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
                 rv[bq][aq] = live(aq, bq) ? F.r[kSplit ? pidx(ifn, jf, F.nx) : jf * F.nx + ifn] : (T)0;
             }
         }
+        // terms outside the level are selected away, not weighted by zero:
+        // their clamped load may land on a cell whose residual was never
+        // written
         T s = (T)0;
 #pragma unroll
         for (int bq = 0; bq < 4; ++bq) {
             const int jf = 2 * J - 1 + bq;
-            const T wb = (jf < 0 || jf >= F.ny) ? (T)0 : (T)rweight(J, C.ny, bq);
+            const bool jin = jf >= 0 && jf < F.ny;
             T row = (T)0;
 #pragma unroll
             for (int aq = 0; aq < 4; ++aq) {
                 const int ifn = 2 * I - 1 + aq;
-                const T wa = (ifn < 0 || ifn >= F.nx) ? (T)0 : (T)rweight(I, C.nx, aq);
-                row += wa * rv[bq][aq];
+                const bool iin = ifn >= 0 && ifn < F.nx;
+                row += iin ? (T)rweight(I, C.nx, aq) * rv[bq][aq] : (T)0;
             }
-            s += wb * row;
+            s += jin ? (T)rweight(J, C.ny, bq) * row : (T)0;
         }
         C.b[idx] = s;
         C.x[idx] = (T)0;
