@@ -208,8 +208,9 @@ int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads);
 int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int32_t* ngroups);
 
 /* Workspace for henry_adjoint_batch: the forward workspace plus, per solve,
- * FP64 adjoint state and checkpoints: 8 (10 n + 8 + (ceil(r/k) + k + 1) 2 n)
- * bytes for n cells, r steps, checkpoint interval k. */
+ * FP64 adjoint state and checkpoints:
+ * 8 (10 n + 8 + ceil(r/k) (8 n + 8) + (k + 1) 2 n) bytes for n cells,
+ * r steps, checkpoint interval k. */
 int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
                                   const henry_opts_t* opts, int32_t ckpt_every, size_t* bytes_out);
 
@@ -222,8 +223,10 @@ int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, in
  * J^n the exact step Jacobian.  Each transposed system is solved by FP64
  * defect correction to max |r|/diag <= adj_tol * max |b|/diag (at most
  * adj_max_it iterations) with the forward V-cycles (opts->prec inner
- * precision) as preconditioner.  The forward pass keeps (p, c) every
- * ckpt_every steps and recomputes each segment during the reverse sweep.
+ * precision) as preconditioner.  The forward pass keeps (p, c) and the
+ * three older states of its extrapolated initial guess every ckpt_every
+ * steps and recomputes each segment (bitwise the same states) during the
+ * reverse sweep.
  *   qoi_out   device [nsolves]
  *   dq_dxi    device [nsolves][3] (CLOSED3) or [nsolves][41] (KL41); must be
  *             NULL for EXPLICIT

@@ -18,9 +18,10 @@
 // one with the transposed stencil.  The salt block goes first, then the
 // pressure block on the recomputed residual.
 //
-// Time reversal by checkpointing: the forward pass stores (p, c) every
-// `ckpt` steps; each segment is recomputed from its checkpoint (bitwise the
-// same states) and then walked backwards.
+// Time reversal by checkpointing: the forward pass stores its state every
+// `ckpt` steps, with the three older states and the counter its
+// extrapolated initial guess draws on; each segment is recomputed from its
+// checkpoint (bitwise the same states) and then walked backwards.
 #pragma once
 
 #include "henry_device.hpp"
@@ -39,34 +40,43 @@ struct AdjLaunch {
 
 __host__ __device__ inline int num_ckpts(int nsteps, int k) { return (nsteps + k - 1) / k; }
 
-// FP64 adjoint region: mu_p, mu_c, lam_p, lam_c, r_p, r_c, b_p, b_c, gK,
-// gphi (n each), 8 doubles of scratch, checkpoints (ncp x 2n), segment
-// states ((k+1) x 2n).
+// Doubles per checkpoint: p, c and the extrapolation history pp, cn, p2,
+// c2, p3, c3 (n each), then the converged-state counter (8 doubles).
+__host__ __device__ inline int64_t ckpt_doubles(int64_t n) { return 8 * n + 8; }
+
+// FP64 adjoint region: mu_p, mu_c, lam_p, lam_c, dinv_p, dinv_c (inverse
+// diagonals of the two blocks at the current step, for the scaled norm),
+// b_p, b_c, gK, gphi (n each), 8 doubles of scratch, checkpoints
+// (ncp x ckpt_doubles), segment states ((k+1) x 2n).
 __host__ __device__ inline int64_t adjoint_bytes(int nx, int ny, int nsteps, int k) {
     const int64_t n = (int64_t)nx * ny;
     const int64_t ncp = num_ckpts(nsteps, k);
-    return align256(8 * (10 * n + 8 + (ncp + k + 1) * 2 * n));
+    return align256(8 * (10 * n + 8 + ncp * ckpt_doubles(n) + (int64_t)(k + 1) * 2 * n));
 }
 
 struct Adj {
-    double *mu_p, *mu_c, *lam_p, *lam_c, *r_p, *r_c, *b_p, *b_c, *gK, *gphi, *scr, *ckpt, *seg;
+    double *mu_p, *mu_c, *lam_p, *lam_c, *dinv_p, *dinv_c, *b_p, *b_c, *gK, *gphi, *scr, *ckpt, *seg;
     int k, ncp;
 };
 
 __device__ inline void bind_adj(Adj& A, uint8_t* base, int n, int nsteps, int k) {
     double* f = reinterpret_cast<double*>(base);
-    A.mu_p = f; A.mu_c = f + n; A.lam_p = f + 2 * n; A.lam_c = f + 3 * n; A.r_p = f + 4 * n; A.r_c = f + 5 * n;
+    A.mu_p = f; A.mu_c = f + n; A.lam_p = f + 2 * n; A.lam_c = f + 3 * n; A.dinv_p = f + 4 * n;
+    A.dinv_c = f + 5 * n;
     A.b_p = f + 6 * n; A.b_c = f + 7 * n; A.gK = f + 8 * n; A.gphi = f + 9 * n; A.scr = f + 10 * n;
     A.k = k;
     A.ncp = num_ckpts(nsteps, k);
     A.ckpt = f + 10 * n + 8;
-    A.seg = A.ckpt + (int64_t)A.ncp * 2 * n;
+    A.seg = A.ckpt + (int64_t)A.ncp * ckpt_doubles(n);
 }
 
 // ------------------------------------------------------------------ flux derivatives (FP64)
-// Derivatives of the flux from cell a to its east (vertical = false) or
-// north (vertical = true) neighbour b with respect to the states and the
-// coefficients of both cells; same flux definition as flux_x / flux_y.
+// Derivatives of the flux from cell a to its east (kVertical = false) or
+// north (kVertical = true) neighbour b with respect to the states of both
+// cells, and with kGrad also to their K and phi; the same flux as the
+// residual's (kf = K_f / mu and wf = phi_f D are the precomputed face
+// coefficients; K and phi enter only the kGrad derivatives of the harmonic
+// means).
 struct FaceDer {
     double M, F;
     double Mpa, Mpb, Mca, Mcb;
@@ -75,17 +85,16 @@ struct FaceDer {
     double Fphia, Fphib;
 };
 
-__device__ inline FaceDer face_der(const Phys& ph, double h, bool vertical, double pa, double pb, double ca,
-                                   double cb, double Ka, double Kb, double fa, double fb) {
+template <bool kVertical, bool kGrad>
+__device__ inline FaceDer face_der(const Phys& ph, double h, double pa, double pb, double ca, double cb, double kf,
+                                   double wf, double Ka, double Kb, double fa, double fb) {
     FaceDer d;
     const double dr = ph.rho1 - ph.rho0;
     const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
-    const double sK = Ka + Kb, Kf = 2.0 * Ka * Kb / sK;
-    const double sf = fa + fb, ff = 2.0 * fa * fb / sf;
-    const double lam = rf * Kf / ph.mu, dlam = 0.5 * dr * Kf / ph.mu;  // d lam / d c_a = d lam / d c_b
-    const double dif = rf * ff * ph.D, ddif = 0.5 * dr * ff * ph.D;
+    const double lam = rf * kf, dlam = 0.5 * dr * kf;  // d lam / d c_a = d lam / d c_b
+    const double dif = rf * wf, ddif = 0.5 * dr * wf;
     double gr = pb - pa, dgr = 0.0;
-    if (vertical) {
+    if constexpr (kVertical) {
         gr += rf * ph.g * h;
         dgr = 0.5 * dr * ph.g * h;
     }
@@ -101,37 +110,48 @@ __device__ inline FaceDer face_der(const Phys& ph, double h, bool vertical, doub
     d.Fpb = d.Mpb * cup;
     d.Fca = d.Mca * cup + (upa ? d.M : 0.0) - ddif * (cb - ca) + dif;
     d.Fcb = d.Mcb * cup + (upa ? 0.0 : d.M) - ddif * (cb - ca) - dif;
-    const double dKa = 2.0 * Kb * Kb / (sK * sK), dKb = 2.0 * Ka * Ka / (sK * sK);
-    d.MKa = -(rf / ph.mu) * gr * dKa;
-    d.MKb = -(rf / ph.mu) * gr * dKb;
-    d.FKa = d.MKa * cup;
-    d.FKb = d.MKb * cup;
-    const double dfa = 2.0 * fb * fb / (sf * sf), dfb = 2.0 * fa * fa / (sf * sf);
-    d.Fphia = -rf * ph.D * dfa * (cb - ca);
-    d.Fphib = -rf * ph.D * dfb * (cb - ca);
+    if constexpr (kGrad) {
+        const double sK = Ka + Kb, sf = fa + fb;
+        const double dKa = 2.0 * Kb * Kb / (sK * sK), dKb = 2.0 * Ka * Ka / (sK * sK);
+        d.MKa = -(rf / ph.mu) * gr * dKa;
+        d.MKb = -(rf / ph.mu) * gr * dKb;
+        d.FKa = d.MKa * cup;
+        d.FKb = d.MKb * cup;
+        const double dfa = 2.0 * fb * fb / (sf * sf), dfb = 2.0 * fa * fa / (sf * sf);
+        d.Fphia = -rf * ph.D * dfa * (cb - ca);
+        d.Fphib = -rf * ph.D * dfb * (cb - ca);
+    } else {
+        d.MKa = d.MKb = d.FKa = d.FKb = d.Fphia = d.Fphib = 0.0;
+    }
     return d;
 }
 
-// Seawater face: derivatives with respect to the cell's own p, c, K, phi.
+// Seawater face (kf = 2 K_P / mu, wf = 2 phi_P D): derivatives with respect
+// to the cell's own p, c, and with kGrad K, phi.
 struct BndDer { double Mp, Mc, Fp, Fc, MK, FK, Fphi; };
 
-__device__ inline BndDer right_der(const Phys& ph, double y, double pP, double cP, double KP, double fP) {
+template <bool kGrad>
+__device__ inline BndDer right_der(const Phys& ph, double y, double pP, double cP, double kf, double wf) {
     BndDer d;
     const double dr = ph.rho1 - ph.rho0;
     const double rB = 0.5 * (rho_of(ph, cP) + ph.rho1);
-    const double lamB = 2.0 * rB * KP / ph.mu;
+    const double lamB = rB * kf;
     const double gB = -ph.rho1 * ph.g * y - pP;
     const double M = -lamB * gB;
     d.Mp = lamB;
-    d.Mc = -(dr * KP / ph.mu) * gB;
-    d.MK = -(2.0 * rB / ph.mu) * gB;
+    d.Mc = -(0.5 * dr * kf) * gB;
     const bool up = M >= 0.0;
     const double cup = up ? cP : 1.0;
-    const double dif = 2.0 * rB * fP * ph.D, ddif = dr * fP * ph.D;
+    const double dif = rB * wf, ddif = 0.5 * dr * wf;
     d.Fp = d.Mp * cup;
     d.Fc = d.Mc * cup + (up ? M : 0.0) - ddif * (1.0 - cP) + dif;
-    d.FK = d.MK * cup;
-    d.Fphi = -2.0 * rB * ph.D * (1.0 - cP);
+    if constexpr (kGrad) {
+        d.MK = -(2.0 * rB / ph.mu) * gB;
+        d.FK = d.MK * cup;
+        d.Fphi = -2.0 * rB * ph.D * (1.0 - cP);
+    } else {
+        d.MK = d.FK = d.Fphi = 0.0;
+    }
     return d;
 }
 
@@ -148,94 +168,99 @@ __device__ inline BndDer left_der(const Phys& ph, double cP, double fP) {
 }
 
 // ------------------------------------------------------------------ J^T lam and gradients
-// mode 0: r = b - J^T lam (lam from mu), scaled max norm returned; the
-//         inner rhs of the requested block is written to level 0.
-// mode 1: gradient accumulation g -= lam^T dR/dtheta and the rhs of the
-//         previous step.
-template <typename T>
-__device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int mode, int block) {
+// kGrad = false: r = b - J^T lam (lam from mu), scaled max norm returned;
+//                the inner rhs of the requested block is written to level 0.
+// kGrad = true:  gradient accumulation g -= lam^T dR/dtheta and the rhs of
+//                the previous step.
+// Every operand is loaded from clamped indices first; the interior and the
+// boundary form of the east and west faces are both formed and selected.
+template <typename T, bool kGrad>
+__device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int block) {
     const int nx = S.nx, ny = S.ny, n = S.n;
     const double h = S.h, h2t = h * h / S.tau;
     const double dr = ph.rho1 - ph.rho0;
     const double* p = S.p;
     const double* c = S.c;
-    const double* K = S.K;
-    const double* f = S.phi;
     const double* lp = A.lam_p;
     const double* lc = A.lam_c;
     Level<T>& L0 = S.lv[0];
+    const int sx = log2i(nx);
     double rmax = 0.0, gq = 0.0;
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const int i = idx % nx, j = idx / nx;
-        const double cP = c[idx], cnP = S.cn[idx], fP = f[idx];
+        const int i = idx & (nx - 1), j = idx >> sx;
+        const Nb q(i, j, nx, ny);
+        const double cP = c[idx], cnP = S.cn[idx], fP = S.phi[idx], pP = p[idx];
         const double lpP = lp[idx], lcP = lc[idx];
+        const double pE = p[q.e], cE = c[q.e], lpE = lp[q.e], lcE = lc[q.e];
+        const double pW = p[q.w], cW = c[q.w], lpW = lp[q.w], lcW = lc[q.w];
+        const double pN = p[q.n], cN = c[q.n], lpN = lp[q.n], lcN = lc[q.n];
+        const double pS = p[q.s], cS = c[q.s], lpS = lp[q.s], lcS = lc[q.s];
+        const double txP = S.tx[idx], wxP = S.wx[idx], tyP = S.ty[idx], wyP = S.wy[idx];
+        const double txW = S.tx[q.w], wxW = S.wx[q.w], tyS = S.ty[q.s], wyS = S.wy[q.s];
+        double KP = 0.0, KE = 0.0, KW = 0.0, KN = 0.0, KS = 0.0, fE = 0.0, fW = 0.0, fN = 0.0, fS = 0.0;
+        if constexpr (kGrad) {
+            KP = S.K[idx]; KE = S.K[q.e]; KW = S.K[q.w]; KN = S.K[q.n]; KS = S.K[q.s];
+            fE = S.phi[q.e]; fW = S.phi[q.w]; fN = S.phi[q.n]; fS = S.phi[q.s];
+        }
         double jp = 0.0, jc = 0.0;       // (J^T lam) at p_P, c_P
         double gK = 0.0, gf = 0.0;       // lam^T dR/dK_P, lam^T dR/dphi_P
         // stored mass
         jc += lpP * h2t * fP * dr + lcP * h2t * fP * (ph.rho0 + 2.0 * dr * cP);
-        gf += lpP * h2t * (rho_of(ph, cP) - rho_of(ph, cnP)) +
-              lcP * h2t * (rho_of(ph, cP) * cP - rho_of(ph, cnP) * cnP);
-        // east: P = a
-        if (i + 1 < nx) {
-            const int q = idx + 1;
-            const FaceDer d = face_der(ph, h, false, p[idx], p[q], cP, c[q], K[idx], K[q], fP, f[q]);
-            const double wp = lpP - lp[q], wc = lcP - lc[q];
-            jp += wp * d.Mpa + wc * d.Fpa;
-            jc += wp * d.Mca + wc * d.Fca;
-            gK += wp * d.MKa + wc * d.FKa;
-            gf += wc * d.Fphia;
-        } else {
-            const double y = -1.0 + (j + 0.5) * h;
-            const BndDer d = right_der(ph, y, p[idx], cP, K[idx], fP);
-            jp += lpP * d.Mp + lcP * d.Fp;
-            jc += lpP * d.Mc + lcP * d.Fc;
-            gK += lpP * d.MK + lcP * d.FK;
-            gf += lcP * d.Fphi;
+        if constexpr (kGrad)
+            gf += lpP * h2t * (rho_of(ph, cP) - rho_of(ph, cnP)) +
+                  lcP * h2t * (rho_of(ph, cP) * cP - rho_of(ph, cnP) * cnP);
+        // east: P = a, or the seawater face
+        {
+            const FaceDer d = face_der<false, kGrad>(ph, h, pP, pE, cP, cE, txP, wxP, KP, KE, fP, fE);
+            const BndDer b = right_der<kGrad>(ph, -1.0 + (j + 0.5) * h, pP, cP, txP, wxP);
+            const double wp = lpP - lpE, wc = lcP - lcE;
+            jp += q.he ? wp * d.Mpa + wc * d.Fpa : lpP * b.Mp + lcP * b.Fp;
+            jc += q.he ? wp * d.Mca + wc * d.Fca : lpP * b.Mc + lcP * b.Fc;
+            if constexpr (kGrad) {
+                gK += q.he ? wp * d.MKa + wc * d.FKa : lpP * b.MK + lcP * b.FK;
+                gf += q.he ? wc * d.Fphia : lcP * b.Fphi;
+            }
         }
-        // west: P = b
-        if (i > 0) {
-            const int q = idx - 1;
-            const FaceDer d = face_der(ph, h, false, p[q], p[idx], c[q], cP, K[q], K[idx], f[q], fP);
-            const double wp = lp[q] - lpP, wc = lc[q] - lcP;
-            jp += wp * d.Mpb + wc * d.Fpb;
-            jc += wp * d.Mcb + wc * d.Fcb;
-            gK += wp * d.MKb + wc * d.FKb;
-            gf += wc * d.Fphib;
-        } else {
-            const BndDer d = left_der(ph, cP, fP);
-            jc += lcP * d.Fc;
-            gf += lcP * d.Fphi;
-            gq += lpP * (-ph.rho0 * h);
+        // west: P = b, or the recharge face
+        {
+            const FaceDer d = face_der<false, kGrad>(ph, h, pW, pP, cW, cP, txW, wxW, KW, KP, fW, fP);
+            const BndDer b = left_der(ph, cP, fP);
+            const double wp = lpW - lpP, wc = lcW - lcP;
+            jp += q.hw ? wp * d.Mpb + wc * d.Fpb : 0.0;
+            jc += q.hw ? wp * d.Mcb + wc * d.Fcb : lcP * b.Fc;
+            if constexpr (kGrad) {
+                gK += q.hw ? wp * d.MKb + wc * d.FKb : 0.0;
+                gf += q.hw ? wc * d.Fphib : lcP * b.Fphi;
+                gq += q.hw ? 0.0 : lpP * (-ph.rho0 * h);
+            }
         }
-        // north: P = a
-        if (j + 1 < ny) {
-            const int q = idx + nx;
-            const FaceDer d = face_der(ph, h, true, p[idx], p[q], cP, c[q], K[idx], K[q], fP, f[q]);
-            const double wp = lpP - lp[q], wc = lcP - lc[q];
-            jp += wp * d.Mpa + wc * d.Fpa;
-            jc += wp * d.Mca + wc * d.Fca;
-            gK += wp * d.MKa + wc * d.FKa;
-            gf += wc * d.Fphia;
+        // north: P = a (nothing across the top)
+        {
+            const FaceDer d = face_der<true, kGrad>(ph, h, pP, pN, cP, cN, tyP, wyP, KP, KN, fP, fN);
+            const double wp = lpP - lpN, wc = lcP - lcN;
+            jp += q.hn ? wp * d.Mpa + wc * d.Fpa : 0.0;
+            jc += q.hn ? wp * d.Mca + wc * d.Fca : 0.0;
+            if constexpr (kGrad) {
+                gK += q.hn ? wp * d.MKa + wc * d.FKa : 0.0;
+                gf += q.hn ? wc * d.Fphia : 0.0;
+            }
         }
-        // south: P = b
-        if (j > 0) {
-            const int q = idx - nx;
-            const FaceDer d = face_der(ph, h, true, p[q], p[idx], c[q], cP, K[q], K[idx], f[q], fP);
-            const double wp = lp[q] - lpP, wc = lc[q] - lcP;
-            jp += wp * d.Mpb + wc * d.Fpb;
-            jc += wp * d.Mcb + wc * d.Fcb;
-            gK += wp * d.MKb + wc * d.FKb;
-            gf += wc * d.Fphib;
+        // south: P = b (nothing across the bottom)
+        {
+            const FaceDer d = face_der<true, kGrad>(ph, h, pS, pP, cS, cP, tyS, wyS, KS, KP, fS, fP);
+            const double wp = lpS - lpP, wc = lcS - lcP;
+            jp += q.hs ? wp * d.Mpb + wc * d.Fpb : 0.0;
+            jc += q.hs ? wp * d.Mcb + wc * d.Fcb : 0.0;
+            if constexpr (kGrad) {
+                gK += q.hs ? wp * d.MKb + wc * d.FKb : 0.0;
+                gf += q.hs ? wc * d.Fphib : 0.0;
+            }
         }
-        if (mode == 0) {
+        if constexpr (!kGrad) {
             const double rp = A.b_p[idx] - jp, rc = A.b_c[idx] - jc;
-            A.r_p[idx] = rp;
-            A.r_c[idx] = rc;
             // norm in units of the local diagonal of each block
-            const Stencil<T> sp = pstencil(L0, NbS(i, j, L0.nx, L0.ny));
-            const Stencil<T> sc = cstencil_t(L0, Nb(i, j, L0.nx, L0.ny), j);
-            rmax = nanmax(rmax, fabs(rp) / (double)sp.d);
-            rmax = nanmax(rmax, fabs(rc) / (double)sc.d);
+            rmax = nanmax(rmax, fabs(rp) * A.dinv_p[idx]);
+            rmax = nanmax(rmax, fabs(rc) * A.dinv_c[idx]);
             // the pressure cycle's arrays are colour-split, the transport's natural
             const int at = block == 0 ? pidx(i, j, nx) : idx;
             L0.b[at] = (T)(block == 0 ? rp : rc);
@@ -248,7 +273,7 @@ __device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int 
             A.b_c[idx] = lpP * h2t * fP * dr + lcP * h2t * fP * (ph.rho0 + 2.0 * dr * cnP);
         }
     }
-    if (mode == 0) return block_max(rmax, red);
+    if constexpr (!kGrad) return block_max(rmax, red);
     const double g = block_sum(gq, red);
     if (threadIdx.x == 0) A.scr[0] -= g;
     __syncthreads();
@@ -277,18 +302,23 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
     residual_pass(ph, S, 1, red, np, nc);
     coarsen_transport(S);
     // scaled norm of the rhs
+    // (and the inverse block diagonals of this step for the norms)
     double bm = 0.0;
     for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
         const int i = idx % S.nx, j = idx / S.nx;
-        bm = nanmax(bm, fabs(A.b_p[idx]) / (double)pstencil(S.lv[0], NbS(i, j, S.nx, S.ny)).d);
-        bm = nanmax(bm, fabs(A.b_c[idx]) / (double)cstencil_t(S.lv[0], Nb(i, j, S.nx, S.ny), j).d);
+        const double ip = 1.0 / (double)pstencil(S.lv[0], NbS(i, j, S.nx, S.ny)).d;
+        const double ic = 1.0 / (double)cstencil_t(S.lv[0], Nb(i, j, S.nx, S.ny), j).d;
+        A.dinv_p[idx] = ip;
+        A.dinv_c[idx] = ic;
+        bm = nanmax(bm, fabs(A.b_p[idx]) * ip);
+        bm = nanmax(bm, fabs(A.b_c[idx]) * ic);
     }
     bm = block_max(bm, red);
     if (!(bm == bm)) return 2;
     int st = 1;
     for (int it = 0; it < max_it; ++it) {
         lam_from_mu(S, A);
-        const double rn = jt_pass(ph, S, A, red, 0, 1);
+        const double rn = jt_pass<T, false>(ph, S, A, red, 1);
         if (!(rn == rn)) { st = 2; break; }
         if (rn <= tol * bm) { st = 0; break; }
         iters += 1.0;
@@ -296,7 +326,7 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
         for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) A.mu_c[idx] += (double)S.lv[0].x[idx];
         __syncthreads();
         lam_from_mu(S, A);
-        jt_pass(ph, S, A, red, 0, 0);
+        jt_pass<T, false>(ph, S, A, red, 0);
         vcycle<T, false>(S);
         for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x)
             A.mu_p[idx] += (double)S.lv[0].x[pidx(idx % S.nx, idx / S.nx, S.nx)];
@@ -314,6 +344,45 @@ __device__ void save_state(const Solve<T>& S, double* dst) {
     }
     __syncthreads();
 }
+
+// Checkpoint: the state and the extrapolation history before a step, and
+// the count of converged states in a row.
+template <typename T>
+__device__ void save_ckpt(const Solve<T>& S, double* dst, int good) {
+    const int n = S.n;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        dst[idx] = S.p[idx];
+        dst[n + idx] = S.c[idx];
+        dst[2 * n + idx] = S.pp[idx];
+        dst[3 * n + idx] = S.cn[idx];
+        dst[4 * n + idx] = S.p2[idx];
+        dst[5 * n + idx] = S.c2[idx];
+        dst[6 * n + idx] = S.p3[idx];
+        dst[7 * n + idx] = S.c3[idx];
+    }
+    if (threadIdx.x == 0) dst[8 * n] = (double)good;
+    __syncthreads();
+}
+
+template <typename T>
+__device__ int load_ckpt(Solve<T>& S, const double* src) {
+    const int n = S.n;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        S.p[idx] = src[idx];
+        S.c[idx] = src[n + idx];
+        S.pp[idx] = src[2 * n + idx];
+        S.cn[idx] = src[3 * n + idx];
+        S.p2[idx] = src[4 * n + idx];
+        S.c2[idx] = src[5 * n + idx];
+        S.p3[idx] = src[6 * n + idx];
+        S.c3[idx] = src[7 * n + idx];
+    }
+    __syncthreads();
+    return (int)src[8 * n];
+}
+
+// Extrapolation order of a step after `good` converged states in a row.
+__device__ inline int extrap_order(int good) { return good - 1 < 3 ? (good - 1 > 0 ? good - 1 : 0) : 3; }
 
 template <typename T>
 __device__ void load_state(Solve<T>& S, const double* src, const double* prev) {
@@ -347,14 +416,18 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     pc.init();
     double fiters = 0.0, aiters = 0.0;
     int status = 0;
-    // ---- forward pass with checkpoints
+    // ---- forward pass with checkpoints (each step starts from the same
+    // extrapolated guess as the forward solve kernel's)
+    const int64_t ck = ckpt_doubles(n);
     initial_state(ph, S, nullptr);
     __syncthreads();
+    int good = 1;
     for (int s = 0; s < N; ++s) {
-        if (s % k == 0) save_state(S, A.ckpt + (int64_t)(s / k) * 2 * n);
-        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, fiters, pc);
+        if (s % k == 0) save_ckpt(S, A.ckpt + (int64_t)(s / k) * ck, good);
+        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, fiters, pc, extrap_order(good));
         if (st == 2) { status = 2; break; }
         if (st == 1 && status == 0) status = 1;
+        good = st == 0 ? (good < 4 ? good + 1 : 4) : 0;
     }
     const double Q = qoi_of(ph, S, red);
     // ---- adjoint initial conditions: dQ/du^N and the explicit dQ/dphi
@@ -374,11 +447,12 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     // ---- reverse sweep over the checkpoint segments
     for (int seg = A.ncp - 1; seg >= 0 && status != 2; --seg) {
         const int s0 = seg * k, s1 = min(N, s0 + k);
-        load_state(S, A.ckpt + (int64_t)seg * 2 * n, nullptr);
+        int g = load_ckpt(S, A.ckpt + (int64_t)seg * ck);
         save_state(S, A.seg);
         for (int s = s0; s < s1; ++s) {
             double dummy = 0.0;
-            implicit_step(ph, S, red, lp.max_outer, lp.tol, dummy, pc);
+            const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, dummy, pc, extrap_order(g));
+            g = st == 0 ? (g < 4 ? g + 1 : 4) : 0;
             save_state(S, A.seg + (int64_t)(s - s0 + 1) * 2 * n);
         }
         for (int m = s1; m > s0; --m) {
@@ -386,7 +460,7 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
             const int st = adjoint_step(ph, S, A, red, al.max_it, al.tol, aiters);
             if (st == 2) { status = 2; break; }
             if (st == 1 && status == 0) status = 1;
-            jt_pass(ph, S, A, red, 1, 0);
+            jt_pass<T, true>(ph, S, A, red, 0);
         }
     }
     // ---- outputs
