@@ -209,7 +209,7 @@ int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int
 
 /* Workspace for henry_adjoint_batch: the forward workspace plus, per solve,
  * FP64 adjoint state and checkpoints:
- * 8 (10 n + 8 + ceil(r/k) (8 n + 8) + (k + 1) 2 n) bytes for n cells,
+ * 8 (16 n + 8 + ceil(r/k) (8 n + 8) + (k + 1) 2 n) bytes for n cells,
  * r steps, checkpoint interval k. */
 int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
                                   const henry_opts_t* opts, int32_t ckpt_every, size_t* bytes_out);

@@ -46,16 +46,18 @@ __host__ __device__ inline int64_t ckpt_doubles(int64_t n) { return 8 * n + 8; }
 
 // FP64 adjoint region: mu_p, mu_c, lam_p, lam_c, dinv_p, dinv_c (inverse
 // diagonals of the two blocks at the current step, for the scaled norm),
-// b_p, b_c, gK, gphi (n each), 8 doubles of scratch, checkpoints
-// (ncp x ckpt_doubles), segment states ((k+1) x 2n).
+// b_p, b_c, gK, gphi (n each), the three previous steps' mu (mh: p1, c1,
+// p2, c2, p3, c3, n each; the extrapolated start of the transposed
+// solves), 8 doubles of scratch, checkpoints (ncp x ckpt_doubles), segment
+// states ((k+1) x 2n).
 __host__ __device__ inline int64_t adjoint_bytes(int nx, int ny, int nsteps, int k) {
     const int64_t n = (int64_t)nx * ny;
     const int64_t ncp = num_ckpts(nsteps, k);
-    return align256(8 * (10 * n + 8 + ncp * ckpt_doubles(n) + (int64_t)(k + 1) * 2 * n));
+    return align256(8 * (16 * n + 8 + ncp * ckpt_doubles(n) + (int64_t)(k + 1) * 2 * n));
 }
 
 struct Adj {
-    double *mu_p, *mu_c, *lam_p, *lam_c, *dinv_p, *dinv_c, *b_p, *b_c, *gK, *gphi, *scr, *ckpt, *seg;
+    double *mu_p, *mu_c, *lam_p, *lam_c, *dinv_p, *dinv_c, *b_p, *b_c, *gK, *gphi, *mh, *scr, *ckpt, *seg;
     int k, ncp;
 };
 
@@ -63,10 +65,11 @@ __device__ inline void bind_adj(Adj& A, uint8_t* base, int n, int nsteps, int k)
     double* f = reinterpret_cast<double*>(base);
     A.mu_p = f; A.mu_c = f + n; A.lam_p = f + 2 * n; A.lam_c = f + 3 * n; A.dinv_p = f + 4 * n;
     A.dinv_c = f + 5 * n;
-    A.b_p = f + 6 * n; A.b_c = f + 7 * n; A.gK = f + 8 * n; A.gphi = f + 9 * n; A.scr = f + 10 * n;
+    A.b_p = f + 6 * n; A.b_c = f + 7 * n; A.gK = f + 8 * n; A.gphi = f + 9 * n; A.mh = f + 10 * n;
+    A.scr = f + 16 * n;
     A.k = k;
     A.ncp = num_ckpts(nsteps, k);
-    A.ckpt = f + 10 * n + 8;
+    A.ckpt = f + 16 * n + 8;
     A.seg = A.ckpt + (int64_t)A.ncp * ckpt_doubles(n);
 }
 
@@ -290,6 +293,35 @@ __device__ void lam_from_mu(Solve<T>& S, Adj& A) {
     __syncthreads();
 }
 
+// Start of the next transposed solve: the polynomial extrapolation of order
+// `order` (0..3) of mu through the last solves (as the forward steps'
+// initial guess), shifting the history.
+template <typename T>
+__device__ void mu_extrapolate(const Solve<T>& S, Adj& A, int order) {
+    const int n = S.n;
+    double* h1p = A.mh; double* h1c = A.mh + n;
+    double* h2p = A.mh + 2 * n; double* h2c = A.mh + 3 * n;
+    double* h3p = A.mh + 4 * n; double* h3c = A.mh + 5 * n;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        const double p0 = A.mu_p[idx], c0 = A.mu_c[idx];
+        const double p1 = h1p[idx], c1 = h1c[idx], p2 = h2p[idx], c2 = h2c[idx];
+        if (order == 1) {
+            A.mu_p[idx] = 2.0 * p0 - p1;
+            A.mu_c[idx] = 2.0 * c0 - c1;
+        } else if (order == 2) {
+            A.mu_p[idx] = 3.0 * p0 - 3.0 * p1 + p2;
+            A.mu_c[idx] = 3.0 * c0 - 3.0 * c1 + c2;
+        } else if (order == 3) {
+            A.mu_p[idx] = 4.0 * p0 - 6.0 * p1 + 4.0 * p2 - h3p[idx];
+            A.mu_c[idx] = 4.0 * c0 - 6.0 * c1 + 4.0 * c2 - h3c[idx];
+        }
+        h3p[idx] = p2; h3c[idx] = c2;
+        h2p[idx] = p1; h2c[idx] = c1;
+        h1p[idx] = p0; h1c[idx] = c0;
+    }
+    __syncthreads();
+}
+
 // One transposed step solve at the state in S (p^n, c^n; c^{n-1} in S.cn)
 // for the rhs in A.b; mu holds the previous step's solution as the initial
 // guess.  Returns 0 converged, 1 not converged, 2 non-finite.
@@ -444,7 +476,10 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     }
     if (threadIdx.x == 0) A.scr[0] = 0.0;
     __syncthreads();
-    // ---- reverse sweep over the checkpoint segments
+    // ---- reverse sweep over the checkpoint segments (each transposed solve
+    // starts from mu extrapolated through the previous solutions; the zero
+    // start of the first solve is not one of them)
+    int agood = 0;
     for (int seg = A.ncp - 1; seg >= 0 && status != 2; --seg) {
         const int s0 = seg * k, s1 = min(N, s0 + k);
         int g = load_ckpt(S, A.ckpt + (int64_t)seg * ck);
@@ -457,7 +492,9 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
         }
         for (int m = s1; m > s0; --m) {
             load_state(S, A.seg + (int64_t)(m - s0) * 2 * n, A.seg + (int64_t)(m - 1 - s0) * 2 * n);
+            mu_extrapolate(S, A, extrap_order(agood));
             const int st = adjoint_step(ph, S, A, red, al.max_it, al.tol, aiters);
+            agood = st == 0 ? (agood < 4 ? agood + 1 : 4) : 0;
             if (st == 2) { status = 2; break; }
             if (st == 1 && status == 0) status = 1;
             jt_pass<T, true>(ph, S, A, red, 0);
