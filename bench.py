@@ -157,6 +157,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and 1024x512 throughput lines (other workloads, not the metric)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of CALIB_BYTES before the batch (HBM-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -348,6 +350,48 @@ def main():
         errs["batched_mixed_max_rel_c_err_256x128_vs_fp64_tol1e-10"] = worst
         log(f"256x128 vs tight FP64: {worst:.3e}")
 
+    # ---- other workloads of the method, reported beside the metric
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        # discrete adjoint: 512 samples of 128x64/400, checkpoints every 20
+        ag = [(128, 64, 400)] * 512
+        axi = torch.tensor(hm.henry_sample_xi(hi.SEED, 3, 0, 512, 3), dtype=torch.float64, device=dev)
+        aopts = hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60)
+        hm.adjoint(ctx, ag, xi=axi, opts=aopts, ckpt_every=20, adj_tol=args.tol, adj_max_it=60)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a = hm.adjoint(ctx, ag, xi=axi, opts=aopts, ckpt_every=20, adj_tol=args.tol, adj_max_it=60)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t
+        extras["adjoint_128x64"] = dict(
+            workload="512 samples, 128x64, 400 steps, checkpoints every 20, dQ/dxi and dQ/dlog K per cell",
+            seconds=ta, forward_cell_steps_per_s=512 * 128 * 64 * 400 / ta,
+            nonconverged=int((a["status"].cpu().numpy() != 0).sum()), tol=args.tol)
+        log(f"adjoint 512 x 128x64/400: {ta:.2f} s")
+        del a
+        # KL fields on 1024x512: the first 200 steps (tau = T/3200) of 32 samples
+        steps = 200
+        kph = dict(hi.PHYS)
+        kph["T"] = hi.PHYS["T"] * steps / 3200
+        kctx = hm.Context(kph, 0)
+        kctx.set_kl(1024, 512)
+        kxi = torch.tensor(hm.henry_sample_xi_kl(hi.SEED, 6, 0, 32), dtype=torch.float64, device=dev)
+        kg = [(1024, 512, steps)] * 32
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ko = hm.solve(kctx, kg, xi=kxi, opts=hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60))
+        torch.cuda.synchronize()
+        tk = time.perf_counter() - t
+        extras["kl_1024x512_first_200_steps"] = dict(
+            workload="32 KL samples (20+20 modes + recharge), 1024x512, first 200 of 3200 steps",
+            seconds=tk, cell_steps_per_s=32 * 1024 * 512 * steps / tk,
+            mean_outer_iters_per_step=float(ko["iters"].cpu().numpy().mean() / steps),
+            nonconverged=int((ko["status"].cpu().numpy() != 0).sum()))
+        log(f"1024x512 KL, 32 x 200 steps: {tk:.2f} s")
+        del ko
+        kctx.close()
+
     res = {
         "metric": "Henry sample solves/s (cell-steps/s) batched vs plain, same 1e-5 E[c] error",
         "value": value,
@@ -379,6 +423,7 @@ def main():
                      "per_group": [{k: v for k, v in g.items()} for g in per_group],
                      "dominant_group": f"{dom['nx']}x{dom['ny']}"},
         "cpu_baseline": cpu,
+        "other_workloads": extras,
     }
     print(json.dumps(res, default=lambda o: o.item() if hasattr(o, "item") else str(o)))
     ctx.close()
