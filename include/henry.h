@@ -51,6 +51,8 @@ extern "C" {
 #define HENRY_STATUS_OK 0
 #define HENRY_STATUS_NOCONV 1      /* some step hit max_outer; integration went on */
 #define HENRY_STATUS_NONFINITE 2   /* a residual became NaN/Inf; the solve stopped */
+#define HENRY_STATUS_SYNC 3        /* the workgroups of a cluster did not meet at a
+                                      barrier within 10 s; the solve stopped       */
 
 /* Physical constants, SI units (Table 1 of the paper lists rho0, mu, D,
  * E[phi]; the workload fixes rho1, g, k0, q_in and T). */
@@ -104,6 +106,17 @@ typedef struct {
                                  henry_profile_last                              */
     int32_t serial_groups;    /* 1 = run grid groups one after another on one
                                  stream instead of concurrently                  */
+    int32_t cluster;          /* workgroups (CUs) sharing one solve of
+                                 henry_solve_batch: 1, 2, 4 or 8; 0 = built-in
+                                 choice (one per 8192 fine cells, at most 8, and
+                                 at most 256 workgroups per grid group).  Grids
+                                 of 2048 cells or fewer always use 1.  The fine
+                                 levels are split over the cluster, the coarse
+                                 ones run on its first workgroup; the results
+                                 are bitwise the same for every value.  The
+                                 members synchronise through the solve's
+                                 workspace, so the launch must be able to hold
+                                 a group's clusters at once (<= 256 CUs).        */
 } henry_opts_t;
 
 /* Timing of one grid group of the last henry_solve_batch call made with

@@ -19,7 +19,7 @@ _DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlm
     [os.path.join(_ROOT, "include", "henry.h")]
 
 HENRY_OK, HENRY_EINVAL, HENRY_ENOMEM, HENRY_EHIP, HENRY_ENOCONV, HENRY_ENONFINITE = 0, -1, -2, -3, -4, -5
-STATUS_OK, STATUS_NOCONV, STATUS_NONFINITE = 0, 1, 2
+STATUS_OK, STATUS_NOCONV, STATUS_NONFINITE, STATUS_SYNC = 0, 1, 2, 3
 FIELD_CLOSED3, FIELD_KL41, FIELD_EXPLICIT = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
@@ -67,7 +67,8 @@ class Grid(ct.Structure):
 
 class Opts(ct.Structure):
     _fields_ = [("prec", ct.c_int32), ("max_outer", ct.c_int32), ("tol", ct.c_double), ("threads", ct.c_int32),
-                ("steps_per_launch", ct.c_int32), ("profile", ct.c_int32), ("serial_groups", ct.c_int32)]
+                ("steps_per_launch", ct.c_int32), ("profile", ct.c_int32), ("serial_groups", ct.c_int32),
+                ("cluster", ct.c_int32)]
 
 
 class GroupTime(ct.Structure):

@@ -437,12 +437,13 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     const Phys& ph = lp.ph;
     if (threadIdx.x == 0) {
         bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
+        S.lc = 0;
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
         S.q = S.scratch[0];
         bind_adj(A, lp.ws + d.adj_off, d.nx * d.ny, d.nsteps, al.ckpt);
     }
-    __syncthreads();
+    cluster_init_single();
     const int n = S.n, N = d.nsteps, k = A.k;
     PhaseClock pc;
     pc.init();

@@ -32,7 +32,7 @@ constexpr int kLdsCells = 512;  // levels of at most this many cells live in LDS
 static_assert(kLdsCells >= 2, "the coarsest level (2 x 1) must be in LDS");
 
 struct Group {
-    int nx, ny, threads;
+    int nx, ny, threads, cluster;
     std::vector<int> members;  // indices into the solve list
     double cost;
 };
@@ -113,7 +113,21 @@ int check_opts(const henry_opts_t* o) {
     if (o->steps_per_launch < 0) return HENRY_EINVAL;
     if (o->profile != 0 && o->profile != 1) return HENRY_EINVAL;
     if (o->serial_groups != 0 && o->serial_groups != 1) return HENRY_EINVAL;
+    if (o->cluster != 0 && (o->cluster > henry::kMaxCluster || !pow2(o->cluster))) return HENRY_EINVAL;
     return HENRY_OK;
+}
+
+// Workgroups per solve.  A cluster needs the level below the finest in
+// global memory (more than 4 x kLdsCells cells).  Built-in choice: one
+// workgroup per 8192 fine cells, at most 8, and at most as many as keep the
+// group's clusters within the 256 CUs (one 1024-thread workgroup each).
+int cluster_size(int nx, int ny, int nsolves, int requested) {
+    const int cells = nx * ny;
+    if (cells <= 4 * kLdsCells) return 1;
+    if (requested > 0) return requested;
+    int k = 1;
+    while (2 * k <= henry::kMaxCluster && cells >= 2 * k * 8192 && 2 * k * nsolves <= 256) k *= 2;
+    return k;
 }
 
 int64_t solve_bytes(int nx, int ny, int prec) {
@@ -154,6 +168,10 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
+        const int K = G.cluster;
+        const int nblk = K == 1 ? nb : (nb + 7) / 8 * 8 * K;  // see henry::cluster_of_block
+        l.nsolves = nb;
+        l.cluster = K;
         if (l.field_kind == 2) {
             const KlGrid& kg = ctx->kl.at(G.nx);
             l.kl_modes = kg.modes;
@@ -180,9 +198,9 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
             l.g_end = std::min(rmax, g0 + chunk);
             l.g_total = rmax;
             if (prec == HENRY_PREC_MIXED)
-                hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nb), dim3(G.threads), lds, st, l);
+                hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nblk), dim3(G.threads), lds, st, l);
             else
-                hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nb), dim3(G.threads), lds, st, l);
+                hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nblk), dim3(G.threads), lds, st, l);
         }
         if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
         if (profile && hipEventRecord(ctx->prof_ev[2 * gi + 1], st) != hipSuccess) return HENRY_EHIP;
@@ -459,6 +477,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
             t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny, prec);
         }
         G.threads = t;
+        G.cluster = cluster_size(G.nx, G.ny, (int)G.members.size(), o->cluster);
     }
 
     DeviceGuard dg(ctx->device);
@@ -524,7 +543,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     int64_t tolbits;
     std::memcpy(&tolbits, &o->tol, 8);
     for (int64_t v : {(int64_t)o->prec, (int64_t)o->max_outer, tolbits, (int64_t)o->threads, (int64_t)spl,
-                      (int64_t)o->serial_groups, (int64_t)field})
+                      (int64_t)o->serial_groups, (int64_t)field, (int64_t)o->cluster})
         key.words.push_back(v);
     hipStream_t cs = ctx->cap_stream;
     if (hipEventRecord(ctx->cap_in, s0) != hipSuccess) return HENRY_EHIP;
@@ -727,6 +746,8 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
+        l.nsolves = nb;
+        l.cluster = 1;  // one workgroup per adjoint solve
         if (l.field_kind == 2) {
             const KlGrid& kg = ctx->kl.at(G.nx);
             l.kl_modes = kg.modes;

@@ -82,6 +82,8 @@ struct Launch {
     int32_t xi_dim;          // coefficients per solve in xi (3 closed form, 41 KL)
     const double* kl_modes;  // KL: sqrt(lam_k) e_k at the cells of this group's grid, [20][n]
     double kl_sigma_phi, kl_sigma_logk;
+    int32_t nsolves;         // solves of this launch (descs[0 .. nsolves-1])
+    int32_t cluster;         // workgroups per solve (1, 2, 4 or 8)
 };
 
 // ------------------------------------------------------------------ layout
@@ -113,10 +115,15 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
 //           seawater face; 0 above the top row),
 //   isc     residual scale tau / (h^2 phi_P rho0),
 // then the two older states c2, p2 (u^{n-2}) and c3, p3 (u^{n-3}) of the
-// extrapolated initial guess, then kScratch doubles of scratch ([0] recharge, [1] status, [2] outer
-// iterations, [8..] phase timers of builds with HENRY_PHASE_TIMERS).
+// extrapolated initial guess, then kScratch doubles of scratch: [0] recharge, [1] status, [2] outer
+// iterations, [3] converged states in a row, [8..31] phase timers of builds with
+// HENRY_PHASE_TIMERS, [32..63] the state of a cluster of workgroups sharing the solve (barrier
+// counter and error flag in the two 32-bit halves of [32], barriers passed [34], the members' XCD
+// ids [40..47], their partial residual norms [48..63]).
 constexpr int kF64Arrays = 17;
-constexpr int kScratch = 32;
+constexpr int kScratch = 64;
+constexpr int kClusterCtr = 32, kClusterGen = 34, kClusterXcc = 40, kClusterSlots = 48;
+constexpr int kMaxCluster = 8;
 
 template <typename T>
 __host__ __device__ inline int64_t solve_bytes(int nx, int ny) {
@@ -163,6 +170,7 @@ template <typename T>
 struct Solve {
     int nx, ny, n, nsteps, L;
     int lds_from;  // first level whose arrays live in LDS (L if none)
+    int lc;        // levels 0 .. lc-1 are run by the whole cluster (0 with one workgroup)
     double h, tau;
     double q;  // recharge (m/s)
     double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *scratch;
@@ -288,6 +296,133 @@ struct WaveTeam {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 };
+
+// ------------------------------------------------------------------ clusters
+// A large grid's solve can be shared by K workgroups (a cluster, K = 2, 4
+// or 8), one per CU: the fine levels (0 .. S.lc-1) are split over all
+// K x blockDim threads, while member 0 (the leader) runs the coarse levels
+// alone.  Every cell and every line is computed by the same arithmetic
+// whatever the split, and the residual norms are maxima, so a solve gives
+// bitwise the same result for every K.
+//
+// Members of a cluster are placed on one XCD: the workgroups of a launch
+// are dealt to the eight XCDs round robin (block b on XCD b mod 8), so the
+// members of cluster c on XCD x are K consecutive blocks of that XCD's
+// sequence.  Each launch checks the placement (hardware XCC id, exchanged
+// under an agent-scope barrier); the clusters whose members share one XCD,
+// and so one L2, synchronise by waiting for their own stores, a relaxed
+// arrival and an acquire poll (L1 invalidated); any other cluster uses the
+// agent-scope release (L2 write-back) instead.  Blocks of one XCD are
+// dispatched in order, so the lowest cluster not yet complete always gets
+// its members.  Every wait is bounded: after kClusterTimeout a member raises
+// the cluster's error flag, every later barrier of the cluster returns at
+// once, and the solve reports HENRY_STATUS_SYNC.
+struct ClusterState {
+    int K, member, base, size;
+    unsigned* ctr;   // arrivals (K per barrier)
+    unsigned* err;   // sticky error flag
+    double* slots;   // [2K] partial norms
+    unsigned gen;    // barriers passed
+    int local;       // all members on one XCD
+    int failed;
+};
+__shared__ ClusterState g_cl;
+
+constexpr uint64_t kClusterTimeout = 1000000000ull;  // 10 s of the 100 MHz wall clock
+
+__device__ inline int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)); }
+
+// Workgroup 0 of a cluster waits until all K members have arrived; all
+// memory operations before the call are visible to every member after it.
+__device__ inline void cluster_barrier() {
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        g_cl.gen += 1u;
+        const unsigned target = g_cl.gen * (unsigned)g_cl.K;
+        if (!g_cl.failed) {
+            if (g_cl.local) __hip_atomic_fetch_add(g_cl.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else __hip_atomic_fetch_add(g_cl.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t t0 = wall_clock64();
+            while ((int)(__hip_atomic_load(g_cl.ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+                if (__hip_atomic_load(g_cl.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                    wall_clock64() - t0 > kClusterTimeout) {
+                    __hip_atomic_store(g_cl.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    g_cl.failed = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// All K x blockDim threads of the cluster (the workgroup when K = 1).
+struct ClusterTeam {
+    __device__ static int rank() { return g_cl.base + (int)threadIdx.x; }
+    __device__ static int size() { return g_cl.size; }
+    __device__ static void sync() {
+        if (g_cl.K == 1) __syncthreads();
+        else cluster_barrier();
+    }
+};
+
+// Cluster of one workgroup (the adjoint kernel, small grids).
+__device__ inline void cluster_init_single() {
+    if (threadIdx.x == 0) {
+        g_cl.K = 1; g_cl.member = 0; g_cl.base = 0; g_cl.size = (int)blockDim.x;
+        g_cl.ctr = nullptr; g_cl.err = nullptr; g_cl.slots = nullptr;
+        g_cl.gen = 0u; g_cl.local = 1; g_cl.failed = 0;
+    }
+    __syncthreads();
+}
+
+// Binds member `member` of a K-cluster to the cluster state in the solve's
+// scratch `sp` and checks the members' placement.
+__device__ inline void cluster_init(int K, int member, double* sp) {
+    if (threadIdx.x == 0) {
+        g_cl.K = K; g_cl.member = member; g_cl.base = member * (int)blockDim.x; g_cl.size = K * (int)blockDim.x;
+        g_cl.ctr = reinterpret_cast<unsigned*>(sp + kClusterCtr);
+        g_cl.err = g_cl.ctr + 1;
+        g_cl.slots = sp + kClusterSlots;
+        g_cl.gen = (unsigned)sp[kClusterGen];
+        g_cl.local = 0;  // the placement check itself uses the agent-scope protocol
+        g_cl.failed = 0;
+        sp[kClusterXcc + member] = (double)xcc_id();
+    }
+    cluster_barrier();
+    if (threadIdx.x == 0) {
+        // a cluster that failed in an earlier launch stays failed
+        if (__hip_atomic_load(g_cl.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) g_cl.failed = 1;
+        int same = 1;
+        const double x0 = sp[kClusterXcc];
+        for (int k = 1; k < K; ++k) same &= sp[kClusterXcc + k] == x0 ? 1 : 0;
+        g_cl.local = same;
+    }
+    __syncthreads();
+}
+
+// Maxima of two per-thread values over the whole cluster, in a fixed order
+// (NaN propagates); every thread of every member gets the same pair.
+__device__ inline void cluster_max2(double a, double b, double* red, double& ra, double& rb) {
+    const double pa = block_max(a, red), pb = block_max(b, red);
+    if (g_cl.K == 1) {
+        ra = pa; rb = pb;
+        return;
+    }
+    if (threadIdx.x == 0) {
+        g_cl.slots[2 * g_cl.member] = pa;
+        g_cl.slots[2 * g_cl.member + 1] = pb;
+    }
+    cluster_barrier();
+    ra = g_cl.slots[0];
+    rb = g_cl.slots[1];
+    for (int k = 1; k < g_cl.K; ++k) {
+        ra = nanmax(ra, g_cl.slots[2 * k]);
+        rb = nanmax(rb, g_cl.slots[2 * k + 1]);
+    }
+}
 
 // Neighbour indices of (i, j), clamped to the cell itself at the boundary.
 struct Nb {
@@ -444,15 +579,17 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
 // previous row and a load of the next one, and its east and west
 // neighbours' values from the adjacent lanes (one-lane loads only at the
 // ends of a wavefront): 9 full loads per cell instead of 21.
+// The row bands are spread over all threads of the cluster; mode 0 ends
+// with the cluster-wide norms, mode 1 with a cluster barrier only.
 template <typename T>
 __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out) {
     const int nx = S.nx, ny = S.ny;
-    const int bs = blockDim.x;
+    const int bs = ClusterTeam::size(), rk = ClusterTeam::rank();
     const int cw = nx < bs ? nx : bs;  // both powers of two
     const int G = bs / cw;
     const int band = (ny + G - 1) / G;
     const int lane = threadIdx.x & (kWave - 1);
-    const int g = threadIdx.x / cw, ci = threadIdx.x - g * cw;
+    const int g = rk / cw, ci = rk - g * cw;
     const int j0 = g * band;
     double mp = 0.0, mc = 0.0;
     for (int cx = 0; cx < nx; cx += cw) {
@@ -494,14 +631,18 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
             pP = a.pN; cP = a.cN;
         }
     }
-    np_out = block_max(mp, red);
-    nc_out = block_max(mc, red);
-    __syncthreads();
+    if (mode == 0) {
+        cluster_max2(mp, mc, red, np_out, nc_out);
+        __syncthreads();
+    } else {
+        np_out = nc_out = 0.0;
+        ClusterTeam::sync();
+    }
 }
 
 // ------------------------------------------------------------------ coefficient coarsening
 // One level of each hierarchy from the level below it (Team loops; the
-// team synchronises after the level).
+// caller synchronises the team before the level is read).
 template <typename T, class Team, int ASF, int ASC>
 __device__ void coarsen_pressure_level(const Level<T>& F0, Level<T>& C0) {
     const LV<T, ASF> F(F0);
@@ -514,7 +655,6 @@ __device__ void coarsen_pressure_level(const Level<T>& F0, Level<T>& C0) {
         C.te[idx] = (T)0.5 * (F.te[pidx(2 * I + 1, 2 * J, F.nx)] + F.te[pidx(2 * I + 1, 2 * J + 1, F.nx)]);
         C.tn[idx] = (T)0.5 * (F.tn[pidx(2 * I, 2 * J + 1, F.nx)] + F.tn[pidx(2 * I + 1, 2 * J + 1, F.nx)]);
     }
-    Team::sync();
 }
 
 template <typename T, class Team, int ASF, int ASC>
@@ -540,16 +680,27 @@ __device__ void coarsen_transport_level(const Level<T>& F0, Level<T>& C0) {
         C.mr[J] = F.mr[2 * J] + F.mr[2 * J + 1];
         C.ml[J] = F.ml[2 * J] + F.ml[2 * J + 1];
     }
-    Team::sync();
 }
 
-// Re-discretised coarse coefficients of every level: the workgroup forms
-// the levels whose finer neighbour is in global memory; wavefront 0 alone
-// forms the rest (LDS levels, from LDS levels).
+// Re-discretised coarse coefficients.  The cluster forms levels 1 .. lc
+// (from cluster levels; no barrier after the last, whose next reader, the
+// leader's part of the V-cycle, comes after the restriction's barrier).
 template <typename T, bool kTransport>
-__device__ void coarsen(Solve<T>& S) {
+__device__ void coarsen_cluster(Solve<T>& S) {
+    for (int l = 1; l <= S.lc; ++l) {
+        if (l > 1) ClusterTeam::sync();
+        if constexpr (kTransport) coarsen_transport_level<T, ClusterTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
+        else coarsen_pressure_level<T, ClusterTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
+    }
+}
+
+// Levels `from` .. L-1, run by the leader alone: its workgroup forms the
+// levels whose finer neighbour is in global memory, wavefront 0 the rest
+// (LDS levels, from LDS levels).
+template <typename T, bool kTransport>
+__device__ void coarsen_leader(Solve<T>& S, int from) {
     const int lw = S.lds_from;
-    for (int l = 1; l < S.L && l <= lw; ++l) {
+    for (int l = from > 1 ? from : 1; l < S.L && l <= lw; ++l) {
         if (l < lw) {
             if constexpr (kTransport) coarsen_transport_level<T, BlockTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
             else coarsen_pressure_level<T, BlockTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
@@ -557,14 +708,26 @@ __device__ void coarsen(Solve<T>& S) {
             if constexpr (kTransport) coarsen_transport_level<T, BlockTeam, 1, 3>(S.lv[l - 1], S.lv[l]);
             else coarsen_pressure_level<T, BlockTeam, 1, 3>(S.lv[l - 1], S.lv[l]);
         }
+        __syncthreads();
     }
     if (threadIdx.x < kWave) {
-        for (int l = lw + 1; l < S.L; ++l) {
+        for (int l = (from > lw + 1 ? from : lw + 1); l < S.L; ++l) {
             if constexpr (kTransport) coarsen_transport_level<T, WaveTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
             else coarsen_pressure_level<T, WaveTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
+            WaveTeam::sync();
         }
     }
     __syncthreads();
+}
+
+// Every level, complete on return (the adjoint's transposed solves reuse
+// the coefficients over several cycles).
+template <typename T, bool kTransport>
+__device__ void coarsen(Solve<T>& S) {
+    coarsen_cluster<T, kTransport>(S);
+    if (S.lc > 0) ClusterTeam::sync();
+    if (g_cl.member == 0) coarsen_leader<T, kTransport>(S, S.lc + 1);
+    ClusterTeam::sync();
 }
 
 template <typename T>
@@ -1084,32 +1247,50 @@ __device__ void vcoarsest(Solve<T>& S) {
     }
 }
 
-// One V-cycle.  Levels in global memory are run by the whole workgroup;
-// from the first level in LDS (S.lds_from; the coarsest level always is)
-// down to the coarsest and back, wavefront 0 runs the cycle alone while the
-// other wavefronts wait at one barrier.
+// One V-cycle.  The cluster levels (0 .. lc-1) are run by the whole
+// cluster; the leader alone runs the rest: its workgroup the levels in
+// global memory, and from the first level in LDS (S.lds_from; the coarsest
+// level always is) down to the coarsest and back, its wavefront 0 alone
+// while the other wavefronts wait at one barrier.  With coarse_coeffs the
+// leader first forms the coefficients of levels lc+1 .. L-1 (the cluster
+// formed levels 1 .. lc before the cycle).
 template <typename T, bool kTransport, bool kTrans = false>
-__device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr) {
+__device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr, bool coarse_coeffs = false) {
     const int L = S.L;
     const int lw = S.lds_from;
+    const int lc = S.lc;
     const int t0 = kTransport ? 16 : 8;
     if (pc) pc->tick(kTransport ? 4 : 1);
-    for (int l = 0; l < lw; ++l) {
-        if (l + 1 < lw) vdown<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
-        else vdown<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+    for (int l = 0; l < lc; ++l) {
+        vdown<T, kTransport, kTrans, ClusterTeam, 1, 1>(S, l);
         if (pc) pc->tick(t0 + (l == 0 ? 1 : 2));
     }
-    if (threadIdx.x < kWave) {
-        for (int l = lw; l < L - 1; ++l) vdown<T, kTransport, kTrans, WaveTeam, 3, 3>(S, l);
-        vcoarsest<T, kTransport, kTrans, WaveTeam, 3>(S);
-        for (int l = L - 2; l >= lw; --l) vup<T, kTransport, kTrans, WaveTeam, 3, 3>(S, l);
+    if (g_cl.member == 0) {
+        if (coarse_coeffs) coarsen_leader<T, kTransport>(S, lc + 1);
+        for (int l = lc; l < lw; ++l) {
+            if (l + 1 < lw) vdown<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
+            else vdown<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+            if (pc) pc->tick(t0 + (l == 0 ? 1 : 2));
+        }
+        if (threadIdx.x < kWave) {
+            for (int l = lw; l < L - 1; ++l) vdown<T, kTransport, kTrans, WaveTeam, 3, 3>(S, l);
+            vcoarsest<T, kTransport, kTrans, WaveTeam, 3>(S);
+            for (int l = L - 2; l >= lw; --l) vup<T, kTransport, kTrans, WaveTeam, 3, 3>(S, l);
+        }
+        __syncthreads();
+        if (pc) pc->tick(t0 + 3);
+        for (int l = lw - 1; l >= lc; --l) {
+            if (l + 1 < lw) vup<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
+            else vup<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+            if (pc) pc->tick(t0 + (l == 0 ? 6 : 4));
+        }
     }
-    __syncthreads();
-    if (pc) pc->tick(t0 + 3);
-    for (int l = lw - 1; l >= 0; --l) {
-        if (l + 1 < lw) vup<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
-        else vup<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
-        if (pc) pc->tick(t0 + (l == 0 ? 6 : 4));
+    if (lc > 0) {
+        ClusterTeam::sync();
+        for (int l = lc - 1; l >= 0; --l) {
+            vup<T, kTransport, kTrans, ClusterTeam, 1, 1>(S, l);
+            if (pc) pc->tick(t0 + (l == 0 ? 6 : 4));
+        }
     }
 }
 
@@ -1128,7 +1309,8 @@ template <typename T>
 __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_outer, double tol, double& iters,
                              PhaseClock& pc, int order = 0) {
     const int n = S.n;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int rk = ClusterTeam::rank(), ts = ClusterTeam::size();
+    for (int idx = rk; idx < n; idx += ts) {
         const double c0 = S.c[idx], p0 = S.p[idx];
         const double c1 = S.cn[idx], p1 = S.pp[idx];
         const double c2 = S.c2[idx], p2 = S.p2[idx];
@@ -1149,7 +1331,7 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
         S.cn[idx] = c0;
         S.pp[idx] = p0;
     }
-    __syncthreads();
+    ClusterTeam::sync();
     pc.tick(7);
     for (int it = 0; it < max_outer; ++it) {
         double np, nc;
@@ -1158,23 +1340,23 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
         if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) return 2;
         if (np <= tol && nc <= tol) return 0;
         iters += 1.0;
-        coarsen_pressure(S);
+        coarsen_cluster<T, false>(S);
         pc.tick(1);
-        vcycle<T, false>(S, &pc);
+        vcycle<T, false>(S, &pc, true);
         pc.tick(2);
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+        for (int idx = rk; idx < n; idx += ts) {
             const int j = idx >> log2i(S.nx);
             S.p[idx] += (double)S.lv[0].x[pidx(idx - j * S.nx, j, S.nx)];
         }
-        __syncthreads();
+        ClusterTeam::sync();
         residual_pass(ph, S, 1, red, np, nc);
         pc.tick(3);
-        coarsen_transport(S);
+        coarsen_cluster<T, true>(S);
         pc.tick(4);
-        vcycle<T, true>(S, &pc);
+        vcycle<T, true>(S, &pc, true);
         pc.tick(5);
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) S.c[idx] += (double)S.lv[0].x[idx];
-        __syncthreads();
+        for (int idx = rk; idx < n; idx += ts) S.c[idx] += (double)S.lv[0].x[idx];
+        ClusterTeam::sync();
         pc.tick(6);
     }
     return 1;
@@ -1184,7 +1366,7 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
 // cell's own hydrostatic value -rho(c) g y.
 template <typename T>
 __device__ void initial_state(const Phys& ph, Solve<T>& S, const double* c0) {
-    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < S.n; idx += ClusterTeam::size()) {
         const int j = idx / S.nx;
         const double c = c0 ? c0[idx] : 0.0;
         S.c[idx] = c;
@@ -1202,40 +1384,68 @@ __device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
 }
 
 // ------------------------------------------------------------------ the solve kernel
+// Blocks of a launch: one per solve, or with clusters of K > 1 the blocks
+// x + 8 (K c + r), r = 0 .. K-1, for cluster (solve) x + 8 c, so that the
+// K members of a solve share an XCD; the launch has ceil(nsolves / 8) 8 K
+// blocks and those of clusters past the last solve return at once.
+__device__ inline void cluster_of_block(int K, int& cid, int& member) {
+    const int b = (int)blockIdx.x;
+    if (K == 1) { cid = b; member = 0; return; }
+    const int x = b & 7, s = b >> 3;
+    cid = x + 8 * (s / K);
+    member = s % K;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kernel(Launch lp) {
     extern __shared__ __align__(256) uint8_t lds_levels[];
     __shared__ Solve<T> S;
     __shared__ double red[16];
-    const SolveDesc d = lp.descs[blockIdx.x];
+    int cid, member;
+    cluster_of_block(lp.cluster, cid, member);
+    if (cid >= lp.nsolves) return;
+    const SolveDesc d = lp.descs[cid];
     const Phys& ph = lp.ph;
-    if (threadIdx.x == 0) {
-        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
-        S.nsteps = d.nsteps;
-        S.tau = ph.T / d.nsteps;
-    }
-    __syncthreads();
-    const int n = S.n;
     // local steps of this launch: a solve with r steps advances r/g_total
     // local steps per global step (lockstep schedule across grids)
     const int s_begin = (int)(((int64_t)lp.g_begin * d.nsteps) / lp.g_total);
     const int s_end = (int)(((int64_t)lp.g_end * d.nsteps) / lp.g_total);
     if (s_begin >= s_end) return;
-    // scratch: [0] = q, [1] = status, [2] = iterations, [3] = converged
-    // states in a row (the initial state counts as one)
+    if (threadIdx.x == 0) {
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
+        S.nsteps = d.nsteps;
+        S.tau = ph.T / d.nsteps;
+        // cluster levels: at least level 0, then every level of >= 4096 K
+        // cells whose coarser neighbour is still in global memory
+        int lc = 0;
+        if (lp.cluster > 1) {
+            lc = 1;
+            while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 4096 * lp.cluster) ++lc;
+        }
+        S.lc = lc;
+    }
+    __syncthreads();
     double* sp = S.scratch;
+    if (lp.cluster > 1) cluster_init(lp.cluster, member, sp);
+    else cluster_init_single();
+    const int n = S.n;
+    // scratch: [0] = q, [1] = status, [2] = iterations, [3] = converged
+    // states in a row (the initial state counts as one); written by the
+    // leader at the end of a launch, read by every member at the next
+    int status = 0, good = 1;
+    double iters = 0.0;
     if (s_begin == 0) {
         initial_state(ph, S, lp.c0 ? lp.c0 + d.field_off : nullptr);
-        if (threadIdx.x == 0) { sp[1] = 0.0; sp[2] = 0.0; sp[3] = 1.0; }
+    } else {
+        status = (int)sp[1];
+        iters = sp[2];
+        good = (int)sp[3];
     }
     if (threadIdx.x == 0) S.q = sp[0];
-    __syncthreads();
-    int status = (int)sp[1];
-    double iters = sp[2];
-    int good = (int)sp[3];
+    ClusterTeam::sync();
     PhaseClock pc;
     pc.init();
-    for (int s = s_begin; s < s_end && status != 2; ++s) {
+    for (int s = s_begin; s < s_end && status != 2 && !g_cl.failed; ++s) {
         // extrapolate only through converged states: a step that stopped at
         // max_outer restarts the history
         const int order = good - 1 < 3 ? (good - 1 > 0 ? good - 1 : 0) : 3;
@@ -1244,10 +1454,14 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
         else if (st == 1 && status == 0) status = 1;
         good = st == 0 ? (good < 4 ? good + 1 : 4) : 0;
     }
+    ClusterTeam::sync();
+    if (g_cl.failed) status = 3;
+    if (member != 0) return;
     if (threadIdx.x == 0) {
         sp[3] = (double)good;
         sp[1] = (double)status;
         sp[2] = iters;
+        sp[kClusterGen] = (double)g_cl.gen;
 #ifdef HENRY_PHASE_TIMERS
         for (int k = 0; k < 24; ++k) sp[8 + k] = (double)pc.acc[k];
 #endif
@@ -1310,6 +1524,11 @@ __global__ void henry_fields_kernel(Launch lp) {
             K[idx] = exp(lp.logk_in[d.field_off + idx]);
         }
         if (threadIdx.x == 0) sp[0] = lp.qin_in[d.index];
+    }
+    // a fresh cluster state for the solve's first launch
+    if (threadIdx.x == 0) {
+        sp[kClusterCtr] = 0.0;
+        sp[kClusterGen] = 0.0;
     }
     __syncthreads();
     // face coefficients (harmonic means) and the residual scale

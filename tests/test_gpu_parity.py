@@ -135,6 +135,47 @@ def test_chunked_launches_match_single_launch(torch_cuda, ctx):
     assert torch_cuda.equal(a["c"], b["c"]) and torch_cuda.equal(a["qoi"], b["qoi"])
 
 
+@pytest.mark.parametrize("prec", [hm.PREC_FP64, hm.PREC_MIXED])
+def test_batched_equals_one_solve_per_call(torch_cuda, ctx, prec):
+    """The plain path (one solve per call) and the batched path run the same
+    per-solve computation: bitwise equal fields and QoI, whatever the batch
+    mixes in (other grids, other step counts, other workgroup sizes)."""
+    solves = [(16, 8, 50), (64, 32, 200), (32, 16, 100), (16, 8, 50), (128, 64, 40)]
+    xi = hm.henry_sample_xi(0, 6, 0, len(solves), 3)
+    batch = run(torch_cuda, ctx, solves, xi, prec)
+    cs = hm.unpack(batch["c"], solves)
+    for k, s in enumerate(solves):
+        one = run(torch_cuda, ctx, [s], xi[k:k + 1], prec)
+        assert torch_cuda.equal(one["c"].view(s[1], s[0]), cs[k]), (k, s)
+        assert one["qoi"][0].item() == batch["qoi"][k].item(), (k, s)
+
+
+@pytest.mark.parametrize("prec", [hm.PREC_MIXED, hm.PREC_FP64])
+def test_cluster_sizes_are_bitwise_equal(torch_cuda, ctx, prec):
+    """A solve shared by 2, 4 or 8 workgroups (fine levels split over the
+    cluster, coarse levels on its leader) computes every cell and line with
+    the same arithmetic as one workgroup: c, p, Q, status and iteration
+    counts are bitwise equal, in one launch and in chunked graph launches."""
+    torch = torch_cuda
+    solves = [(128, 64, 40), (256, 128, 160), (128, 64, 40), (16, 8, 50)]
+    xi = hm.henry_sample_xi(0, 7, 0, len(solves), 3)
+    ref = run(torch, ctx, solves, xi, prec, tol=1e-9, cluster=1)
+    assert list(ref["status"].cpu().numpy()) == [hm.STATUS_OK] * len(solves)
+    for K, spl in ((2, 0), (4, 0), (8, 0), (4, 5)):
+        out = run(torch, ctx, solves, xi, prec, tol=1e-9, cluster=K, steps_per_launch=spl)
+        for key in ("c", "p", "qoi", "status", "iters"):
+            assert torch.equal(out[key], ref[key]), (K, spl, key)
+
+
+def test_cluster_solve_matches_oracle(torch_cuda, ctx):
+    solves = [(128, 64, 40)]
+    xi = hm.henry_sample_xi(0, 8, 0, 1, 3)
+    out = run(torch_cuda, ctx, solves, xi, hm.PREC_MIXED, cluster=4)
+    refs = oracle_jobs(solves, xi)
+    worst = check_against(out, solves, refs, 1e-5)
+    print(f"128x64/40 on a 4-workgroup cluster: worst rel err {worst:.3e}")
+
+
 def test_repeat_is_bitwise_deterministic(torch_cuda, ctx):
     solves = [(32, 16, 100)] * 3
     xi = hm.henry_sample_xi(0, 5, 0, 3, 3)
