@@ -125,6 +125,8 @@ typedef struct {
     int32_t nx, ny, nsolves, launches;
     int64_t cell_steps;      /* sum over the group's solves of nx*ny*nsteps */
     double ms;               /* HIP-event time of the group's solve launches */
+    int32_t threads, cluster; /* workgroup size and workgroups per solve used
+                                 (0 in the one entry of a graph replay)      */
 } henry_group_time_t;
 
 typedef struct henry_ctx henry_ctx;

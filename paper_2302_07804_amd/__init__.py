@@ -73,7 +73,7 @@ class Opts(ct.Structure):
 
 class GroupTime(ct.Structure):
     _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nsolves", ct.c_int32), ("launches", ct.c_int32),
-                ("cell_steps", ct.c_int64), ("ms", ct.c_double)]
+                ("cell_steps", ct.c_int64), ("ms", ct.c_double), ("threads", ct.c_int32), ("cluster", ct.c_int32)]
 
 
 _lib = None
@@ -238,8 +238,8 @@ def henry_profile_last(ctx: Context):
     arr = (GroupTime * cap)()
     n = ct.c_int32()
     _chk(lib().henry_profile_last(ctx.handle, arr, cap, ct.byref(n)), "henry_profile_last")
-    return [dict(nx=g.nx, ny=g.ny, nsolves=g.nsolves, launches=g.launches, cell_steps=g.cell_steps, ms=g.ms)
-            for g in arr[:n.value]]
+    return [dict(nx=g.nx, ny=g.ny, nsolves=g.nsolves, launches=g.launches, cell_steps=g.cell_steps, ms=g.ms,
+                 threads=g.threads, cluster=g.cluster) for g in arr[:n.value]]
 
 
 def mlmc_level_estimate(ctx: Context, fine_grids, m, c_fine, c_coarse, q_fine, q_coarse, mean_Y, var_Y, qstats,

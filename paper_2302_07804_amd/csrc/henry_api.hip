@@ -189,6 +189,7 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         if (profile) {
             henry_group_time_t& pt = ctx->prof[gi];
             pt.nx = G.nx; pt.ny = G.ny; pt.nsolves = nb; pt.launches = 0; pt.cell_steps = 0;
+            pt.threads = G.threads; pt.cluster = K;
             for (int k : G.members) pt.cell_steps += (int64_t)solves[k].nx * solves[k].ny * solves[k].nsteps;
             if (hipEventRecord(ctx->prof_ev[2 * gi], st) != hipSuccess) return HENRY_EHIP;
         }
@@ -568,6 +569,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     if (o->profile) {
         henry_group_time_t& pt = ctx->prof[0];
         pt.nx = 0; pt.ny = 0; pt.nsolves = nsolves; pt.launches = 0; pt.cell_steps = 0;
+        pt.threads = 0; pt.cluster = 0;
         for (int k = 0; k < nsolves; ++k) pt.cell_steps += (int64_t)solves[k].nx * solves[k].ny * solves[k].nsteps;
         for (int gi = 0; gi < ng; ++gi) pt.launches += (rmax + spl - 1) / spl;
         if (hipEventRecord(ctx->prof_ev[0], cs) != hipSuccess) return HENRY_EHIP;

@@ -1415,12 +1415,13 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
         bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
-        // cluster levels: at least level 0, then every level of >= 4096 K
-        // cells whose coarser neighbour is still in global memory
+        // cluster levels: at least level 0, then every level of >= 2048 K
+        // cells (>= 2048 per member) whose coarser neighbour is still in
+        // global memory
         int lc = 0;
         if (lp.cluster > 1) {
             lc = 1;
-            while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 4096 * lp.cluster) ++lc;
+            while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 2048 * lp.cluster) ++lc;
         }
         S.lc = lc;
     }
