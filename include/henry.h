@@ -52,7 +52,8 @@ extern "C" {
 #define HENRY_STATUS_NOCONV 1      /* some step hit max_outer; integration went on */
 #define HENRY_STATUS_NONFINITE 2   /* a residual became NaN/Inf; the solve stopped */
 #define HENRY_STATUS_SYNC 3        /* the workgroups of a cluster did not meet at a
-                                      barrier within 10 s; the solve stopped       */
+                                      barrier within opts.cluster_wait_us (10 s by
+                                      default); the solve stopped                 */
 
 /* Physical constants, SI units (Table 1 of the paper lists rho0, mu, D,
  * E[phi]; the workload fixes rho1, g, k0, q_in and T). */
@@ -117,6 +118,10 @@ typedef struct {
                                  members synchronise through the solve's
                                  workspace, so the launch must be able to hold
                                  a group's clusters at once (<= 256 CUs).        */
+    int32_t cluster_wait_us;  /* bound of one wait at a cluster barrier, in
+                                 microseconds; 0 = 10 s.  A member that waits
+                                 longer stops its cluster: the solve reports
+                                 HENRY_STATUS_SYNC.                              */
 } henry_opts_t;
 
 /* Timing of one grid group of the last henry_solve_batch call made with

@@ -436,8 +436,7 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     const SolveDesc d = lp.descs[blockIdx.x];
     const Phys& ph = lp.ph;
     if (threadIdx.x == 0) {
-        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
-        S.lc = 0;
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells, lp.lds_block_cells);
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
         S.q = S.scratch[0];

@@ -28,8 +28,18 @@ namespace {
 constexpr int kStreams = 4;
 // Multigrid levels of at most this many cells (32 x 16 and coarser) are kept
 // in LDS: 28 KB per workgroup at FP32, 56 KB at FP64.
-constexpr int kLdsCells = 512;  // levels of at most this many cells live in LDS
+constexpr int kLdsCells = 512;  // levels of at most this many cells live in LDS (run by wavefront 0)
 static_assert(kLdsCells >= 2, "the coarsest level (2 x 1) must be in LDS");
+// With FP32 inner arrays, levels 1.. of up to 2048 cells also live in LDS
+// (run by the whole workgroup): 82 KB for the 2048-cell level, ~110 KB in
+// all, within the 160 KB of one CU.  The FP64 arrays would not fit.
+constexpr int kLdsBlockCellsF32 = 2048;
+int lds_block_cells(int prec) { return prec == HENRY_PREC_MIXED ? kLdsBlockCellsF32 : 0; }
+size_t lds_bytes(int nx, int ny, int prec) {
+    return (size_t)(prec == HENRY_PREC_MIXED
+                        ? henry::lds_level_bytes<float>(nx, ny, kLdsCells, lds_block_cells(prec))
+                        : henry::lds_level_bytes<double>(nx, ny, kLdsCells, lds_block_cells(prec)));
+}
 
 struct Group {
     int nx, ny, threads, cluster;
@@ -114,6 +124,7 @@ int check_opts(const henry_opts_t* o) {
     if (o->profile != 0 && o->profile != 1) return HENRY_EINVAL;
     if (o->serial_groups != 0 && o->serial_groups != 1) return HENRY_EINVAL;
     if (o->cluster != 0 && (o->cluster > henry::kMaxCluster || !pow2(o->cluster))) return HENRY_EINVAL;
+    if (o->cluster_wait_us < 0) return HENRY_EINVAL;
     return HENRY_OK;
 }
 
@@ -172,6 +183,7 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         const int nblk = K == 1 ? nb : (nb + 7) / 8 * 8 * K;  // see henry::cluster_of_block
         l.nsolves = nb;
         l.cluster = K;
+        l.cluster_wait = (uint64_t)(o->cluster_wait_us > 0 ? o->cluster_wait_us : 10000000) * 100u;  // 100 MHz
         if (l.field_kind == 2) {
             const KlGrid& kg = ctx->kl.at(G.nx);
             l.kl_modes = kg.modes;
@@ -182,9 +194,8 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         // lockstep time chunks: local step s of a solve with r steps runs in
         // global step s * rmax / r; one chunk when steps_per_launch == 0
         l.lds_cells = kLdsCells;
-        const size_t lds = (size_t)(prec == HENRY_PREC_MIXED
-                                        ? henry::lds_level_bytes<float>(G.nx, G.ny, kLdsCells)
-                                        : henry::lds_level_bytes<double>(G.nx, G.ny, kLdsCells));
+        l.lds_block_cells = lds_block_cells(prec);
+        const size_t lds = lds_bytes(G.nx, G.ny, prec);
         const int chunk = spl > 0 ? spl : rmax;
         if (profile) {
             henry_group_time_t& pt = ctx->prof[gi];
@@ -544,7 +555,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     int64_t tolbits;
     std::memcpy(&tolbits, &o->tol, 8);
     for (int64_t v : {(int64_t)o->prec, (int64_t)o->max_outer, tolbits, (int64_t)o->threads, (int64_t)spl,
-                      (int64_t)o->serial_groups, (int64_t)field, (int64_t)o->cluster})
+                      (int64_t)o->serial_groups, (int64_t)field, (int64_t)o->cluster, (int64_t)o->cluster_wait_us})
         key.words.push_back(v);
     hipStream_t cs = ctx->cap_stream;
     if (hipEventRecord(ctx->cap_in, s0) != hipSuccess) return HENRY_EHIP;
@@ -758,9 +769,8 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
         }
         hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
         l.lds_cells = kLdsCells;
-        const size_t lds = (size_t)(prec == HENRY_PREC_MIXED
-                                        ? henry::lds_level_bytes<float>(G.nx, G.ny, kLdsCells)
-                                        : henry::lds_level_bytes<double>(G.nx, G.ny, kLdsCells));
+        l.lds_block_cells = lds_block_cells(prec);
+        const size_t lds = lds_bytes(G.nx, G.ny, prec);
         if (prec == HENRY_PREC_MIXED)
             hipLaunchKernelGGL(henry::henry_adjoint_kernel<float>, dim3(nb), dim3(G.threads), lds, st, l, al);
         else

@@ -1,7 +1,8 @@
 // henry_device.hpp -- gfx950 device code for batched Henry solves.
 //
-// One workgroup owns one solve (one random sample on one grid) and runs its
-// whole implicit time loop (Sec. 2.3: implicit Euler, fixed tau).  Each step
+// One workgroup, or for a large grid a cluster of 2-8 workgroups on one XCD,
+// owns one solve (one random sample on one grid) and runs its whole
+// implicit time loop (Sec. 2.3: implicit Euler, fixed tau).  Each step
 // is a defect correction on the FP64 nonlinear residual of the cell-centred
 // discretisation of e_cont_eq / e_tran_eq / e_Darcy_vel (Sec. 2.1):
 //
@@ -78,12 +79,14 @@ struct Launch {
     int32_t field_kind;
     int32_t g_begin, g_end;  // global step range of this launch
     int32_t g_total;         // global steps of the whole batch (max nsteps)
-    int32_t lds_cells;       // multigrid levels with at most this many cells live in LDS
+    int32_t lds_cells;       // multigrid levels with at most this many cells live in LDS (wavefront 0)
+    int32_t lds_block_cells; // levels 1.. with at most this many cells also live in LDS (whole workgroup)
     int32_t xi_dim;          // coefficients per solve in xi (3 closed form, 41 KL)
     const double* kl_modes;  // KL: sqrt(lam_k) e_k at the cells of this group's grid, [20][n]
     double kl_sigma_phi, kl_sigma_logk;
     int32_t nsolves;         // solves of this launch (descs[0 .. nsolves-1])
     int32_t cluster;         // workgroups per solve (1, 2, 4 or 8)
+    uint64_t cluster_wait;   // bound of one cluster-barrier wait, ticks of the 100 MHz wall clock
 };
 
 // ------------------------------------------------------------------ layout
@@ -117,12 +120,12 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
 // then the two older states c2, p2 (u^{n-2}) and c3, p3 (u^{n-3}) of the
 // extrapolated initial guess, then kScratch doubles of scratch: [0] recharge, [1] status, [2] outer
 // iterations, [3] converged states in a row, [8..31] phase timers of builds with
-// HENRY_PHASE_TIMERS, [32..63] the state of a cluster of workgroups sharing the solve (barrier
-// counter and error flag in the two 32-bit halves of [32], barriers passed [34], the members' XCD
+// HENRY_PHASE_TIMERS, [32..63] the state of a cluster of workgroups sharing the solve (the members'
+// 32-bit arrival counts in [32..35], the error flag in [36], barriers passed [37], the members' XCD
 // ids [40..47], their partial residual norms [48..63]).
 constexpr int kF64Arrays = 17;
 constexpr int kScratch = 64;
-constexpr int kClusterCtr = 32, kClusterGen = 34, kClusterXcc = 40, kClusterSlots = 48;
+constexpr int kClusterFlags = 32, kClusterErr = 36, kClusterGen = 37, kClusterXcc = 40, kClusterSlots = 48;
 constexpr int kMaxCluster = 8;
 
 template <typename T>
@@ -169,34 +172,46 @@ struct LV {
 template <typename T>
 struct Solve {
     int nx, ny, n, nsteps, L;
-    int lds_from;  // first level whose arrays live in LDS (L if none)
+    int lds_from;  // first level whose arrays live in LDS and that wavefront 0 runs alone
+    int lb;        // first level whose arrays live in LDS (lb <= lds_from)
     int lc;        // levels 0 .. lc-1 are run by the whole cluster (0 with one workgroup)
+    int hand;      // level lc is in LDS and fed by the cluster through its global copy hg
     double h, tau;
     double q;  // recharge (m/s)
     double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *scratch;
     Level<T> lv[kMaxLevels];
+    Level<T> hg;  // the global-memory arrays of level lb
 };
 
-// Dynamic LDS bytes for the levels of an nx x ny hierarchy with at most
-// `lds_cells` cells (the coarse end of the V-cycles).
+// Levels in LDS: every level of at most `lds_cells` cells (run by
+// wavefront 0), and levels 1.. of at most `lds_block_cells` cells (run by
+// the whole workgroup; level 0 always stays in global memory, where the
+// FP64 residual pass of the whole cluster writes it).
+__host__ __device__ inline bool level_in_lds(int l, int cells, int lds_cells, int lds_block_cells) {
+    return cells <= lds_cells || (l >= 1 && cells <= lds_block_cells);
+}
+
+// Dynamic LDS bytes for the LDS levels of an nx x ny hierarchy.
 template <typename T>
-__host__ __device__ inline int64_t lds_level_bytes(int nx, int ny, int lds_cells) {
+__host__ __device__ inline int64_t lds_level_bytes(int nx, int ny, int lds_cells, int lds_block_cells) {
     int64_t b = 0;
     int lx = nx, ly = ny;
     const int L = num_levels(ny);
     for (int l = 0; l < L; ++l) {
-        if (lx * ly <= lds_cells) b += level_bytes<T>(lx, ly);
+        if (level_in_lds(l, lx * ly, lds_cells, lds_block_cells)) b += level_bytes<T>(lx, ly);
         lx >>= 1; ly >>= 1;
     }
     return b;
 }
 
-// Binds the solve's arrays.  Levels with at most `lds_cells` cells get
-// their inner arrays in the workgroup's LDS (`lds`): they are rebuilt every
-// iteration, so nothing there has to survive a launch.  lds_cells >= 2, so
+// Binds the solve's arrays.  The LDS levels (level_in_lds) get their inner
+// arrays in the workgroup's LDS (`lds`): they are rebuilt every iteration,
+// so nothing there has to survive a launch.  Every level keeps its region
+// in the workspace too (S.hg views that of level lb).  lds_cells >= 2, so
 // the coarsest level (2 x 1) is always in LDS and S.lds_from < S.L.
 template <typename T>
-__device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, uint8_t* lds, int lds_cells) {
+__device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, uint8_t* lds, int lds_cells,
+                                  int lds_block_cells) {
     S.nx = nx; S.ny = ny; S.n = nx * ny; S.L = num_levels(ny);
     S.h = 1.0 / ny;
     double* f = reinterpret_cast<double*>(base);
@@ -209,17 +224,25 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, ui
     uint8_t* ql = lds;
     int lx = nx, ly = ny;
     S.lds_from = S.L;
-    for (int l = 0; l < S.L; ++l) {
-        const bool in_lds = lx * ly <= lds_cells;
-        if (in_lds && S.lds_from == S.L) S.lds_from = l;
-        T* a = reinterpret_cast<T*>(in_lds ? ql : q);
-        if (in_lds) ql += level_bytes<T>(lx, ly);
+    S.lb = S.L;
+    S.lc = 0;
+    S.hand = 0;
+    auto bind_level = [](Level<T>& v, T* a, int lx, int ly) {
         const int m = lx * ly;
-        Level<T>& v = S.lv[l];
         v.nx = lx; v.ny = ly;
         v.x = a; v.b = a + m; v.r = a + 2 * m; v.te = a + 3 * m; v.tn = a + 4 * m; v.acc = a + 5 * m;
         v.mx = a + 6 * m; v.my = a + 7 * m; v.dx = a + 8 * m; v.dy = a + 9 * m;
         v.dl = a + 10 * m; v.dr = a + 10 * m + ly; v.mr = a + 10 * m + 2 * ly; v.ml = a + 10 * m + 3 * ly;
+    };
+    for (int l = 0; l < S.L; ++l) {
+        const bool in_lds = level_in_lds(l, lx * ly, lds_cells, lds_block_cells);
+        if (in_lds && S.lb == S.L) {
+            S.lb = l;
+            bind_level(S.hg, reinterpret_cast<T*>(q), lx, ly);
+        }
+        if (lx * ly <= lds_cells && S.lds_from == S.L) S.lds_from = l;
+        bind_level(S.lv[l], reinterpret_cast<T*>(in_lds ? ql : q), lx, ly);
+        if (in_lds) ql += level_bytes<T>(lx, ly);
         q += level_bytes<T>(lx, ly);
         lx >>= 1; ly >>= 1;
     }
@@ -311,49 +334,62 @@ struct WaveTeam {
 // sequence.  Each launch checks the placement (hardware XCC id, exchanged
 // under an agent-scope barrier); the clusters whose members share one XCD,
 // and so one L2, synchronise by waiting for their own stores, a relaxed
-// arrival and an acquire poll (L1 invalidated); any other cluster uses the
+// store of the member's arrival count and an acquire poll of all members'
+// counts in one load (L1 invalidated); any other cluster uses the
 // agent-scope release (L2 write-back) instead.  Blocks of one XCD are
 // dispatched in order, so the lowest cluster not yet complete always gets
-// its members.  Every wait is bounded: after kClusterTimeout a member raises
-// the cluster's error flag, every later barrier of the cluster returns at
-// once, and the solve reports HENRY_STATUS_SYNC.
+// its members.  Every wait is bounded (Launch::cluster_wait, 10 s by
+// default): past it a member raises the cluster's error flag, every later
+// barrier of the cluster returns at once, and the solve reports
+// HENRY_STATUS_SYNC.
 struct ClusterState {
     int K, member, base, size;
-    unsigned* ctr;   // arrivals (K per barrier)
+    unsigned* flags; // [K] barriers each member has arrived at
     unsigned* err;   // sticky error flag
     double* slots;   // [2K] partial norms
     unsigned gen;    // barriers passed
     int local;       // all members on one XCD
     int failed;
+    uint64_t wait;   // bound of one wait (wall-clock ticks)
 };
 __shared__ ClusterState g_cl;
 
-constexpr uint64_t kClusterTimeout = 1000000000ull;  // 10 s of the 100 MHz wall clock
-
 __device__ inline int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)); }
 
-// Workgroup 0 of a cluster waits until all K members have arrived; all
+// Every workgroup of a cluster waits until all K members have arrived; all
 // memory operations before the call are visible to every member after it.
+// Wavefront 0 publishes the member's arrival count and polls the K counts
+// with one load per lane.
 __device__ inline void cluster_barrier() {
     __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached L2
     __syncthreads();
-    if (threadIdx.x == 0) {
-        g_cl.gen += 1u;
-        const unsigned target = g_cl.gen * (unsigned)g_cl.K;
+    if (threadIdx.x < kWave) {
+        const int lane = (int)threadIdx.x;
+        const unsigned gen = g_cl.gen + 1u;
         if (!g_cl.failed) {
-            if (g_cl.local) __hip_atomic_fetch_add(g_cl.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else __hip_atomic_fetch_add(g_cl.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) {
+                if (g_cl.local) __hip_atomic_store(g_cl.flags + g_cl.member, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else __hip_atomic_store(g_cl.flags + g_cl.member, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const unsigned* f = g_cl.flags + (lane < g_cl.K ? lane : 0);
             const uint64_t t0 = wall_clock64();
-            while ((int)(__hip_atomic_load(g_cl.ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+            bool failed = false;
+            while (true) {
+                const unsigned v = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (__all((int)(v - gen) >= 0)) break;
                 if (__hip_atomic_load(g_cl.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                    wall_clock64() - t0 > kClusterTimeout) {
-                    __hip_atomic_store(g_cl.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    g_cl.failed = 1;
+                    wall_clock64() - t0 > g_cl.wait) {
+                    failed = true;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+            if (failed && lane == 0) {
+                __hip_atomic_store(g_cl.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                g_cl.failed = 1;
+            }
         }
+        if (lane == 0) g_cl.gen = gen;
     }
     __syncthreads();
 }
@@ -372,19 +408,20 @@ struct ClusterTeam {
 __device__ inline void cluster_init_single() {
     if (threadIdx.x == 0) {
         g_cl.K = 1; g_cl.member = 0; g_cl.base = 0; g_cl.size = (int)blockDim.x;
-        g_cl.ctr = nullptr; g_cl.err = nullptr; g_cl.slots = nullptr;
-        g_cl.gen = 0u; g_cl.local = 1; g_cl.failed = 0;
+        g_cl.flags = nullptr; g_cl.err = nullptr; g_cl.slots = nullptr;
+        g_cl.gen = 0u; g_cl.local = 1; g_cl.failed = 0; g_cl.wait = 0;
     }
     __syncthreads();
 }
 
 // Binds member `member` of a K-cluster to the cluster state in the solve's
 // scratch `sp` and checks the members' placement.
-__device__ inline void cluster_init(int K, int member, double* sp) {
+__device__ inline void cluster_init(int K, int member, double* sp, uint64_t wait) {
     if (threadIdx.x == 0) {
+        g_cl.wait = wait;
         g_cl.K = K; g_cl.member = member; g_cl.base = member * (int)blockDim.x; g_cl.size = K * (int)blockDim.x;
-        g_cl.ctr = reinterpret_cast<unsigned*>(sp + kClusterCtr);
-        g_cl.err = g_cl.ctr + 1;
+        g_cl.flags = reinterpret_cast<unsigned*>(sp + kClusterFlags);
+        g_cl.err = reinterpret_cast<unsigned*>(sp + kClusterErr);
         g_cl.slots = sp + kClusterSlots;
         g_cl.gen = (unsigned)sp[kClusterGen];
         g_cl.local = 0;  // the placement check itself uses the agent-scope protocol
@@ -682,38 +719,39 @@ __device__ void coarsen_transport_level(const Level<T>& F0, Level<T>& C0) {
     }
 }
 
+template <typename T, bool kTransport, class Team, int ASF, int ASC>
+__device__ void coarsen_level(const Level<T>& F, Level<T>& C) {
+    if constexpr (kTransport) coarsen_transport_level<T, Team, ASF, ASC>(F, C);
+    else coarsen_pressure_level<T, Team, ASF, ASC>(F, C);
+}
+
 // Re-discretised coarse coefficients.  The cluster forms levels 1 .. lc
-// (from cluster levels; no barrier after the last, whose next reader, the
-// leader's part of the V-cycle, comes after the restriction's barrier).
+// (from cluster levels; level lc into its global copy when the leader runs
+// it in LDS; no barrier after the last, whose next reader, the leader's
+// part of the V-cycle, comes after the restriction's barrier).
 template <typename T, bool kTransport>
 __device__ void coarsen_cluster(Solve<T>& S) {
     for (int l = 1; l <= S.lc; ++l) {
         if (l > 1) ClusterTeam::sync();
-        if constexpr (kTransport) coarsen_transport_level<T, ClusterTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
-        else coarsen_pressure_level<T, ClusterTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
+        coarsen_level<T, kTransport, ClusterTeam, 1, 1>(S.lv[l - 1], (S.hand && l == S.lc) ? S.hg : S.lv[l]);
     }
 }
 
 // Levels `from` .. L-1, run by the leader alone: its workgroup forms the
-// levels whose finer neighbour is in global memory, wavefront 0 the rest
-// (LDS levels, from LDS levels).
+// levels whose finer neighbour is in global memory or in the workgroup's
+// part of LDS, wavefront 0 the rest (LDS levels, from LDS levels).
 template <typename T, bool kTransport>
 __device__ void coarsen_leader(Solve<T>& S, int from) {
-    const int lw = S.lds_from;
+    const int lw = S.lds_from, lb = S.lb;
     for (int l = from > 1 ? from : 1; l < S.L && l <= lw; ++l) {
-        if (l < lw) {
-            if constexpr (kTransport) coarsen_transport_level<T, BlockTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
-            else coarsen_pressure_level<T, BlockTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
-        } else {
-            if constexpr (kTransport) coarsen_transport_level<T, BlockTeam, 1, 3>(S.lv[l - 1], S.lv[l]);
-            else coarsen_pressure_level<T, BlockTeam, 1, 3>(S.lv[l - 1], S.lv[l]);
-        }
+        if (l < lb) coarsen_level<T, kTransport, BlockTeam, 1, 1>(S.lv[l - 1], S.lv[l]);
+        else if (l == lb) coarsen_level<T, kTransport, BlockTeam, 1, 3>(S.lv[l - 1], S.lv[l]);
+        else coarsen_level<T, kTransport, BlockTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
         __syncthreads();
     }
     if (threadIdx.x < kWave) {
         for (int l = (from > lw + 1 ? from : lw + 1); l < S.L; ++l) {
-            if constexpr (kTransport) coarsen_transport_level<T, WaveTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
-            else coarsen_pressure_level<T, WaveTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
+            coarsen_level<T, kTransport, WaveTeam, 3, 3>(S.lv[l - 1], S.lv[l]);
             WaveTeam::sync();
         }
     }
@@ -1206,27 +1244,63 @@ struct PhaseClock {
 template <typename T, bool kTransport, bool kTrans, class Team, int AS, int ASN>
 __device__ void vdown(Solve<T>& S, int l) {
     Level<T>& v = S.lv[l];
+    Level<T>& c = (S.hand && l + 1 == S.lc) ? S.hg : S.lv[l + 1];
     if constexpr (kTransport) line_smooth<T, kTrans, Team, AS>(v, false);
     else rbgs<T, Team, AS>(v, 2);
     level_residual<T, kTransport, kTrans, Team, AS>(v);
     Team::sync();
-    restrict_residual<T, Team, AS, ASN, !kTransport>(v, S.lv[l + 1]);
+    restrict_residual<T, Team, AS, ASN, !kTransport>(v, c);
     Team::sync();
 }
 
 // Upward leg on level l: prolongation from level l+1, smooth.  The
-// transport post-smoothing takes y-lines on the LDS levels and x-lines on
-// the levels in global memory: there a y-line sweep costs about three x-line
-// sweeps (the rows of a column are a cache line apart), and the outer
-// iteration counts stay the same (1.69 per step on 256x128/800 either way);
-// the cycle still relaxes along y on every level of 512 cells or fewer.
+// transport post-smoothing takes y-lines on the levels wavefront 0 runs and
+// x-lines on the larger ones: in global memory a y-line sweep costs about
+// three x-line sweeps (the rows of a column are a cache line apart), and
+// the outer iteration counts stay the same (1.69 per step on 256x128/800
+// either way); the cycle still relaxes along y on every level of 512 cells
+// or fewer.
 template <typename T, bool kTransport, bool kTrans, class Team, int AS, int ASN>
 __device__ void vup(Solve<T>& S, int l) {
     Level<T>& v = S.lv[l];
-    prolong_add<T, Team, ASN, AS, !kTransport>(S.lv[l + 1], v);
+    const Level<T>& c = (S.hand && l + 1 == S.lc) ? S.hg : S.lv[l + 1];
+    prolong_add<T, Team, ASN, AS, !kTransport>(c, v);
     Team::sync();
-    if constexpr (kTransport) line_smooth<T, kTrans, Team, AS>(v, AS == 3);
+    if constexpr (kTransport) line_smooth<T, kTrans, Team, AS>(v, std::is_same<Team, WaveTeam>::value);
     else rbgs<T, Team, AS>(v, 2);
+}
+
+// Level lc between the cluster and the leader's LDS (S.hand): the leader
+// copies what the cluster formed in the level's global copy (coefficients,
+// restricted right-hand side) into LDS before its part of the cycle, and
+// the correction x back afterwards.
+template <typename T, bool kTransport>
+__device__ void handoff_in(Solve<T>& S) {
+    const Level<T>& G = S.hg;
+    const LV<T, 3> D(S.lv[S.lc]);
+    const int n = G.nx * G.ny;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        D.b[i] = G.b[i];
+        D.x[i] = (T)0;
+        if constexpr (kTransport) {
+            D.acc[i] = G.acc[i]; D.mx[i] = G.mx[i]; D.my[i] = G.my[i]; D.dx[i] = G.dx[i]; D.dy[i] = G.dy[i];
+        } else {
+            D.te[i] = G.te[i]; D.tn[i] = G.tn[i];
+        }
+    }
+    if constexpr (kTransport) {
+        for (int j = threadIdx.x; j < G.ny; j += blockDim.x) {
+            D.dl[j] = G.dl[j]; D.dr[j] = G.dr[j]; D.mr[j] = G.mr[j]; D.ml[j] = G.ml[j];
+        }
+    }
+}
+
+template <typename T>
+__device__ void handoff_out(Solve<T>& S) {
+    const LV<T, 3> D(S.lv[S.lc]);
+    Level<T>& G = S.hg;
+    const int n = G.nx * G.ny;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) G.x[i] = D.x[i];
 }
 
 // The coarsest level of every hierarchy has one row (ny = 1, nx = 2): the
@@ -1265,11 +1339,17 @@ __device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr, bool coarse_coeffs
         vdown<T, kTransport, kTrans, ClusterTeam, 1, 1>(S, l);
         if (pc) pc->tick(t0 + (l == 0 ? 1 : 2));
     }
+    const int lb = S.lb;
     if (g_cl.member == 0) {
+        if (S.hand) {
+            handoff_in<T, kTransport>(S);
+            __syncthreads();
+        }
         if (coarse_coeffs) coarsen_leader<T, kTransport>(S, lc + 1);
         for (int l = lc; l < lw; ++l) {
-            if (l + 1 < lw) vdown<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
-            else vdown<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+            if (l + 1 < lb) vdown<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
+            else if (l < lb) vdown<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+            else vdown<T, kTransport, kTrans, BlockTeam, 3, 3>(S, l);
             if (pc) pc->tick(t0 + (l == 0 ? 1 : 2));
         }
         if (threadIdx.x < kWave) {
@@ -1280,10 +1360,12 @@ __device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr, bool coarse_coeffs
         __syncthreads();
         if (pc) pc->tick(t0 + 3);
         for (int l = lw - 1; l >= lc; --l) {
-            if (l + 1 < lw) vup<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
-            else vup<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+            if (l + 1 < lb) vup<T, kTransport, kTrans, BlockTeam, 1, 1>(S, l);
+            else if (l < lb) vup<T, kTransport, kTrans, BlockTeam, 1, 3>(S, l);
+            else vup<T, kTransport, kTrans, BlockTeam, 3, 3>(S, l);
             if (pc) pc->tick(t0 + (l == 0 ? 6 : 4));
         }
+        if (S.hand) handoff_out(S);
     }
     if (lc > 0) {
         ClusterTeam::sync();
@@ -1412,7 +1494,7 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
     const int s_end = (int)(((int64_t)lp.g_end * d.nsteps) / lp.g_total);
     if (s_begin >= s_end) return;
     if (threadIdx.x == 0) {
-        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells);
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells, lp.lds_block_cells);
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
         // cluster levels: at least level 0, then every level of >= 2048 K
@@ -1424,10 +1506,11 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
             while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 2048 * lp.cluster) ++lc;
         }
         S.lc = lc;
+        S.hand = lc > 0 && lc == S.lb;  // cluster levels (>= 4096 cells) never are in LDS: lc <= lb
     }
     __syncthreads();
     double* sp = S.scratch;
-    if (lp.cluster > 1) cluster_init(lp.cluster, member, sp);
+    if (lp.cluster > 1) cluster_init(lp.cluster, member, sp, lp.cluster_wait);
     else cluster_init_single();
     const int n = S.n;
     // scratch: [0] = q, [1] = status, [2] = iterations, [3] = converged
@@ -1528,8 +1611,7 @@ __global__ void henry_fields_kernel(Launch lp) {
     }
     // a fresh cluster state for the solve's first launch
     if (threadIdx.x == 0) {
-        sp[kClusterCtr] = 0.0;
-        sp[kClusterGen] = 0.0;
+        for (int k = kClusterFlags; k <= kClusterGen; ++k) sp[k] = 0.0;
     }
     __syncthreads();
     // face coefficients (harmonic means) and the residual scale

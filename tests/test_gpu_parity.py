@@ -167,6 +167,21 @@ def test_cluster_sizes_are_bitwise_equal(torch_cuda, ctx, prec):
             assert torch.equal(out[key], ref[key]), (K, spl, key)
 
 
+def test_cluster_wait_bound_reports_sync_status(torch_cuda, ctx):
+    """A cluster whose members wait longer than opts.cluster_wait_us at a
+    barrier stops (every later barrier returns at once) and reports
+    HENRY_STATUS_SYNC; here the bound (1 us) is below the time the members
+    spend waiting for the leader's coarse levels.  The next call starts from
+    a fresh cluster state and converges."""
+    torch = torch_cuda
+    solves = [(256, 128, 160), (16, 8, 50)]
+    xi = hm.henry_sample_xi(0, 10, 0, len(solves), 3)
+    bad = run(torch, ctx, solves, xi, hm.PREC_MIXED, tol=1e-9, cluster=4, cluster_wait_us=1)
+    assert list(bad["status"].cpu().numpy()) == [hm.STATUS_SYNC, hm.STATUS_OK]
+    good = run(torch, ctx, solves, xi, hm.PREC_MIXED, tol=1e-9, cluster=4)
+    assert list(good["status"].cpu().numpy()) == [hm.STATUS_OK] * 2
+
+
 def test_cluster_solve_matches_oracle(torch_cuda, ctx):
     solves = [(128, 64, 40)]
     xi = hm.henry_sample_xi(0, 8, 0, 1, 3)
