@@ -162,7 +162,12 @@ int64_t desc_bytes(int nsolves) { return henry::align256((int64_t)nsolves * (int
 // Fork from `s0`, launch every group (fields kernel, then the solve kernel
 // over lockstep chunks of `steps_per_launch` global steps, or one launch),
 // join back into `s0`.  Groups run concurrently on the context's streams
-// unless `serial`.
+// unless `serial`.  Groups whose solves are shared by clusters all take
+// stream 0, one after another: two cluster launches side by side could each
+// hold CUs for partly dispatched clusters and wait on each other (the waits
+// are bounded, but the solves would report HENRY_STATUS_SYNC).  The groups
+// of one workgroup per solve never wait; they take the other streams in
+// turn, so none of them queues behind a cluster group.
 int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::vector<int>& gstart,
                    const henry_grid_t* solves, const henry_opts_t* o, const henry::Launch& lp,
                    henry::SolveDesc* dtable, int rmax, hipStream_t s0, bool serial, bool profile) {
@@ -173,13 +178,18 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
     if (hipEventRecord(ctx->fork, s0) != hipSuccess) return HENRY_EHIP;
     for (int k = 0; k < nstreams; ++k)
         if (hipStreamWaitEvent(ctx->streams[k], ctx->fork, 0) != hipSuccess) return HENRY_EHIP;
+    bool any_cluster = false;
+    for (const Group& G : order) any_cluster |= G.cluster > 1;
+    const int first = any_cluster && nstreams > 1 ? 1 : 0;  // streams of the single-workgroup groups
+    int next = 0;
     for (int gi = 0; gi < ng; ++gi) {
         const Group& G = order[gi];
-        hipStream_t st = serial ? s0 : ctx->streams[gi % kStreams];
+        const int K = G.cluster;
+        const int si = K > 1 || nstreams == 0 ? 0 : first + (next++ % (nstreams - first));
+        hipStream_t st = serial ? s0 : ctx->streams[si];
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
-        const int K = G.cluster;
         const int nblk = K == 1 ? nb : (nb + 7) / 8 * 8 * K;  // see henry::cluster_of_block
         l.nsolves = nb;
         l.cluster = K;

@@ -167,6 +167,23 @@ def test_cluster_sizes_are_bitwise_equal(torch_cuda, ctx, prec):
             assert torch.equal(out[key], ref[key]), (K, spl, key)
 
 
+def test_two_cluster_groups_in_one_batch(torch_cuda, ctx):
+    """Two grid groups shared by clusters (512x256 on 8 workgroups, 256x128
+    on 4) and a group of one workgroup per solve in one call: the cluster
+    groups run one after the other, and every solve equals its
+    one-workgroup result bitwise."""
+    torch = torch_cuda
+    solves = [(512, 256, 100), (256, 128, 160), (256, 128, 160), (16, 8, 50)]
+    xi = hm.henry_sample_xi(0, 11, 0, len(solves), 3)
+    ref = run(torch, ctx, solves, xi, hm.PREC_MIXED, tol=1e-7, cluster=1)
+    out = run(torch, ctx, solves, xi, hm.PREC_MIXED, tol=1e-7, profile=1)
+    groups = {(g["nx"], g["cluster"]) for g in hm.henry_profile_last(ctx)}
+    assert {(512, 8), (256, 4), (16, 1)} <= groups, groups
+    assert list(out["status"].cpu().numpy()) == [hm.STATUS_OK] * len(solves)
+    for key in ("c", "p", "qoi", "status", "iters"):
+        assert torch.equal(out[key], ref[key]), key
+
+
 def test_cluster_wait_bound_reports_sync_status(torch_cuda, ctx):
     """A cluster whose members wait longer than opts.cluster_wait_us at a
     barrier stops (every later barrier returns at once) and reports
