@@ -945,18 +945,17 @@ __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
 // Pressure: red cells, the first half of each row of the colour-split
 // layout; transport: the even rows.
 constexpr int kRBatch = 2;
-template <typename T, bool kTransport, bool kTrans = false, class Team = BlockTeam, int AS = 0>
-__device__ void level_residual(Level<T>& v0) {
-    const LV<T, AS> v(v0);
+template <typename T, bool kTransport, bool kTrans, class Team, int AS, int KB>
+__device__ inline void level_residual_kb(const LV<T, AS>& v) {
     const int half = v.nx >> 1;
     const int n = kTransport ? v.nx * ((v.ny + 1) >> 1) : half * v.ny;  // live cells
     const int ts = Team::size();
     const int sx = log2i(v.nx);
-    for (int k0 = Team::rank(); k0 < n; k0 += kRBatch * ts) {
-        T res[kRBatch];
-        int at[kRBatch];
+    for (int k0 = Team::rank(); k0 < n; k0 += KB * ts) {
+        T res[KB];
+        int at[KB];
 #pragma unroll
-        for (int u = 0; u < kRBatch; ++u) {
+        for (int u = 0; u < KB; ++u) {
             const int k = k0 + u * ts;
             const int kk = k < n ? k : 0;
             int i, j, idx;
@@ -984,9 +983,18 @@ __device__ void level_residual(Level<T>& v0) {
             res[u] = bP - ax;
         }
 #pragma unroll
-        for (int u = 0; u < kRBatch; ++u)
+        for (int u = 0; u < KB; ++u)
             if (k0 + u * ts < n) v.r[at[u]] = res[u];
     }
+}
+
+// One cell per thread when one pass of the team covers the live cells.
+template <typename T, bool kTransport, bool kTrans = false, class Team = BlockTeam, int AS = 0>
+__device__ void level_residual(Level<T>& v0) {
+    const LV<T, AS> v(v0);
+    const int n = kTransport ? v.nx * ((v.ny + 1) >> 1) : (v.nx >> 1) * v.ny;
+    if (n <= Team::size()) level_residual_kb<T, kTransport, kTrans, Team, AS, 1>(v);
+    else level_residual_kb<T, kTransport, kTrans, Team, AS, kRBatch>(v);
 }
 
 // ------------------------------------------------------------------ smoothers
@@ -995,9 +1003,9 @@ __device__ void level_residual(Level<T>& v0) {
 // before it writes any of them, so their loads are in flight together.
 constexpr int kBatch = 4;
 
-template <typename T, class Team = BlockTeam, int AS = 0>
-__device__ void rbgs(Level<T>& v0, int sweeps) {
-    const LV<T, AS> v(v0);
+// One half-sweep (colour col) with KB cells gathered per thread.
+template <typename T, class Team, int AS, int KB>
+__device__ inline void rbgs_colour(const LV<T, AS>& v, int col) {
     const int nx = v.nx, ny = v.ny;
     const int half = nx >> 1;  // nx is even on every level
     const int sh = log2i(half);
@@ -1006,36 +1014,48 @@ __device__ void rbgs(Level<T>& v0, int sweeps) {
     const auto tn = v.tn;
     const auto b = v.b;
     const auto x = v.x;
+    for (int k0 = Team::rank(); k0 < m; k0 += KB * Team::size()) {
+        T num[KB], den[KB];
+        int at[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int k = k0 + u * Team::size();
+            const int kk = k < m ? k : 0;
+            const int j = kk >> sh;
+            const int i = 2 * (kk & (half - 1)) + ((j + col) & 1);
+            const NbS q(i, j, nx, ny);  // q.idx = j nx + col half + (kk mod half)
+            at[u] = k < m ? q.idx : -1;
+            const T tE = te[q.idx], tWl = te[q.w], tN = tn[q.idx], tSl = tn[q.s];
+            const T xW = x[q.w], xE = x[q.e], xS = x[q.s], xN = x[q.n];
+            const T bP = b[q.idx];
+            const T tW = q.hw ? tWl : (T)0, tS = q.hs ? tSl : (T)0;
+            const T tEc = q.he ? tE : (T)0;  // the seawater coefficient is diagonal only
+            T a = bP;
+            a += tW * xW;
+            a += tEc * xE;
+            a += tS * xS;
+            a += tN * xN;
+            num[u] = a;
+            den[u] = tE + tW + tN + tS;
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (at[u] >= 0) x[at[u]] = qdiv(num[u], den[u]);
+    }
+}
+
+// A colour that one pass of the team covers takes one cell per thread
+// (the coarse levels: a fixed batch would issue the loads and arithmetic of
+// kBatch cells per lane for one useful cell or none); larger ones take
+// kBatch.  The cells and their arithmetic are the same either way.
+template <typename T, class Team = BlockTeam, int AS = 0>
+__device__ void rbgs(Level<T>& v0, int sweeps) {
+    const LV<T, AS> v(v0);
+    const bool one = (v.nx >> 1) * v.ny <= Team::size();
     for (int s = 0; s < sweeps; ++s)
         for (int col = 0; col < 2; ++col) {
-            for (int k0 = Team::rank(); k0 < m; k0 += kBatch * Team::size()) {
-                T num[kBatch], den[kBatch];
-                int at[kBatch];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int k = k0 + u * Team::size();
-                    const int kk = k < m ? k : 0;
-                    const int j = kk >> sh;
-                    const int i = 2 * (kk & (half - 1)) + ((j + col) & 1);
-                    const NbS q(i, j, nx, ny);  // q.idx = j nx + col half + (kk mod half)
-                    at[u] = k < m ? q.idx : -1;
-                    const T tE = te[q.idx], tWl = te[q.w], tN = tn[q.idx], tSl = tn[q.s];
-                    const T xW = x[q.w], xE = x[q.e], xS = x[q.s], xN = x[q.n];
-                    const T bP = b[q.idx];
-                    const T tW = q.hw ? tWl : (T)0, tS = q.hs ? tSl : (T)0;
-                    const T tEc = q.he ? tE : (T)0;  // the seawater coefficient is diagonal only
-                    T a = bP;
-                    a += tW * xW;
-                    a += tEc * xE;
-                    a += tS * xS;
-                    a += tN * xN;
-                    num[u] = a;
-                    den[u] = tE + tW + tN + tS;
-                }
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u)
-                    if (at[u] >= 0) x[at[u]] = qdiv(num[u], den[u]);
-            }
+            if (one) rbgs_colour<T, Team, AS, 1>(v, col);
+            else rbgs_colour<T, Team, AS, kBatch>(v, col);
             Team::sync();
         }
 }
