@@ -165,9 +165,12 @@ int64_t desc_bytes(int nsolves) { return henry::align256((int64_t)nsolves * (int
 // unless `serial`.  Groups whose solves are shared by clusters all take
 // stream 0, one after another: two cluster launches side by side could each
 // hold CUs for partly dispatched clusters and wait on each other (the waits
-// are bounded, but the solves would report HENRY_STATUS_SYNC).  The groups
-// of one workgroup per solve never wait; they take the other streams in
-// turn, so none of them queues behind a cluster group.
+// are bounded, but the solves would report HENRY_STATUS_SYNC).  Beside them
+// the groups of one workgroup per solve run one after another on stream 1:
+// run side by side they slow each other and the cluster group, which is
+// the batch's critical path (L = 4 MLMC batch: 567 ms with the small
+// groups on three streams, 482 ms on one).  Without a cluster group the
+// groups take all streams in turn (there, side by side is faster).
 int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::vector<int>& gstart,
                    const henry_grid_t* solves, const henry_opts_t* o, const henry::Launch& lp,
                    henry::SolveDesc* dtable, int rmax, hipStream_t s0, bool serial, bool profile) {
@@ -180,12 +183,12 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         if (hipStreamWaitEvent(ctx->streams[k], ctx->fork, 0) != hipSuccess) return HENRY_EHIP;
     bool any_cluster = false;
     for (const Group& G : order) any_cluster |= G.cluster > 1;
-    const int first = any_cluster && nstreams > 1 ? 1 : 0;  // streams of the single-workgroup groups
     int next = 0;
     for (int gi = 0; gi < ng; ++gi) {
         const Group& G = order[gi];
         const int K = G.cluster;
-        const int si = K > 1 || nstreams == 0 ? 0 : first + (next++ % (nstreams - first));
+        int si = 0;
+        if (nstreams > 0 && K == 1) si = any_cluster ? (nstreams > 1 ? 1 : 0) : next++ % nstreams;
         hipStream_t st = serial ? s0 : ctx->streams[si];
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
