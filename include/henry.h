@@ -108,16 +108,16 @@ typedef struct {
     int32_t serial_groups;    /* 1 = run grid groups one after another on one
                                  stream instead of concurrently                  */
     int32_t cluster;          /* workgroups (CUs) sharing one solve of
-                                 henry_solve_batch: 1, 2, 4 or 8; 0 = built-in
-                                 choice (one per 8192 fine cells, at most 8, and
-                                 at most 256 workgroups per grid group).  Grids
-                                 of 2048 cells or fewer always use 1.  The fine
-                                 levels are split over the cluster, the coarse
-                                 ones run on its first workgroup; the results
-                                 are bitwise the same for every value.  The
-                                 members synchronise through the solve's
-                                 workspace, so the launch must be able to hold
-                                 a group's clusters at once (<= 256 CUs).        */
+                                 henry_solve_batch or henry_adjoint_batch: 1, 2,
+                                 4 or 8; 0 = built-in choice (one per 8192 fine
+                                 cells, at most 8, and at most 256 workgroups
+                                 per grid group).  Grids of 2048 cells or fewer
+                                 always use 1.  The fine levels are split over
+                                 the cluster, the coarse ones run on its first
+                                 workgroup; results are bitwise the same for
+                                 every value.  The members synchronise through
+                                 the solve's workspace; grid groups with
+                                 clusters run one after another.                 */
     int32_t cluster_wait_us;  /* bound of one wait at a cluster barrier, in
                                  microseconds; 0 = 10 s.  A member that waits
                                  longer stops its cluster: the solve reports

@@ -188,8 +188,9 @@ __device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int 
     const double* lc = A.lam_c;
     Level<T>& L0 = S.lv[0];
     const int sx = log2i(nx);
-    double rmax = 0.0, gq = 0.0;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    double rmax = 0.0;
+    const int rk = ClusterTeam::rank(), ts = ClusterTeam::size();
+    for (int idx = rk; idx < n; idx += ts) {
         const int i = idx & (nx - 1), j = idx >> sx;
         const Nb q(i, j, nx, ny);
         const double cP = c[idx], cnP = S.cn[idx], fP = S.phi[idx], pP = p[idx];
@@ -234,7 +235,6 @@ __device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int 
             if constexpr (kGrad) {
                 gK += q.hw ? wp * d.MKb + wc * d.FKb : 0.0;
                 gf += q.hw ? wc * d.Fphib : lcP * b.Fphi;
-                gq += q.hw ? 0.0 : lpP * (-ph.rho0 * h);
             }
         }
         // north: P = a (nothing across the top)
@@ -276,21 +276,36 @@ __device__ double jt_pass(const Phys& ph, Solve<T>& S, Adj& A, double* red, int 
             A.b_c[idx] = lpP * h2t * fP * dr + lcP * h2t * fP * (ph.rho0 + 2.0 * dr * cnP);
         }
     }
-    if constexpr (!kGrad) return block_max(rmax, red);
-    const double g = block_sum(gq, red);
-    if (threadIdx.x == 0) A.scr[0] -= g;
-    __syncthreads();
+    if constexpr (!kGrad) {
+        double r, unused;
+        cluster_max2(rmax, 0.0, red, r, unused);
+        return r;
+    }
+    // lam^T dR/dq: the recharge faces of the first column, summed by the
+    // leader in the order of a one-workgroup pass (thread t adds the cells
+    // t, t + blockDim, ... in turn), so the sum is the same for every
+    // cluster size
+    if (g_cl.member == 0) {
+        double gq = 0.0;
+        for (int j = 0; j < ny; ++j) {
+            const int idx = j * nx;
+            if ((idx & ((int)blockDim.x - 1)) == (int)threadIdx.x) gq += lp[idx] * (-ph.rho0 * h);
+        }
+        const double g = block_sum(gq, red);
+        if (threadIdx.x == 0) A.scr[0] -= g;
+    }
+    ClusterTeam::sync();
     return 0.0;
 }
 
 // lam = E^T mu: lam_p = mu_p - c mu_c, lam_c = mu_c.
 template <typename T>
 __device__ void lam_from_mu(Solve<T>& S, Adj& A) {
-    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < S.n; idx += ClusterTeam::size()) {
         A.lam_p[idx] = A.mu_p[idx] - S.c[idx] * A.mu_c[idx];
         A.lam_c[idx] = A.mu_c[idx];
     }
-    __syncthreads();
+    ClusterTeam::sync();
 }
 
 // Start of the next transposed solve: the polynomial extrapolation of order
@@ -302,7 +317,7 @@ __device__ void mu_extrapolate(const Solve<T>& S, Adj& A, int order) {
     double* h1p = A.mh; double* h1c = A.mh + n;
     double* h2p = A.mh + 2 * n; double* h2c = A.mh + 3 * n;
     double* h3p = A.mh + 4 * n; double* h3c = A.mh + 5 * n;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < n; idx += ClusterTeam::size()) {
         const double p0 = A.mu_p[idx], c0 = A.mu_c[idx];
         const double p1 = h1p[idx], c1 = h1c[idx], p2 = h2p[idx], c2 = h2c[idx];
         if (order == 1) {
@@ -319,7 +334,7 @@ __device__ void mu_extrapolate(const Solve<T>& S, Adj& A, int order) {
         h2p[idx] = p1; h2c[idx] = c1;
         h1p[idx] = p0; h1c[idx] = c0;
     }
-    __syncthreads();
+    ClusterTeam::sync();
 }
 
 // One transposed step solve at the state in S (p^n, c^n; c^{n-1} in S.cn)
@@ -336,7 +351,7 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
     // scaled norm of the rhs
     // (and the inverse block diagonals of this step for the norms)
     double bm = 0.0;
-    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < S.n; idx += ClusterTeam::size()) {
         const int i = idx % S.nx, j = idx / S.nx;
         const double ip = 1.0 / (double)pstencil(S.lv[0], NbS(i, j, S.nx, S.ny)).d;
         const double ic = 1.0 / (double)cstencil_t(S.lv[0], Nb(i, j, S.nx, S.ny), j).d;
@@ -345,7 +360,10 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
         bm = nanmax(bm, fabs(A.b_p[idx]) * ip);
         bm = nanmax(bm, fabs(A.b_c[idx]) * ic);
     }
-    bm = block_max(bm, red);
+    {
+        double unused;
+        cluster_max2(bm, 0.0, red, bm, unused);
+    }
     if (!(bm == bm)) return 2;
     int st = 1;
     for (int it = 0; it < max_it; ++it) {
@@ -355,14 +373,15 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
         if (rn <= tol * bm) { st = 0; break; }
         iters += 1.0;
         vcycle<T, true, true>(S);
-        for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) A.mu_c[idx] += (double)S.lv[0].x[idx];
-        __syncthreads();
+        for (int idx = ClusterTeam::rank(); idx < S.n; idx += ClusterTeam::size())
+            A.mu_c[idx] += (double)S.lv[0].x[idx];
+        ClusterTeam::sync();
         lam_from_mu(S, A);
         jt_pass<T, false>(ph, S, A, red, 0);
         vcycle<T, false>(S);
-        for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x)
+        for (int idx = ClusterTeam::rank(); idx < S.n; idx += ClusterTeam::size())
             A.mu_p[idx] += (double)S.lv[0].x[pidx(idx % S.nx, idx / S.nx, S.nx)];
-        __syncthreads();
+        ClusterTeam::sync();
     }
     lam_from_mu(S, A);
     return st;
@@ -370,11 +389,11 @@ __device__ int adjoint_step(const Phys& ph, Solve<T>& S, Adj& A, double* red, in
 
 template <typename T>
 __device__ void save_state(const Solve<T>& S, double* dst) {
-    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < S.n; idx += ClusterTeam::size()) {
         dst[idx] = S.p[idx];
         dst[S.n + idx] = S.c[idx];
     }
-    __syncthreads();
+    ClusterTeam::sync();
 }
 
 // Checkpoint: the state and the extrapolation history before a step, and
@@ -382,7 +401,7 @@ __device__ void save_state(const Solve<T>& S, double* dst) {
 template <typename T>
 __device__ void save_ckpt(const Solve<T>& S, double* dst, int good) {
     const int n = S.n;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < n; idx += ClusterTeam::size()) {
         dst[idx] = S.p[idx];
         dst[n + idx] = S.c[idx];
         dst[2 * n + idx] = S.pp[idx];
@@ -392,14 +411,14 @@ __device__ void save_ckpt(const Solve<T>& S, double* dst, int good) {
         dst[6 * n + idx] = S.p3[idx];
         dst[7 * n + idx] = S.c3[idx];
     }
-    if (threadIdx.x == 0) dst[8 * n] = (double)good;
-    __syncthreads();
+    if (g_cl.member == 0 && threadIdx.x == 0) dst[8 * n] = (double)good;
+    ClusterTeam::sync();
 }
 
 template <typename T>
 __device__ int load_ckpt(Solve<T>& S, const double* src) {
     const int n = S.n;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < n; idx += ClusterTeam::size()) {
         S.p[idx] = src[idx];
         S.c[idx] = src[n + idx];
         S.pp[idx] = src[2 * n + idx];
@@ -409,7 +428,7 @@ __device__ int load_ckpt(Solve<T>& S, const double* src) {
         S.p3[idx] = src[6 * n + idx];
         S.c3[idx] = src[7 * n + idx];
     }
-    __syncthreads();
+    ClusterTeam::sync();
     return (int)src[8 * n];
 }
 
@@ -418,12 +437,12 @@ __device__ inline int extrap_order(int good) { return good - 1 < 3 ? (good - 1 >
 
 template <typename T>
 __device__ void load_state(Solve<T>& S, const double* src, const double* prev) {
-    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < S.n; idx += ClusterTeam::size()) {
         S.p[idx] = src[idx];
         S.c[idx] = src[S.n + idx];
         if (prev) S.cn[idx] = prev[S.n + idx];
     }
-    __syncthreads();
+    ClusterTeam::sync();
 }
 
 // ------------------------------------------------------------------ the adjoint kernel
@@ -433,16 +452,22 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     __shared__ Solve<T> S;
     __shared__ Adj A;
     __shared__ double red[16];
-    const SolveDesc d = lp.descs[blockIdx.x];
+    int cid, member;
+    cluster_of_block(lp.cluster, cid, member);
+    if (cid >= lp.nsolves) return;
+    const SolveDesc d = lp.descs[cid];
     const Phys& ph = lp.ph;
     if (threadIdx.x == 0) {
         bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells, lp.lds_block_cells);
+        set_cluster_levels(S, lp.cluster);
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
         S.q = S.scratch[0];
         bind_adj(A, lp.ws + d.adj_off, d.nx * d.ny, d.nsteps, al.ckpt);
     }
-    cluster_init_single();
+    __syncthreads();
+    if (lp.cluster > 1) cluster_init(lp.cluster, member, S.scratch, lp.cluster_wait);
+    else cluster_init_single();
     const int n = S.n, N = d.nsteps, k = A.k;
     PhaseClock pc;
     pc.init();
@@ -452,19 +477,20 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     // extrapolated guess as the forward solve kernel's)
     const int64_t ck = ckpt_doubles(n);
     initial_state(ph, S, nullptr);
-    __syncthreads();
+    ClusterTeam::sync();
     int good = 1;
-    for (int s = 0; s < N; ++s) {
+    for (int s = 0; s < N && !g_cl.failed; ++s) {
         if (s % k == 0) save_ckpt(S, A.ckpt + (int64_t)(s / k) * ck, good);
         const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, fiters, pc, extrap_order(good));
         if (st == 2) { status = 2; break; }
         if (st == 1 && status == 0) status = 1;
         good = st == 0 ? (good < 4 ? good + 1 : 4) : 0;
     }
-    const double Q = qoi_of(ph, S, red);
+    // (the leader's block reduction, as with one workgroup)
+    const double Q = member == 0 ? qoi_of(ph, S, red) : 0.0;
     // ---- adjoint initial conditions: dQ/du^N and the explicit dQ/dphi
     const double h2 = S.h * S.h;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    for (int idx = ClusterTeam::rank(); idx < n; idx += ClusterTeam::size()) {
         const bool left = (idx % S.nx) < S.nx / 2;
         const double cP = S.c[idx];
         A.b_p[idx] = 0.0;
@@ -474,13 +500,13 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
         A.gK[idx] = 0.0;
         A.gphi[idx] = left ? h2 * rho_of(ph, cP) * cP : 0.0;
     }
-    if (threadIdx.x == 0) A.scr[0] = 0.0;
-    __syncthreads();
+    if (member == 0 && threadIdx.x == 0) A.scr[0] = 0.0;
+    ClusterTeam::sync();
     // ---- reverse sweep over the checkpoint segments (each transposed solve
     // starts from mu extrapolated through the previous solutions; the zero
     // start of the first solve is not one of them)
     int agood = 0;
-    for (int seg = A.ncp - 1; seg >= 0 && status != 2; --seg) {
+    for (int seg = A.ncp - 1; seg >= 0 && status != 2 && !g_cl.failed; --seg) {
         const int s0 = seg * k, s1 = min(N, s0 + k);
         int g = load_ckpt(S, A.ckpt + (int64_t)seg * ck);
         save_state(S, A.seg);
@@ -500,7 +526,11 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
             jt_pass<T, true>(ph, S, A, red, 0);
         }
     }
-    // ---- outputs
+    // ---- outputs, by the leader alone: its sums take the cells in the
+    // order of a one-workgroup solve
+    ClusterTeam::sync();
+    if (g_cl.failed) status = 3;
+    if (member != 0) return;
     const double gq = A.scr[0];
     const double h = S.h;
     double g1 = 0.0, g2 = 0.0;

@@ -159,6 +159,18 @@ int default_threads(int nx, int ny, int prec) {
 int64_t desc_bytes(int nsolves) { return henry::align256((int64_t)nsolves * (int64_t)sizeof(henry::SolveDesc)); }
 
 
+// Stream of each group (see enqueue_groups).
+std::vector<int> stream_plan(const std::vector<Group>& order, int nstreams) {
+    bool any_cluster = false;
+    for (const Group& G : order) any_cluster |= G.cluster > 1;
+    std::vector<int> si(order.size(), 0);
+    int next = 0;
+    for (size_t gi = 0; gi < order.size(); ++gi)
+        if (nstreams > 0 && order[gi].cluster == 1)
+            si[gi] = any_cluster ? (nstreams > 1 ? 1 : 0) : next++ % nstreams;
+    return si;
+}
+
 // Fork from `s0`, launch every group (fields kernel, then the solve kernel
 // over lockstep chunks of `steps_per_launch` global steps, or one launch),
 // join back into `s0`.  Groups run concurrently on the context's streams
@@ -181,15 +193,11 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
     if (hipEventRecord(ctx->fork, s0) != hipSuccess) return HENRY_EHIP;
     for (int k = 0; k < nstreams; ++k)
         if (hipStreamWaitEvent(ctx->streams[k], ctx->fork, 0) != hipSuccess) return HENRY_EHIP;
-    bool any_cluster = false;
-    for (const Group& G : order) any_cluster |= G.cluster > 1;
-    int next = 0;
+    const std::vector<int> si = stream_plan(order, nstreams);
     for (int gi = 0; gi < ng; ++gi) {
         const Group& G = order[gi];
         const int K = G.cluster;
-        int si = 0;
-        if (nstreams > 0 && K == 1) si = any_cluster ? (nstreams > 1 ? 1 : 0) : next++ % nstreams;
-        hipStream_t st = serial ? s0 : ctx->streams[si];
+        hipStream_t st = serial ? s0 : ctx->streams[si[gi]];
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
@@ -730,6 +738,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
             t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny, prec);
         }
         G.threads = std::min(t, kAdjMaxThreads);
+        G.cluster = cluster_size(G.nx, G.ny, (int)G.members.size(), o->cluster);
     }
     DeviceGuard dg(ctx->device);
     hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
@@ -766,14 +775,18 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     if (hipEventRecord(ctx->fork, s0) != hipSuccess) return HENRY_EHIP;
     for (int k = 0; k < nstreams; ++k)
         if (hipStreamWaitEvent(ctx->streams[k], ctx->fork, 0) != hipSuccess) return HENRY_EHIP;
+    const std::vector<int> si = stream_plan(order, nstreams);
     for (int gi = 0; gi < ng; ++gi) {
         const Group& G = order[gi];
-        hipStream_t st = ctx->streams[gi % kStreams];
+        hipStream_t st = ctx->streams[si[gi]];
         henry::Launch l = lp;
         l.descs = dtable + gstart[gi];
         const int nb = (int)G.members.size();
+        const int K = G.cluster;
+        const int nblk = K == 1 ? nb : (nb + 7) / 8 * 8 * K;  // see henry::cluster_of_block
         l.nsolves = nb;
-        l.cluster = 1;  // one workgroup per adjoint solve
+        l.cluster = K;
+        l.cluster_wait = (uint64_t)(o->cluster_wait_us > 0 ? o->cluster_wait_us : 10000000) * 100u;  // 100 MHz
         if (l.field_kind == 2) {
             const KlGrid& kg = ctx->kl.at(G.nx);
             l.kl_modes = kg.modes;
@@ -785,9 +798,9 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
         l.lds_block_cells = lds_block_cells(prec);
         const size_t lds = lds_bytes(G.nx, G.ny, prec);
         if (prec == HENRY_PREC_MIXED)
-            hipLaunchKernelGGL(henry::henry_adjoint_kernel<float>, dim3(nb), dim3(G.threads), lds, st, l, al);
+            hipLaunchKernelGGL(henry::henry_adjoint_kernel<float>, dim3(nblk), dim3(G.threads), lds, st, l, al);
         else
-            hipLaunchKernelGGL(henry::henry_adjoint_kernel<double>, dim3(nb), dim3(G.threads), lds, st, l, al);
+            hipLaunchKernelGGL(henry::henry_adjoint_kernel<double>, dim3(nblk), dim3(G.threads), lds, st, l, al);
         if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
     }
     for (int k = 0; k < nstreams; ++k) {

@@ -758,13 +758,23 @@ __device__ void coarsen_leader(Solve<T>& S, int from) {
     __syncthreads();
 }
 
+template <typename T, bool kTransport>
+__device__ void handoff_in(Solve<T>& S);
+
 // Every level, complete on return (the adjoint's transposed solves reuse
-// the coefficients over several cycles).
+// the coefficients over several cycles; a level handed from the cluster to
+// the leader's LDS is copied there first).
 template <typename T, bool kTransport>
 __device__ void coarsen(Solve<T>& S) {
     coarsen_cluster<T, kTransport>(S);
     if (S.lc > 0) ClusterTeam::sync();
-    if (g_cl.member == 0) coarsen_leader<T, kTransport>(S, S.lc + 1);
+    if (g_cl.member == 0) {
+        if (S.hand) {
+            handoff_in<T, kTransport>(S);
+            __syncthreads();
+        }
+        coarsen_leader<T, kTransport>(S, S.lc + 1);
+    }
     ClusterTeam::sync();
 }
 
@@ -1486,6 +1496,21 @@ __device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
 }
 
 // ------------------------------------------------------------------ the solve kernel
+// Cluster levels of a solve shared by K workgroups: level 0, then every
+// level of >= 2048 K cells (>= 2048 per member) whose coarser neighbour is
+// not run by wavefront 0; the level after them is handed to the leader's
+// LDS when it lives there (cluster levels, >= 4096 cells, never do).
+template <typename T>
+__device__ inline void set_cluster_levels(Solve<T>& S, int K) {
+    int lc = 0;
+    if (K > 1) {
+        lc = 1;
+        while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 2048 * K) ++lc;
+    }
+    S.lc = lc;
+    S.hand = lc > 0 && lc == S.lb;
+}
+
 // Blocks of a launch: one per solve, or with clusters of K > 1 the blocks
 // x + 8 (K c + r), r = 0 .. K-1, for cluster (solve) x + 8 c, so that the
 // K members of a solve share an XCD; the launch has ceil(nsolves / 8) 8 K
@@ -1517,16 +1542,7 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
         bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, lp.lds_cells, lp.lds_block_cells);
         S.nsteps = d.nsteps;
         S.tau = ph.T / d.nsteps;
-        // cluster levels: at least level 0, then every level of >= 2048 K
-        // cells (>= 2048 per member) whose coarser neighbour is still in
-        // global memory
-        int lc = 0;
-        if (lp.cluster > 1) {
-            lc = 1;
-            while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 2048 * lp.cluster) ++lc;
-        }
-        S.lc = lc;
-        S.hand = lc > 0 && lc == S.lb;  // cluster levels (>= 4096 cells) never are in LDS: lc <= lb
+        set_cluster_levels(S, lp.cluster);
     }
     __syncthreads();
     double* sp = S.scratch;

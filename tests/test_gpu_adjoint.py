@@ -68,6 +68,27 @@ def test_checkpoint_interval_does_not_change_gradients(torch_cuda, ctx):
         assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k]), k
 
 
+@pytest.mark.parametrize("prec", [hm.PREC_MIXED, hm.PREC_FP64])
+def test_adjoint_cluster_sizes_are_bitwise_equal(torch_cuda, ctx, prec):
+    """The adjoint of a solve shared by 2, 4 or 8 workgroups: every cell and
+    line computed with the same arithmetic, norms as maxima, the gradient
+    sums taken by the leader in one-workgroup order, so Q, dQ/dxi, dQ/dlog K,
+    dQ/dphi, dQ/dq, status and iteration counts equal those of one
+    workgroup bitwise (checkpoint segments included)."""
+    torch = torch_cuda
+    solves = [(256, 128, 160), (128, 64, 40)]
+    xi = dev(torch, hm.henry_sample_xi(0, 12, 0, len(solves), 3))
+    kw = dict(ckpt_every=30, adj_tol=1e-9, adj_max_it=60)
+    ref = hm.adjoint(ctx, solves, xi=xi, opts=hm.make_opts(prec=prec, tol=1e-9, max_outer=60, cluster=1), **kw)
+    torch.cuda.synchronize()
+    assert list(ref["status"].cpu().numpy()) == [0, 0]
+    for K in (2, 4, 8):
+        out = hm.adjoint(ctx, solves, xi=xi, opts=hm.make_opts(prec=prec, tol=1e-9, max_outer=60, cluster=K), **kw)
+        torch.cuda.synchronize()
+        for key in ("qoi", "dq_dxi", "dq_dlogk", "dq_dphi", "dq_dq", "status", "iters"):
+            assert torch.equal(out[key], ref[key]), (K, key)
+
+
 @pytest.mark.parametrize("prec", [hm.PREC_FP64, hm.PREC_MIXED])
 def test_adjoint_vs_central_differences_128x64(torch_cuda, ctx, prec):
     """128x64 grid, 400 steps, checkpoints every 20, two samples: dQ/dxi and
