@@ -159,6 +159,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and 1024x512 throughput lines (other workloads, not the metric)")
+    ap.add_argument("--kl-adjoint", action="store_true",
+                    help="also run the discrete adjoint of the 32-sample 1024x512 KL workload at full length "
+                         "(3200 steps, checkpoints every 100; ~95 s) and check dQ/dxi of sample 0 against "
+                         "central differences of the forward map in three coefficients")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of CALIB_BYTES before the batch (HBM-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -388,6 +392,38 @@ def main():
             nonconverged=int((ko["status"].cpu().numpy() != 0).sum()))
         log(f"1024x512 KL, 32 x 3200 steps: {tk:.2f} s")
         del ko
+        if args.kl_adjoint:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ka = hm.adjoint(kctx, kg, xi=kxi, opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-8, max_outer=60),
+                            ckpt_every=100, adj_tol=1e-8, adj_max_it=60)
+            torch.cuda.synchronize()
+            tka = time.perf_counter() - t
+            g0 = ka["dq_dxi"][0].cpu().numpy()
+            log(f"1024x512 KL adjoint, 32 x 3200 steps: {tka:.2f} s")
+            # central differences of the forward map, sample 0, coefficients 1, 21, 41
+            h, ks = 1e-3, [0, 20, 40]
+            x0 = kxi[0].cpu().numpy()
+            pts = []
+            for k in ks:
+                for sg in (1.0, -1.0):
+                    x = x0.copy()
+                    x[k] += sg * h
+                    pts.append(x)
+            fo = hm.solve(kctx, [(1024, 512, steps)] * len(pts),
+                          xi=torch.tensor(np.array(pts), dtype=torch.float64, device=dev),
+                          opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-9, max_outer=40))
+            qf = fo["qoi"].cpu().numpy()
+            fd = [(qf[2 * i] - qf[2 * i + 1]) / (2 * h) for i in range(len(ks))]
+            extras["kl_1024x512_adjoint"] = dict(
+                workload="32 KL samples, 1024x512, 3200 steps, checkpoints every 100, dQ/dxi (41), dQ/dlog K, "
+                         "dQ/dphi per cell", seconds=tka, tol=1e-8,
+                nonconverged=int((ka["status"].cpu().numpy() != 0).sum()),
+                outer_iters_per_step=float(ka["iters"].cpu().numpy().mean() / steps),
+                fd_check={f"xi{k + 1}": dict(adjoint=float(g0[k]), central_difference=float(d),
+                                             rel_diff=float(abs(g0[k] - d) / abs(d))) for k, d in zip(ks, fd)})
+            log(f"1024x512 KL adjoint vs central differences: {extras['kl_1024x512_adjoint']['fd_check']}")
+            del ka, fo
         kctx.close()
 
     res = {
