@@ -40,12 +40,12 @@ def algorithmic_bytes_per_outer(elt: int) -> float:
     (elt = bytes of the inner type).  Hierarchy phases carry the 4/3 factor
     of the multigrid levels below the fine grid."""
     f64 = 8
-    residual_p = 5 * f64 + 2 * f64 + 4 * elt          # p,c,c^n,phi,K in; R^p,R^c, te,tn,b,x out
+    residual_p = 5 * f64 + 4 * elt                    # p,c,c^n,phi,K in; te,tn,b,x out (norms reduced)
     coarsen_p = (2 * elt + 2 * elt / 4) / 3            # te,tn -> coarse levels
     sweep_p = 4 * elt + elt                            # x,b,te,tn in; x out (both colours)
     vcycle_p = (4 * sweep_p + (4 * elt + elt) + (elt + elt / 2) + (elt / 4 + 2 * elt)) * 4 / 3
     update = 2 * f64 + elt                             # p (or c) read-modify-write, correction in
-    residual_c = 5 * f64 + f64 + 7 * elt               # same inputs; R^c out; acc,mx,my,dx,dy,b,x out
+    residual_c = 5 * f64 + 7 * elt                    # same inputs; acc,mx,my,dx,dy,b,x out
     coarsen_c = (5 * elt + 5 * elt / 4) / 3
     sweep_c = 7 * elt + elt                            # one line direction: 5 coefs, b, neighbours in; x out
     vcycle_c = (2 * sweep_c + (7 * elt + elt) + (elt + elt / 2) + (elt / 4 + 2 * elt)) * 4 / 3  # x pre, y post
@@ -55,7 +55,7 @@ def algorithmic_bytes_per_outer(elt: int) -> float:
 def algorithmic_bytes_per_step() -> float:
     """Per fine cell and time step outside the iterations: c -> c^n copy
     and the final (converged) residual evaluation."""
-    return 2 * 8 + (5 * 8 + 2 * 8 + 4 * 4)
+    return 2 * 8 + (5 * 8 + 4 * 4)
 
 
 def workload():

@@ -110,7 +110,7 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
     return align256((int64_t)(kLevelArrays * nx * ny + kRowArrays * ny) * (int64_t)sizeof(T));
 }
 
-// FP64 arrays: p, c, cn, phi, K, Rp, Rc, pp (previous p), then the face
+// FP64 arrays: p, c, cn, phi, K, pp (previous p), then the face
 // coefficients that depend only on the fields, set once per solve:
 //   tx, ty  east / north face K_f / mu (harmonic K; 2 K_P / mu on the
 //           seawater face; 0 above the top row),
@@ -123,7 +123,7 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
 // HENRY_PHASE_TIMERS, [32..63] the state of a cluster of workgroups sharing the solve (the members'
 // 32-bit arrival counts in [32..35], the error flag in [36], barriers passed [37], the members' XCD
 // ids [40..47], their partial residual norms [48..63]).
-constexpr int kF64Arrays = 17;
+enum : int { kP, kC, kCn, kPhi, kK, kPp, kTx, kTy, kWx, kWy, kIsc, kC2, kP2, kC3, kP3, kF64Arrays };
 constexpr int kScratch = 64;
 constexpr int kClusterFlags = 32, kClusterErr = 36, kClusterGen = 37, kClusterXcc = 40, kClusterSlots = 48;
 constexpr int kMaxCluster = 8;
@@ -178,7 +178,7 @@ struct Solve {
     int hand;      // level lc is in LDS and fed by the cluster through its global copy hg
     double h, tau;
     double q;  // recharge (m/s)
-    double *p, *c, *cn, *phi, *K, *Rp, *Rc, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *scratch;
+    double *p, *c, *cn, *phi, *K, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *scratch;
     Level<T> lv[kMaxLevels];
     Level<T> hg;  // the global-memory arrays of level lb
 };
@@ -216,10 +216,10 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, ui
     S.h = 1.0 / ny;
     double* f = reinterpret_cast<double*>(base);
     const int n = nx * ny;
-    S.p = f; S.c = f + n; S.cn = f + 2 * n; S.phi = f + 3 * n; S.K = f + 4 * n; S.Rp = f + 5 * n;
-    S.Rc = f + 6 * n; S.pp = f + 7 * n; S.tx = f + 8 * n; S.ty = f + 9 * n; S.wx = f + 10 * n;
-    S.wy = f + 11 * n; S.isc = f + 12 * n; S.c2 = f + 13 * n; S.p2 = f + 14 * n; S.c3 = f + 15 * n;
-    S.p3 = f + 16 * n; S.scratch = f + kF64Arrays * n;
+    auto arr = [&](int k) { return f + (int64_t)k * n; };
+    S.p = arr(kP); S.c = arr(kC); S.cn = arr(kCn); S.phi = arr(kPhi); S.K = arr(kK); S.pp = arr(kPp);
+    S.tx = arr(kTx); S.ty = arr(kTy); S.wx = arr(kWx); S.wy = arr(kWy); S.isc = arr(kIsc);
+    S.c2 = arr(kC2); S.p2 = arr(kP2); S.c3 = arr(kC3); S.p3 = arr(kP3); S.scratch = arr(kF64Arrays);
     uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
     uint8_t* ql = lds;
     int lx = nx, ly = ny;
@@ -587,7 +587,6 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
         const int ps = pidx(idx - j * S.nx, j, S.nx);  // pressure cycle: colour-split
         L0.te[ps] = (T)(q.he ? fe.lam : fr.lam);
         L0.tn[ps] = (T)(q.hn ? fn.lam : 0.0);
-        S.Rp[idx] = Rp;
         L0.b[ps] = (T)(-Rp);
         L0.x[ps] = (T)0;
         mp = nanmax(mp, fabs(Rp * a.sc));
@@ -602,7 +601,6 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
         L0.b[idx] = (T)(-(Rc - a.cP * Rp));
         L0.x[idx] = (T)0;
     }
-    S.Rc[idx] = Rc;
     mc = nanmax(mc, fabs(Rc * a.sc));
 }
 
@@ -1610,9 +1608,9 @@ __global__ void henry_fields_kernel(Launch lp) {
     uint8_t* base = lp.ws + d.ws_off;
     double* f = reinterpret_cast<double*>(base);
     const int nx = d.nx, ny = d.ny, n = nx * ny;
-    double* phi = f + 3 * n;
-    double* K = f + 4 * n;
-    double* sp = f + kF64Arrays * n;
+    double* phi = f + (int64_t)kPhi * n;
+    double* K = f + (int64_t)kK * n;
+    double* sp = f + (int64_t)kF64Arrays * n;
     const double h = 1.0 / ny;
     if (lp.field_kind == 2) {
         // truncated KL expansions: phi = phi0 (1 + s_phi Z_phi), log K = log k0 + s_K Z_K,
@@ -1651,11 +1649,11 @@ __global__ void henry_fields_kernel(Launch lp) {
     }
     __syncthreads();
     // face coefficients (harmonic means) and the residual scale
-    double* tx = f + 8 * n;
-    double* ty = f + 9 * n;
-    double* wx = f + 10 * n;
-    double* wy = f + 11 * n;
-    double* isc = f + 12 * n;
+    double* tx = f + (int64_t)kTx * n;
+    double* ty = f + (int64_t)kTy * n;
+    double* wx = f + (int64_t)kWx * n;
+    double* wy = f + (int64_t)kWy * n;
+    double* isc = f + (int64_t)kIsc * n;
     const double tau = ph.T / d.nsteps;
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
         const int i = idx % nx, j = idx / nx;
