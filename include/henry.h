@@ -183,6 +183,27 @@ int henry_ctx_set_kl(henry_ctx* ctx, int32_t nx, int32_t ny, double corr_len, do
  * (0,1), as in henry_sample_xi.  out_host [count][41]. */
 int henry_sample_xi_kl(uint64_t seed, int32_t level, int64_t first, int64_t count, double* out_host);
 
+/* The FP64 residual of each solve's discrete equations at a given state:
+ * the cell-centred finite-volume form of the fluid and salt balances
+ * (e_cont_eq, e_tran_eq with Darcy's law e_Darcy_vel, Sec. 2.1) after one
+ * implicit Euler step of tau = T / nsteps (Sec. 2.3), per cell
+ *   R^p = (h^2/tau) phi (rho(c) - rho(c^n)) + sum of the face mass fluxes out,
+ *   R^c = (h^2/tau) phi (rho(c) c - rho(c^n) c^n) + sum of the face salt fluxes out
+ * (kg/s per m of depth), the residual whose scaled max norm ends a step of
+ * henry_solve_batch.
+ *   solves, field, xi, phi, logk, qin: as henry_solve_batch
+ *   p, c, cn  device packed FP64 [ny][nx] per solve: the state (p, c) and
+ *             the previous time level c^n
+ *   rp_out, rc_out  device packed FP64 residuals
+ *   workspace, ws_bytes: at least henry_workspace_bytes(ctx, solves, nsolves,
+ *             NULL, ...); its content is overwritten.
+ * Errors: HENRY_EINVAL (bad grid, NULL pointer, missing KL basis),
+ * HENRY_ENOMEM (ws_bytes too small), HENRY_EHIP. */
+int henry_residual_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                         const double* xi, const double* phi, const double* logk, const double* qin,
+                         const double* p, const double* c, const double* cn, double* rp_out, double* rc_out,
+                         void* workspace, size_t ws_bytes, void* stream);
+
 /* Workspace (device bytes) that henry_solve_batch needs for these solves. */
 int henry_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
                           const henry_opts_t* opts, size_t* bytes_out);

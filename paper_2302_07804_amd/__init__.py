@@ -27,7 +27,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opts_default", "henry_sample_xi",
            "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_tune_set", "henry_tune_get",
            "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
-           "henry_ctx_set_kl", "henry_sample_xi_kl")
+           "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -104,6 +104,8 @@ def lib():
     L.henry_solve_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), vp, vp,
                                     vp, vp, vp, vp, ct.c_size_t, vp]
     L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
+    L.henry_residual_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                       ct.c_size_t, vp]
     L.henry_tune_set.argtypes = [vp, i32, i32, i32]
     L.henry_tune_get.argtypes = [vp, i32, i32, ct.POINTER(i32)]
     L.henry_adjoint_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), i32,
@@ -230,6 +232,34 @@ def henry_solve_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None,
                                  workspace.numel() * workspace.element_size() if workspace is not None else 0,
                                  _stream_of(stream))
     _chk(rc, "henry_solve_batch")
+
+
+def henry_residual_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, p=None, c=None,
+                         cn=None, rp_out=None, rc_out=None, workspace=None, stream=None):
+    """Thin wrapper: tensors are device tensors owned by the caller."""
+    g = grids(solves)
+    rc = lib().henry_residual_batch(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk), _ptr(qin),
+                                    _ptr(p), _ptr(c), _ptr(cn), _ptr(rp_out), _ptr(rc_out), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                    _stream_of(stream))
+    _chk(rc, "henry_residual_batch")
+
+
+def residual(ctx: Context, solves, p, c, cn, xi=None, phi=None, logk=None, qin=None, stream=None):
+    """R^p, R^c (packed device tensors) of each solve's discrete equations at
+    the state (p, c) with previous time level cn (packed device tensors)."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    cells = sum(int(s[0]) * int(s[1]) for s in solves)
+    ws_bytes = henry_workspace_bytes(solves)
+    ws = torch.empty((ws_bytes + 255) // 256 * 256 // 8 + 32, dtype=torch.float64, device=dev)
+    off = (-ws.data_ptr()) % 256 // 8
+    ws = ws[off:off + (ws_bytes + 7) // 8]
+    rp = torch.empty(cells, dtype=torch.float64, device=dev)
+    rc = torch.empty(cells, dtype=torch.float64, device=dev)
+    henry_residual_batch(ctx, solves, _field_of(xi), xi=xi, phi=phi, logk=logk, qin=qin, p=p, c=c, cn=cn,
+                         rp_out=rp, rc_out=rc, workspace=ws, stream=stream)
+    return rp, rc
 
 
 def henry_profile_last(ctx: Context):

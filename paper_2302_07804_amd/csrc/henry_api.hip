@@ -613,6 +613,91 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     return HENRY_OK;
 }
 
+int henry_residual_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                         const double* xi, const double* phi, const double* logk, const double* qin,
+                         const double* p, const double* c, const double* cn, double* rp_out, double* rc_out,
+                         void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx || nsolves < 0) return HENRY_EINVAL;
+    if (nsolves == 0) return HENRY_OK;
+    if (!solves || !p || !c || !cn || !rp_out || !rc_out || !workspace) return HENRY_EINVAL;
+    if (field == HENRY_FIELD_CLOSED3) {
+        if (!xi) return HENRY_EINVAL;
+    } else if (field == HENRY_FIELD_KL41) {
+        if (!xi) return HENRY_EINVAL;
+        for (int k = 0; k < nsolves; ++k)
+            if (ctx->kl.find(solves[k].nx) == ctx->kl.end()) return HENRY_EINVAL;
+    } else if (field == HENRY_FIELD_EXPLICIT) {
+        if (!phi || !logk || !qin) return HENRY_EINVAL;
+    } else {
+        return HENRY_EINVAL;
+    }
+    size_t need = 0;
+    if (int rc = henry_workspace_bytes(ctx, solves, nsolves, nullptr, &need)) return rc;
+    if (ws_bytes < need) return HENRY_ENOMEM;
+    if (((uintptr_t)workspace & 255) != 0) return HENRY_EINVAL;
+    // the layout of the mixed-precision solve (the residual is FP64 either way)
+    std::vector<henry::SolveDesc> desc(nsolves);
+    int64_t off = desc_bytes(nsolves), foff = 0;
+    std::map<long, Group> groups;
+    for (int k = 0; k < nsolves; ++k) {
+        const henry_grid_t& g = solves[k];
+        henry::SolveDesc& d = desc[k];
+        d.nx = g.nx; d.ny = g.ny; d.nsteps = g.nsteps; d.nlev = henry::num_levels(g.ny);
+        d.reserved = 0; d.index = k; d.ws_off = off; d.field_off = foff; d.adj_off = 0;
+        off += solve_bytes(g.nx, g.ny, HENRY_PREC_MIXED);
+        foff += (int64_t)g.nx * g.ny;
+        Group& G = groups[(long)g.nx];
+        G.nx = g.nx; G.ny = g.ny;
+        G.members.push_back(k);
+    }
+    std::vector<henry::SolveDesc> table;
+    std::vector<std::pair<int, const Group*>> starts;
+    for (auto& kv : groups) {
+        starts.emplace_back((int)table.size(), &kv.second);
+        for (int k : kv.second.members) table.push_back(desc[k]);
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    const size_t tbytes = sizeof(henry::SolveDesc) * (size_t)nsolves;
+    if (ctx->pinned && hipEventSynchronize(ctx->staging_done) != hipSuccess) return HENRY_EHIP;
+    if (ctx->pinned_bytes < tbytes) {
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+        if (hipHostMalloc(&ctx->pinned, tbytes, hipHostMallocDefault) != hipSuccess) return HENRY_ENOMEM;
+        ctx->pinned_bytes = tbytes;
+    }
+    std::memcpy(ctx->pinned, table.data(), tbytes);
+    uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
+    henry::SolveDesc* dtable = reinterpret_cast<henry::SolveDesc*>(ws);
+    if (hipMemcpyAsync(dtable, ctx->pinned, tbytes, hipMemcpyHostToDevice, s0) != hipSuccess) return HENRY_EHIP;
+    if (hipEventRecord(ctx->staging_done, s0) != hipSuccess) return HENRY_EHIP;
+    henry::Launch lp{};
+    lp.ws = ws;
+    lp.xi = xi; lp.phi_in = phi; lp.logk_in = logk; lp.qin_in = qin;
+    std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
+    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : (field == HENRY_FIELD_KL41 ? 2 : 1);
+    lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
+    lp.cluster = 1;
+    for (const auto& st : starts) {
+        const Group& G = *st.second;
+        henry::Launch l = lp;
+        l.descs = dtable + st.first;
+        l.nsolves = (int)G.members.size();
+        if (l.field_kind == 2) {
+            const KlGrid& kg = ctx->kl.at(G.nx);
+            l.kl_modes = kg.modes;
+            l.kl_sigma_phi = kg.sigma_phi;
+            l.kl_sigma_logk = kg.sigma_logk;
+        }
+        hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(l.nsolves), dim3(256), 0, s0, l);
+        hipLaunchKernelGGL(henry::henry_residual_kernel, dim3(l.nsolves), dim3(256), 0, s0, l, p, c, cn, rp_out,
+                           rc_out);
+    }
+    if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    return HENRY_OK;
+}
+
 int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
     if (!ctx || nx < 2 || nx > 1024 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
     if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;

@@ -181,6 +181,7 @@ struct Solve {
     double *p, *c, *cn, *phi, *K, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *scratch;
     Level<T> lv[kMaxLevels];
     Level<T> hg;  // the global-memory arrays of level lb
+    double *rout_p, *rout_c;  // residual outputs (henry_residual_kernel)
 };
 
 // Levels in LDS: every level of at most `lds_cells` cells (run by
@@ -590,6 +591,9 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
         L0.b[ps] = (T)(-Rp);
         L0.x[ps] = (T)0;
         mp = nanmax(mp, fabs(Rp * a.sc));
+    } else if (mode == 2) {
+        S.rout_p[idx] = Rp;
+        S.rout_c[idx] = Rc;
     } else {
         L0.mx[idx] = (T)(q.he ? fe.M : 0.0);
         L0.dx[idx] = (T)(q.he ? fe.dif : 0.0);
@@ -608,6 +612,7 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
 //         scaled max norms (block max).
 // mode 1: the salt defect S = R^c - c R^p with the transport coefficients
 //         at level 0.
+// mode 2: R^p and R^c into S.rout_p, S.rout_c (the residual entry point).
 // Thread layout: lanes along x (cw = min(nx, blockDim) columns), the
 // blockDim / cw row groups each march up their own band of rows.  A cell
 // takes p and c of the rows below and above from the registers of the
@@ -1597,6 +1602,36 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
             if (lp.iters) lp.iters[d.index] = (int32_t)iters;
         }
     }
+}
+
+// The FP64 residual of one solve's discrete equations at a given state
+// (p, c; previous time level cn): the same residual pass as the solver's,
+// writing R^p and R^c instead of the inner-solve arrays.  One workgroup per
+// solve, after henry_fields_kernel.
+__global__ void __launch_bounds__(1024) henry_residual_kernel(Launch lp, const double* p, const double* c,
+                                                              const double* cn, double* rp, double* rc) {
+    extern __shared__ __align__(256) uint8_t lds_levels[];  // launched with none: no level in LDS
+    __shared__ Solve<float> S;
+    __shared__ double red[16];
+    const SolveDesc d = lp.descs[blockIdx.x];
+    const Phys& ph = lp.ph;
+    if (threadIdx.x == 0) {
+        bind_solve(S, lp.ws + d.ws_off, d.nx, d.ny, lds_levels, 0, 0);
+        S.nsteps = d.nsteps;
+        S.tau = ph.T / d.nsteps;
+        S.q = S.scratch[0];
+        S.rout_p = rp + d.field_off;
+        S.rout_c = rc + d.field_off;
+    }
+    cluster_init_single();
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+        S.p[idx] = p[d.field_off + idx];
+        S.c[idx] = c[d.field_off + idx];
+        S.cn[idx] = cn[d.field_off + idx];
+    }
+    __syncthreads();
+    double np, nc;
+    residual_pass(ph, S, 2, red, np, nc);
 }
 
 // ------------------------------------------------------------------ random fields

@@ -102,6 +102,13 @@ def test_solve_batch_rejects_null_context(L):
     assert hm.strerror(hm.HENRY_EINVAL) == "invalid argument"
 
 
+def test_residual_batch_rejects_bad_arguments(L):
+    g = hm.grids([(16, 8, 50)])
+    null = [None] * 9
+    assert L.henry_residual_batch(None, g, 1, 0, *null, None, 0, None) == hm.HENRY_EINVAL
+    assert L.henry_residual_batch(None, g, 0, 0, *null, None, 0, None) == hm.HENRY_EINVAL
+
+
 @pytest.mark.parametrize("nx,ny", [(16, 8), (64, 32), (256, 128)])
 def test_kl_basis_matches_oracle(L, nx, ny):
     from oracle import kl
