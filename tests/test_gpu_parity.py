@@ -298,16 +298,20 @@ def test_mlmc_level_estimate_matches_oracle_stats(torch_cuda, ctx):
     assert ve[1].item() == pytest.approx(float(vo.max()), rel=1e-13)
 
 
-def test_graph_replays_match_eager(torch_cuda, ctx):
+@pytest.mark.parametrize("solves,cluster", [([(16, 8, 50)] * 3 + [(32, 16, 100)] * 2, 0),
+                                            ([(128, 64, 40)] * 2 + [(16, 8, 50)], 2)])
+def test_graph_replays_match_eager(torch_cuda, ctx, solves, cluster):
     """steps_per_launch > 0 captures the lockstep time loop once into a
     hipGraph; replays on the same buffers, with eager work in between, must
-    all give the eager result."""
+    all give the eager result (with clusters too: each replay starts from a
+    fresh cluster state, reset by the captured fields kernel)."""
     torch = torch_cuda
-    solves = [(16, 8, 50)] * 3 + [(32, 16, 100)] * 2
     xi = torch.tensor(hm.henry_sample_xi(0, 2, 0, len(solves), 3), dtype=torch.float64, device="cuda")
-    eager = hm.solve(ctx, solves, xi=xi, opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60))
+    eager = hm.solve(ctx, solves, xi=xi, opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60,
+                                                           cluster=cluster))
     torch.cuda.synchronize()
-    gopts = hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60, steps_per_launch=5)
+    assert (eager["status"].cpu().numpy() == hm.STATUS_OK).all()
+    gopts = hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60, steps_per_launch=5, cluster=cluster)
     cells = sum(s[0] * s[1] for s in solves)
     ws_b = hm.henry_workspace_bytes(solves, gopts)
     raw = torch.empty(ws_b // 8 + 64, dtype=torch.float64, device="cuda")
