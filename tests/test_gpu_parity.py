@@ -223,6 +223,56 @@ def test_no_convergence_is_reported_per_solve(torch_cuda, ctx):
     assert list(out["status"].cpu().numpy()) == [hm.STATUS_NOCONV] * 2
 
 
+def test_nonfinite_input_is_reported_for_its_solve_only(torch_cuda, ctx):
+    """A NaN coefficient in one solve's xi makes its fields and residual
+    non-finite: that solve reports HENRY_STATUS_NONFINITE and stops, while
+    the other solves of the batch are bitwise those of a batch without it."""
+    torch = torch_cuda
+    solves = [(16, 8, 50)] * 3 + [(128, 64, 40)]
+    xi = hm.henry_sample_xi(0, 15, 0, len(solves), 3)
+    bad = xi.copy()
+    bad[1, 0] = np.nan
+    out = run(torch, ctx, solves, bad, hm.PREC_MIXED, tol=1e-9)
+    ref = run(torch, ctx, [solves[k] for k in (0, 2, 3)], xi[[0, 2, 3]], hm.PREC_MIXED, tol=1e-9)
+    assert list(out["status"].cpu().numpy()) == [hm.STATUS_OK, hm.STATUS_NONFINITE, hm.STATUS_OK, hm.STATUS_OK]
+    cs, rs = hm.unpack(out["c"], solves), hm.unpack(ref["c"], [solves[k] for k in (0, 2, 3)])
+    for a, b in zip((cs[0], cs[2], cs[3]), rs):
+        assert torch.equal(a, b)
+    q = out["qoi"].cpu().numpy()
+    assert np.array_equal(q[[0, 2, 3]], ref["qoi"].cpu().numpy())
+
+
+def test_huge_recharge_reports_nonfinite(torch_cuda, ctx):
+    """Explicit fields with a recharge of 1e300 m/s overflow the fluxes."""
+    torch = torch_cuda
+    nx, ny, r = 16, 8, 20
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64).ravel(), device="cuda")
+    phi = np.full((ny, nx), hi.PHYS["phi0"])
+    logk = np.full((ny, nx), np.log(hi.PHYS["k0"]))
+    out = hm.solve(ctx, [(nx, ny, r)] * 2, phi=dev(np.stack([phi, phi])), logk=dev(np.stack([logk, logk])),
+                   qin=dev([1e300, hi.PHYS["q_in"]]), opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-9))
+    torch.cuda.synchronize()
+    assert list(out["status"].cpu().numpy()) == [hm.STATUS_NONFINITE, hm.STATUS_OK]
+
+
+def test_small_workspace_is_rejected(torch_cuda, ctx):
+    torch = torch_cuda
+    solves = [(16, 8, 50)] * 2
+    opts = hm.make_opts(prec=hm.PREC_MIXED)
+    need = hm.henry_workspace_bytes(solves, opts)
+    raw = torch.empty(need // 8 + 64, dtype=torch.float64, device="cuda")
+    off = (-raw.data_ptr()) % 256 // 8
+    ws = raw[off:off + need // 8 - 32]  # 256 bytes short
+    xi = torch.tensor(hm.henry_sample_xi(0, 0, 0, 2, 3), dtype=torch.float64, device="cuda")
+    c = torch.empty(2 * 128, dtype=torch.float64, device="cuda")
+    q = torch.empty(2, dtype=torch.float64, device="cuda")
+    st = torch.empty(2, dtype=torch.int32, device="cuda")
+    with pytest.raises(hm.HenryError) as e:
+        hm.henry_solve_batch(ctx, solves, hm.FIELD_CLOSED3, xi=xi, opts=opts, c_out=c, qoi_out=q, status=st,
+                             workspace=ws)
+    assert e.value.code == hm.HENRY_ENOMEM
+
+
 def test_hydrostatic_seawater_on_gpu(torch_cuda):
     """c0 = 1, no recharge, no diffusion: p = -rho1 g y, zero Darcy flux."""
     torch = torch_cuda
