@@ -25,6 +25,8 @@ int oracle_jacobian_dense(const oracle_phys* ph, int32_t nx, int32_t ny, int32_t
 int oracle_band_solve_dense(int32_t n, int32_t kl, int32_t ku, const double* A, const double* b, double* x,
                             int32_t trans);
 double oracle_qoi(const oracle_phys* ph, int32_t nx, int32_t ny, const double* phi, const double* c);
+/* iters: NULL or [nsteps] Newton iterations per step; p_traj, c_traj: NULL
+ * or [nsteps + 1][ny][nx] states from the initial one on. */
 int oracle_solve(const oracle_phys* ph, int32_t nx, int32_t ny, int32_t nsteps,
                  const double* phi, const double* K, double q, const double* c0,
                  double* p_out, double* c_out, double* qoi, int32_t* iters,
