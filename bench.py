@@ -318,11 +318,13 @@ def main():
                    sample=f"{len(sample_idx)} solves of the workload (48 level-0, 8 level-1 pairs, 1 level-2 "
                           f"pair; {cs_sample} cell-steps), one solve per thread, {tcpu:.1f} s wall")
         c_all = c_out.cpu().numpy()
-        worst = 0.0
+        worst = worst_l2 = 0.0
         for k, r in zip(sample_idx, refs):
             c = c_all[offs[k]:offs[k + 1]].reshape(solves[k].ny, solves[k].nx)
             worst = max(worst, np.abs(c - r["c"]).max() / np.abs(r["c"]).max())
+            worst_l2 = max(worst_l2, np.linalg.norm(c - r["c"]) / np.linalg.norm(r["c"]))
         errs["batched_mixed_max_rel_c_err"] = worst
+        errs["batched_mixed_l2_rel_c_err"] = worst_l2
         # E[c] of level 0 over the sampled solves
         mean_gpu = np.mean([c_all[offs[k]:offs[k + 1]] for k in sample_idx[:48]], axis=0)
         mean_ora = np.mean([r["c"].ravel() for r in refs[:48]], axis=0)
@@ -453,6 +455,8 @@ def main():
         "errors_vs_oracle": errs,
         "nonconverged_solves": int((status_h != 0).sum()),
         "mean_outer_iters_per_step": float(iters_h.sum() / sum(s.nsteps for s in solves)),
+        "outer_iters_per_step_by_grid": {f"{g['nx']}x{g['ny']}": round(g["mean_outer_per_step"], 3)
+                                         for g in per_group},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(),
                      "algorithmic_bytes_per_launch": sum(g["alg_bytes"] for g in per_group) / len(per_group),
