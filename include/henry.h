@@ -24,9 +24,10 @@
  *     (y = -1 + h/2).  "Packed" per-solve fields are concatenated in solve
  *     order: solve k starts at element sum_{m<k} nx_m * ny_m.
  *   - Grids must satisfy nx == 2 * ny (square cells, h = 1/ny), ny a power
- *     of two with 1 <= ny <= 512 (one workgroup owns a solve; its line
- *     solver keeps at most 16 rows of a line per lane, 64 lanes per line),
- *     nsteps >= 1.
+ *     of two with 1 <= ny <= 512 (the line solver keeps at most 16 rows of
+ *     a line per lane, 64 lanes per line), nsteps >= 1.  One workgroup owns
+ *     a solve, or a cluster of workgroups for grids above 2048 cells
+ *     (henry_opts_t.cluster).
  *   - Return codes are the HENRY_* values below; no exception crosses the
  *     ABI.  A context is not thread-safe; use one per host thread.
  */
