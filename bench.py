@@ -376,6 +376,19 @@ def main():
             nonconverged=int((a["status"].cpu().numpy() != 0).sum()), tol=args.tol)
         log(f"adjoint 512 x 128x64/400: {ta:.2f} s")
         del a
+        # adaptive MLMC (Sec. 3) on the L = 4 hierarchy: pilot, eq:M_ell on the
+        # measured variances and GPU costs, final batch, MSE split
+        t = time.perf_counter()
+        am = hm.mlmc_run(ctx, [hi.level_grid(l) for l in range(5)], 0.05, m_pilot=16, seed=hi.SEED,
+                         opts=hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60))
+        ta = time.perf_counter() - t
+        extras["mlmc_adaptive_L4"] = dict(
+            workload="adaptive MLMC for E[Q], eps = 0.05, 16-sample pilots, levels 16x8/50 .. 256x128/800",
+            seconds=ta, final_batch_seconds=am["seconds"], m=[int(x) for x in am["m"]],
+            seconds_per_sample=[float(x) for x in am["s"]], V=[float(x) for x in am["V"]], EQ=am["EQ"],
+            var_est=am["var_est"], alpha=am["alpha"], beta=am["beta"], bias_estimate=am["bias"],
+            mse_within_eps2=am["mse_ok"], nonconverged=am["nonconverged"])
+        log(f"adaptive MLMC L4 eps 0.05: {ta:.2f} s, m = {extras['mlmc_adaptive_L4']['m']}, E[Q] = {am['EQ']:.5f}")
         # KL fields on 1024x512: 32 samples, all 3200 steps (tau = T/3200)
         steps = 3200
         kctx = hm.Context(hi.PHYS, 0)

@@ -307,6 +307,29 @@ int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, con
                         double* const* mean_Y, double* const* var_Y, double* qstats, double* Ec_finest,
                         double* var_est, void* stream);
 
+/* Sample allocation of an MLMC run (Sec. 3, eq:M_ell): with per-level
+ * variances V[l] of Y_l = g_l - g_{l-1} and costs s[l] > 0 per sample
+ * (any unit), the counts that minimise sum m_l s_l at estimator variance
+ * sum V_l / m_l = eps2:
+ *   m_out[l] = ceil(eps2^-1 sqrt(V_l / s_l) sum_i sqrt(V_i s_i)),
+ *   cost_out = eps2^-1 (sum_l sqrt(V_l s_l))^2 (or NULL).
+ * Host arrays of nlevels >= 1.  A level with V_l = 0 gets 0; callers keep
+ * at least their pilot count.  Errors: HENRY_EINVAL (V < 0, s <= 0,
+ * eps2 <= 0, non-finite input, a count beyond 9e18). */
+int henry_mlmc_allocate(int32_t nlevels, const double* V, const double* s, double eps2, int64_t* m_out,
+                        double* cost_out);
+
+/* Convergence rates of an MLMC hierarchy (Sec. 3; the decay the paper fits
+ * in its Fig. 10): least-squares slopes over levels l = first .. nlevels-1
+ * of log2 |E[Y_l]| and log2 V_l, |E[Y_l]| ~ 2^(-alpha l), V_l ~ 2^(-beta l),
+ * and, if bias is not NULL, the bias estimate of the finest level
+ * |E[Y_L]| / (2^alpha - 1) (infinite when alpha <= 0) for the MSE split
+ * eq:MSE.  Host arrays; at least two levels in the fit, at most 64 levels.
+ * Errors: HENRY_EINVAL (fewer than two levels, a zero or non-finite mean or
+ * variance in the fit). */
+int henry_mlmc_rates(int32_t nlevels, const double* mean, const double* var, int32_t first, double* alpha,
+                     double* beta, double* bias);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libhenry.so")
-_SOURCES = [os.path.join(_HERE, "csrc", "henry_api.hip")]
+_SOURCES = [os.path.join(_HERE, "csrc", "henry_api.hip"), os.path.join(_HERE, "csrc", "henry_mlmc_plan.cpp")]
 _DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlmc.hpp", "henry_adjoint.hpp")] + \
     [os.path.join(_ROOT, "include", "henry.h")]
 
@@ -27,7 +27,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opts_default", "henry_sample_xi",
            "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_tune_set", "henry_tune_get",
            "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
-           "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch")
+           "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch", "henry_mlmc_allocate",
+           "henry_mlmc_rates")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -104,6 +105,10 @@ def lib():
     L.henry_solve_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), vp, vp,
                                     vp, vp, vp, vp, ct.c_size_t, vp]
     L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
+    L.henry_mlmc_allocate.argtypes = [i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), dbl,
+                                      ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
+    L.henry_mlmc_rates.argtypes = [i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), i32,
+                                   ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     L.henry_residual_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                        ct.c_size_t, vp]
     L.henry_tune_set.argtypes = [vp, i32, i32, i32]
@@ -260,6 +265,31 @@ def residual(ctx: Context, solves, p, c, cn, xi=None, phi=None, logk=None, qin=N
     henry_residual_batch(ctx, solves, _field_of(xi), xi=xi, phi=phi, logk=logk, qin=qin, p=p, c=c, cn=cn,
                          rp_out=rp, rc_out=rc, workspace=ws, stream=stream)
     return rp, rc
+
+
+def henry_mlmc_allocate(V, s, eps2):
+    """eq:M_ell: (m[l], cost) for variances V[l] and costs s[l] (host)."""
+    import numpy as np
+    V = np.ascontiguousarray(V, np.float64)
+    s = np.ascontiguousarray(s, np.float64)
+    m = np.empty(len(V), np.int64)
+    cost = ct.c_double()
+    dp = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_double))
+    _chk(lib().henry_mlmc_allocate(len(V), dp(V), dp(s), float(eps2), m.ctypes.data_as(ct.POINTER(ct.c_int64)),
+                                   ct.byref(cost)), "henry_mlmc_allocate")
+    return m, cost.value
+
+
+def henry_mlmc_rates(mean, var, first=1):
+    """(alpha, beta, bias of the finest level) from level means and variances."""
+    import numpy as np
+    mean = np.ascontiguousarray(mean, np.float64)
+    var = np.ascontiguousarray(var, np.float64)
+    a, b, bias = ct.c_double(), ct.c_double(), ct.c_double()
+    dp = lambda x: x.ctypes.data_as(ct.POINTER(ct.c_double))
+    _chk(lib().henry_mlmc_rates(len(mean), dp(mean), dp(var), int(first), ct.byref(a), ct.byref(b), ct.byref(bias)),
+         "henry_mlmc_rates")
+    return a.value, b.value, bias.value
 
 
 def henry_profile_last(ctx: Context):
@@ -507,3 +537,9 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return result
+
+
+def mlmc_run(*args, **kwargs):
+    """Adaptive MLMC estimate of E[Q] (see paper_2302_07804_amd.mlmc.mlmc_run)."""
+    from .mlmc import mlmc_run as run
+    return run(*args, **kwargs)

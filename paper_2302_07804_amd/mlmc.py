@@ -1,0 +1,114 @@
+"""Adaptive multilevel Monte Carlo for the expected QoI (Sec. 3 of arXiv
+2302.07804): pilot runs give the per-level variances V_l of
+Y_l = Q_l - Q_{l-1} and the GPU cost s_l of one sample pair; eq:M_ell gives
+the sample counts for the estimator variance eps^2 / 2; the final batch
+solves every level's samples at once; the MSE split eq:MSE checks the bias
+of the finest level, estimated from the fitted weak rate.
+
+Orchestration only: the solves (henry_solve_batch), the level statistics
+(mlmc_level_estimate) and the planning arithmetic (henry_mlmc_allocate,
+henry_mlmc_rates) are calls into libhenry."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import (FIELD_CLOSED3, Context, Opts, henry_mlmc_allocate, henry_mlmc_rates, henry_sample_xi,
+               mlmc_level_estimate, solve)
+
+
+def _pairs(levels, m, seed):
+    """Solve list, xi and per-level (fine, coarse) index ranges: level l
+    solves grid l and grid l-1 for samples 0 .. m[l]-1, both with the key
+    (seed, l, i) (eq:A)."""
+    solves, xis, ranges = [], [], []
+    for l, ml in enumerate(m):
+        xi = henry_sample_xi(seed, l, 0, int(ml), 3)
+        f0 = len(solves)
+        solves += [tuple(levels[l])] * int(ml)
+        xis.append(xi)
+        c0 = len(solves)
+        if l > 0:
+            solves += [tuple(levels[l - 1])] * int(ml)
+            xis.append(xi)
+        ranges.append((f0, c0, len(solves)))
+    return solves, np.concatenate(xis), ranges
+
+
+def _level_statistics(ctx, levels, m, outs):
+    """mlmc_level_estimate over per-level outputs: outs[l] = (solves, out,
+    (f0, c0, c1)) with the fine solves f0..c0-1 and the coarse ones c0..c1-1."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    L = len(levels) - 1
+    c_fine, c_coarse, q_fine, q_coarse = [], [], [], []
+    for l, (sol, out, (f0, c0, c1)) in enumerate(outs):
+        offs = np.concatenate([[0], np.cumsum([s[0] * s[1] for s in sol])])
+        c_fine.append(out["c"][offs[f0]:offs[c0]])
+        q_fine.append(out["qoi"][f0:c0])
+        c_coarse.append(out["c"][offs[c0]:offs[c1]] if l > 0 else None)
+        q_coarse.append(out["qoi"][c0:c1] if l > 0 else None)
+    mean_Y = [torch.empty(g[0] * g[1], dtype=torch.float64, device=dev) for g in levels]
+    var_Y = [torch.empty(g[0] * g[1], dtype=torch.float64, device=dev) for g in levels]
+    qstats = torch.empty(2 * (L + 1), dtype=torch.float64, device=dev)
+    Ec = torch.empty(levels[-1][0] * levels[-1][1], dtype=torch.float64, device=dev)
+    var_est = torch.empty(2, dtype=torch.float64, device=dev)
+    mlmc_level_estimate(ctx, levels, m, c_fine, c_coarse, q_fine, q_coarse, mean_Y, var_Y, qstats, Ec, var_est)
+    torch.cuda.synchronize(dev)
+    qs = qstats.cpu().numpy().reshape(L + 1, 2)
+    return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec
+
+
+def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0, opts: Opts | None = None,
+             max_samples: int | None = None):
+    """Adaptive MLMC estimate of E[Q] to root-mean-square error eps.
+
+    levels: fine grids (nx, ny, nsteps) of levels 0..L (nx = 2 ny, each
+    twice the one before it); level l > 0 pairs grid l with grid l-1.
+    Returns a dict: EQ (sum of the level means), var_est (sum V_l / m_l),
+    m, V, s (seconds per sample at each level, fine and coarse solve), the
+    level means, alpha, beta, the bias estimate, mse_ok (var_est <= eps^2/2
+    and bias^2 <= eps^2/2), the final batch's seconds, and E[c] on the
+    finest grid (device tensor)."""
+    import torch
+    levels = [tuple(int(v) for v in g) for g in levels]
+    L = len(levels) - 1
+    if L < 0 or m_pilot < 2:
+        raise ValueError("need at least one level and a pilot of at least two samples")
+    dev = torch.device("cuda", ctx.device)
+    # ---- pilot: one batch per level, timed on the GPU stream
+    pilot, s = [], []
+    for l in range(L + 1):
+        sol, xi, rng = _pairs(levels[:l + 1], [0] * l + [m_pilot], seed)
+        xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        out = solve(ctx, sol, xi=xi_d, opts=opts)
+        torch.cuda.synchronize(dev)
+        s.append((time.perf_counter() - t0) / m_pilot)
+        pilot.append((sol, out, rng[l]))
+    mean_p, V, _, _ = _level_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
+    # ---- allocation (eq:M_ell) for the variance half of the MSE (eq:MSE)
+    m, cost = henry_mlmc_allocate(V, np.array(s), eps * eps / 2)
+    m = np.maximum(m, m_pilot)
+    if max_samples is not None:
+        m = np.minimum(m, max_samples)
+    # ---- final batch: every level's samples at once
+    sol, xi, rng = _pairs(levels, m, seed)
+    xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    out = solve(ctx, sol, xi=xi_d, opts=opts)
+    torch.cuda.synchronize(dev)
+    seconds = time.perf_counter() - t0
+    status = out["status"].cpu().numpy()
+    mean, var, var_est, Ec = _level_statistics(ctx, levels, m, [(sol, out, r) for r in rng])
+    alpha = beta = bias = float("nan")
+    if L >= 2:
+        alpha, beta, bias = henry_mlmc_rates(mean, var, 1)
+    half = eps * eps / 2
+    return dict(EQ=float(mean.sum()), var_est=var_est, m=m, V=var, V_pilot=V, s=np.array(s), mean=mean,
+                alpha=alpha, beta=beta, bias=bias, planned_cost=cost,
+                mse_ok=bool(var_est <= half * (1 + 1e-12) and (L < 2 or bias * bias <= half)),
+                seconds=seconds, nonconverged=int((status != 0).sum()), Ec=Ec)
