@@ -163,6 +163,10 @@ def main():
                     help="also run the discrete adjoint of the 32-sample 1024x512 KL workload at full length "
                          "(3200 steps, checkpoints every 100; ~95 s) and check dQ/dxi of sample 0 against "
                          "central differences of the forward map in three coefficients")
+    ap.add_argument("--qmc-reference", nargs=2, type=int, metavar=("POINTS", "SHIFTS"), default=None,
+                    help="compare the MLMC estimates truncated after each level with a randomly shifted Halton "
+                         "reference (POINTS points x SHIFTS shifts) on 512x256/1600, at (1.60, -0.95) and for E[Q] "
+                         "(default 128 4 with the other workloads, ~25 s)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of CALIB_BYTES before the batch (HBM-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -440,6 +444,41 @@ def main():
             log(f"1024x512 KL adjoint vs central differences: {extras['kl_1024x512_adjoint']['fd_check']}")
             del ka, fo
         kctx.close()
+
+    qmc_ref = args.qmc_reference or (None if args.no_extras else (128, 4))
+    if qmc_ref:
+        # the reference of Fig. 11: a QMC mean on a grid one level finer than the
+        # hierarchy, against the MLMC estimates truncated after each level
+        npts, nsh = qmc_ref
+        ref_grid = hi.level_grid(L + 1)
+        shifts = (hm.henry_sample_xi(hi.SEED, 99, 0, nsh, 3) + 1.0) / 2.0
+        qr = hm.qmc_run(ctx, ref_grid, npts, shifts=list(shifts),
+                        opts=hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60))
+        kp = hm.point_cell(ref_grid, 1.60, -0.95)
+        Ec_ref = float(qr["Ec"][kp].item())
+        c_shift = np.array([float(e[kp].item()) for e in qr["Ec_shift"]])
+        tel_c = hm.telescoped_at(fine_grids, mean_Y, 1.60, -0.95)
+        qs = qstats.cpu().numpy().reshape(L + 1, 2)
+        tel_q = np.cumsum(qs[:, 0])
+        # standard errors of the truncated estimators: sqrt(sum_l V_l / m_l)
+        se_q = np.sqrt(np.cumsum(qs[:, 1] / np.array(M_PER_LEVEL)))
+        vpt = [float(var_Y[l][hm.point_cell(fine_grids[l], 1.60, -0.95)].item()) for l in range(L + 1)]
+        se_c = np.sqrt(np.cumsum(np.array(vpt) / np.array(M_PER_LEVEL)))
+        extras = extras if extras is not None else {}
+        extras["mlmc_vs_qmc"] = dict(
+            workload=f"QMC reference: {npts} Halton points x {nsh} random shifts on "
+                     f"{ref_grid[0]}x{ref_grid[1]}/{ref_grid[2]}; MLMC: the timed batch, truncated after each level",
+            seconds=qr["seconds"], nonconverged=qr["nonconverged"],
+            qmc_EQ=qr["EQ"], qmc_EQ_se=qr["se"], qmc_c_point=Ec_ref,
+            qmc_c_point_se=float(c_shift.std(ddof=1) / np.sqrt(nsh)) if nsh > 1 else None,
+            mlmc_c_point_by_level=[float(v) for v in tel_c], mlmc_EQ_by_level=[float(v) for v in tel_q],
+            mlmc_c_point_se_by_level=[float(v) for v in se_c], mlmc_EQ_se_by_level=[float(v) for v in se_q],
+            abs_err_c_point=[float(abs(v - Ec_ref)) for v in tel_c],
+            rel_err_c_point=[float(abs(v - Ec_ref) / abs(Ec_ref)) for v in tel_c],
+            abs_err_EQ=[float(abs(v - qr["EQ"])) for v in tel_q],
+            rel_err_EQ=[float(abs(v - qr["EQ"]) / abs(qr["EQ"])) for v in tel_q])
+        log(f"QMC {npts}x{nsh} on {ref_grid}: {qr['seconds']:.1f} s, E[Q] = {qr['EQ']:.6f} +- {qr['se']:.1e}, "
+            f"c(1.60,-0.95) = {Ec_ref:.6f}; MLMC by level c: {tel_c}, E[Q]: {tel_q}")
 
     res = {
         "metric": "Henry sample solves/s (cell-steps/s) batched vs plain, same 1e-5 E[c] error",

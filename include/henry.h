@@ -330,6 +330,22 @@ int henry_mlmc_allocate(int32_t nlevels, const double* V, const double* s, doubl
 int henry_mlmc_rates(int32_t nlevels, const double* mean, const double* var, int32_t first, double* alpha,
                      double* beta, double* bias);
 
+/* Quasi-Monte Carlo points for a reference mean (abstract and Sec. 5,
+ * Fig. 11: the paper checks MLMC against a QMC mean on its finest mesh; its
+ * set-up names the Halton sequence).  For k = 0..count-1, d = 0..dim-1:
+ *   xi[k][d] = 2 frac(phi_{b_d}(first + k) + shift[d]) - 1   in [-1, 1),
+ * phi_b the radical inverse in base b (the base-b digits of the index
+ * mirrored about the radix point), b_d the d-th prime (2, 3, 5, ...).
+ * shift: host, dim values in [0, 1), or NULL for none -- a Cranley-Patterson
+ * rotation; independent uniform shifts give independent unbiased estimates
+ * whose spread estimates the QMC error.  xi: host [count][dim] row-major,
+ * caller-owned; the points feed HENRY_FIELD_CLOSED3 (dim 3) like
+ * henry_sample_xi's.  Index 0 is the origin of the sequence; a rule usually
+ * starts at first = 1.  Each phi_b is correctly rounded (exact in base 2).
+ * Errors: HENRY_EINVAL (first < 0, count < 0, first + count > 2^31,
+ * dim outside 1..16, a shift outside [0, 1), xi NULL with count > 0). */
+int henry_qmc_points(int64_t first, int64_t count, int32_t dim, const double* shift, double* xi);
+
 #ifdef __cplusplus
 }
 #endif

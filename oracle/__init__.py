@@ -287,6 +287,9 @@ def optimal_samples(V, s, eps2):
 
 # ---------------------------------------------------------------- QMC
 def radical_inverse(k: int, base: int) -> float:
+    """Van der Corput radical inverse: the base-`base` digits of k mirrored
+    about the radix point, summed digit by digit (the QMC reference of the
+    abstract and of Sec. 5, Fig. 11, whose set-up names Halton points)."""
     f, r = 1.0, 0.0
     while k > 0:
         f /= base
@@ -299,3 +302,14 @@ def halton(n: int, dim: int = 3, skip: int = 1) -> np.ndarray:
     """First n Halton points (bases 2, 3, 5, ...) starting at index `skip`."""
     bases = [2, 3, 5, 7, 11, 13][:dim]
     return np.array([[radical_inverse(k, b) for b in bases] for k in range(skip, skip + n)])
+
+
+def qmc_xi(n: int, dim: int = 3, skip: int = 1, shift=None) -> np.ndarray:
+    """Halton points as uniform coefficients on [-1, 1)^dim: each unit-cube
+    point rotated by `shift` modulo 1 (a Cranley-Patterson random shift;
+    None: no rotation), then mapped by u -> 2u - 1."""
+    u = halton(n, dim, skip)
+    if shift is not None:
+        u = u + np.asarray(shift, dtype=np.float64)
+        u = np.where(u >= 1.0, u - 1.0, u)
+    return 2.0 * u - 1.0

@@ -28,7 +28,7 @@ EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opt
            "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_tune_set", "henry_tune_get",
            "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
            "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch", "henry_mlmc_allocate",
-           "henry_mlmc_rates")
+           "henry_mlmc_rates", "henry_qmc_points")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -111,6 +111,7 @@ def lib():
                                    ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     L.henry_residual_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                        ct.c_size_t, vp]
+    L.henry_qmc_points.argtypes = [i64, i64, i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     L.henry_tune_set.argtypes = [vp, i32, i32, i32]
     L.henry_tune_get.argtypes = [vp, i32, i32, ct.POINTER(i32)]
     L.henry_adjoint_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), i32,
@@ -161,6 +162,20 @@ def henry_sample_xi(seed: int, level: int, first: int, count: int, dim: int = 3)
     out = np.empty((count, dim), np.float64)
     _chk(lib().henry_sample_xi(seed, level, first, count, dim, out.ctypes.data_as(ct.POINTER(ct.c_double))),
          "henry_sample_xi")
+    return out
+
+
+def henry_qmc_points(first: int, count: int, dim: int = 3, shift=None):
+    """Halton points 2 frac(phi(first + k) + shift) - 1, [count][dim] on the host."""
+    import numpy as np
+    out = np.empty((max(count, 0), max(dim, 0)), np.float64)
+    sh = None
+    if shift is not None:
+        sh = np.ascontiguousarray(shift, dtype=np.float64)
+        if sh.shape != (max(dim, 0),):
+            raise ValueError(f"shift must have {dim} entries")
+    _chk(lib().henry_qmc_points(first, count, dim, None if sh is None else sh.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                out.ctypes.data_as(ct.POINTER(ct.c_double))), "henry_qmc_points")
     return out
 
 
@@ -543,3 +558,21 @@ def mlmc_run(*args, **kwargs):
     """Adaptive MLMC estimate of E[Q] (see paper_2302_07804_amd.mlmc.mlmc_run)."""
     from .mlmc import mlmc_run as run
     return run(*args, **kwargs)
+
+
+def qmc_run(*args, **kwargs):
+    """Randomly shifted Halton estimate of E[Q] and E[c] (see paper_2302_07804_amd.mlmc.qmc_run)."""
+    from .mlmc import qmc_run as run
+    return run(*args, **kwargs)
+
+
+def point_cell(*args, **kwargs):
+    """Cell index of a point (see paper_2302_07804_amd.mlmc.point_cell)."""
+    from .mlmc import point_cell as pc
+    return pc(*args, **kwargs)
+
+
+def telescoped_at(*args, **kwargs):
+    """MLMC estimates at a point truncated after each level (see paper_2302_07804_amd.mlmc.telescoped_at)."""
+    from .mlmc import telescoped_at as tel
+    return tel(*args, **kwargs)

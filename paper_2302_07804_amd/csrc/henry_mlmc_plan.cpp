@@ -1,6 +1,7 @@
 // henry_mlmc_plan.cpp -- host-side planning of an MLMC run (Sec. 3): the
 // sample allocation of eq:M_ell and the convergence-rate fits and bias
-// estimate behind the MSE split eq:MSE.  Plain host arithmetic; the solves
+// estimate behind the MSE split eq:MSE; and the quasi-Monte Carlo points of
+// the reference mean (abstract; Sec. 5, Fig. 11).  Plain host arithmetic; the solves
 // and the level statistics run on the GPU (henry_solve_batch,
 // mlmc_level_estimate).
 #include <cmath>
@@ -24,9 +25,42 @@ double ls_slope(const double* y, int first, int n) {
     return sxy / sxx;
 }
 
+constexpr int kPrimes[16] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53};
+
+// Radical inverse of k in base b: the base-b digits of k mirrored about the
+// radix point.  The mirrored digits form an integer R over b^n (n = number of
+// digits); for k < 2^31 and b <= 53 both are below 2^37, so the one division
+// gives the correctly rounded value.
+double radical_inverse(int64_t k, int b) {
+    int64_t R = 0, D = 1;
+    for (; k > 0; k /= b) {
+        R = R * b + k % b;
+        D *= b;
+    }
+    return (double)R / (double)D;
+}
+
 }  // namespace
 
 extern "C" {
+
+int henry_qmc_points(int64_t first, int64_t count, int32_t dim, const double* shift, double* xi) {
+    if (first < 0 || count < 0 || count > (int64_t(1) << 31) - first || dim < 1 || dim > 16) return HENRY_EINVAL;
+    if (count > 0 && !xi) return HENRY_EINVAL;
+    if (shift)
+        for (int d = 0; d < dim; ++d)
+            if (!(shift[d] >= 0.0 && shift[d] < 1.0)) return HENRY_EINVAL;
+    for (int64_t k = 0; k < count; ++k)
+        for (int d = 0; d < dim; ++d) {
+            double u = radical_inverse(first + k, kPrimes[d]);
+            if (shift) {
+                u += shift[d];
+                if (u >= 1.0) u -= 1.0;  // the rotation is taken modulo 1
+            }
+            xi[k * dim + d] = 2.0 * u - 1.0;
+        }
+    return HENRY_OK;
+}
 
 int henry_mlmc_allocate(int32_t nlevels, const double* V, const double* s, double eps2, int64_t* m_out,
                         double* cost_out) {

@@ -5,17 +5,22 @@ the sample counts for the estimator variance eps^2 / 2; the final batch
 solves every level's samples at once; the MSE split eq:MSE checks the bias
 of the finest level, estimated from the fitted weak rate.
 
+The quasi-Monte Carlo reference of Sec. 5 (Fig. 11): a randomly shifted
+Halton rule on one fine grid gives E[Q] and E[c] with an error estimate from
+the spread of the shifts; MLMC estimates truncated after each level are
+compared with it at a point.
+
 Orchestration only: the solves (henry_solve_batch), the level statistics
-(mlmc_level_estimate) and the planning arithmetic (henry_mlmc_allocate,
-henry_mlmc_rates) are calls into libhenry."""
+(mlmc_level_estimate), the points (henry_qmc_points) and the planning
+arithmetic (henry_mlmc_allocate, henry_mlmc_rates) are calls into libhenry."""
 from __future__ import annotations
 
 import time
 
 import numpy as np
 
-from . import (FIELD_CLOSED3, Context, Opts, henry_mlmc_allocate, henry_mlmc_rates, henry_sample_xi,
-               mlmc_level_estimate, solve)
+from . import (FIELD_CLOSED3, Context, Opts, henry_mlmc_allocate, henry_mlmc_rates, henry_qmc_points,
+               henry_sample_xi, mlmc_level_estimate, solve)
 
 
 def _pairs(levels, m, seed):
@@ -57,7 +62,7 @@ def _level_statistics(ctx, levels, m, outs):
     mlmc_level_estimate(ctx, levels, m, c_fine, c_coarse, q_fine, q_coarse, mean_Y, var_Y, qstats, Ec, var_est)
     torch.cuda.synchronize(dev)
     qs = qstats.cpu().numpy().reshape(L + 1, 2)
-    return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec
+    return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y
 
 
 def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0, opts: Opts | None = None,
@@ -69,8 +74,8 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
     Returns a dict: EQ (sum of the level means), var_est (sum V_l / m_l),
     m, V, s (seconds per sample at each level, fine and coarse solve), the
     level means, alpha, beta, the bias estimate, mse_ok (var_est <= eps^2/2
-    and bias^2 <= eps^2/2), the final batch's seconds, and E[c] on the
-    finest grid (device tensor)."""
+    and bias^2 <= eps^2/2), the final batch's seconds, E[c] on the finest
+    grid and the level mean fields of Y_l = c_l - c_{l-1} (device tensors)."""
     import torch
     levels = [tuple(int(v) for v in g) for g in levels]
     L = len(levels) - 1
@@ -88,7 +93,7 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
         torch.cuda.synchronize(dev)
         s.append((time.perf_counter() - t0) / m_pilot)
         pilot.append((sol, out, rng[l]))
-    mean_p, V, _, _ = _level_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
+    mean_p, V, _, _, _ = _level_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
     # ---- allocation (eq:M_ell) for the variance half of the MSE (eq:MSE)
     m, cost = henry_mlmc_allocate(V, np.array(s), eps * eps / 2)
     m = np.maximum(m, m_pilot)
@@ -103,7 +108,7 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
     torch.cuda.synchronize(dev)
     seconds = time.perf_counter() - t0
     status = out["status"].cpu().numpy()
-    mean, var, var_est, Ec = _level_statistics(ctx, levels, m, [(sol, out, r) for r in rng])
+    mean, var, var_est, Ec, mean_Y = _level_statistics(ctx, levels, m, [(sol, out, r) for r in rng])
     alpha = beta = bias = float("nan")
     if L >= 2:
         alpha, beta, bias = henry_mlmc_rates(mean, var, 1)
@@ -111,4 +116,68 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
     return dict(EQ=float(mean.sum()), var_est=var_est, m=m, V=var, V_pilot=V, s=np.array(s), mean=mean,
                 alpha=alpha, beta=beta, bias=bias, planned_cost=cost,
                 mse_ok=bool(var_est <= half * (1 + 1e-12) and (L < 2 or bias * bias <= half)),
-                seconds=seconds, nonconverged=int((status != 0).sum()), Ec=Ec)
+                seconds=seconds, nonconverged=int((status != 0).sum()), Ec=Ec, mean_Y=mean_Y)
+
+
+def point_cell(grid, x: float, y: float) -> int:
+    """Index in the [ny][nx] layout of the cell of `grid` that contains the
+    point (x, y) of D = [0,2] x [-1,0].  The finite-volume solution is
+    constant per cell, so this cell's value is the solution at the point,
+    and on nested grids the injected coarse value at the point is the
+    coarse cell's.  A point on a cell face is ambiguous and rejected."""
+    nx, ny = int(grid[0]), int(grid[1])
+    if not (0.0 < x < 2.0 and -1.0 < y < 0.0):
+        raise ValueError(f"({x}, {y}) is not inside the domain")
+    u, v = x * ny, (y + 1.0) * ny  # h = 1 / ny
+    if u == int(u) or v == int(v):
+        raise ValueError(f"({x}, {y}) lies on a cell face of {nx}x{ny}")
+    return int(v) * nx + int(u)
+
+
+def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts | None = None):
+    """Quasi-Monte Carlo estimate of E[Q] and E[c] on one grid (nx, ny,
+    nsteps): R = len(shifts) Halton rules of n points each, rule r rotated
+    by shifts[r] (values in [0, 1); None: one unshifted rule), all R*n
+    solves in one batch.  Returns a dict: EQ (mean over all points),
+    EQ_shift (the R rule means), se (their standard deviation over sqrt(R),
+    the usual error estimate of a randomly shifted rule; nan for R = 1), Ec
+    (mean field) and Ec_shift (each rule's mean field; device tensors),
+    seconds (the batch), nonconverged."""
+    import torch
+    grid = tuple(int(v) for v in grid)
+    if n < 2:
+        raise ValueError("a QMC rule needs at least two points")
+    shifts = [None] if shifts is None else [np.asarray(sh, dtype=np.float64) for sh in shifts]
+    R = len(shifts)
+    dev = torch.device("cuda", ctx.device)
+    xi = np.concatenate([henry_qmc_points(first, n, 3, sh) for sh in shifts])
+    xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+    sol = [grid] * (R * n)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    out = solve(ctx, sol, xi=xi_d, opts=opts)
+    torch.cuda.synchronize(dev)
+    seconds = time.perf_counter() - t0
+    status = out["status"].cpu().numpy()
+    cells = grid[0] * grid[1]
+    mean, _, _, Ec, _ = _level_statistics(ctx, [grid], [R * n], [(sol, out, (0, R * n, R * n))])
+    per, Ec_shift = [], []
+    for r in range(R):
+        sl = dict(c=out["c"][r * n * cells:(r + 1) * n * cells], qoi=out["qoi"][r * n:(r + 1) * n])
+        mr, _, _, Er, _ = _level_statistics(ctx, [grid], [n], [(sol[:n], sl, (0, n, n))])
+        per.append(float(mr[0]))
+        Ec_shift.append(Er)
+    per = np.array(per)
+    se = float(per.std(ddof=1) / np.sqrt(R)) if R > 1 else float("nan")
+    return dict(EQ=float(mean[0]), EQ_shift=per, se=se, Ec=Ec, Ec_shift=Ec_shift, seconds=seconds,
+                nonconverged=int((status != 0).sum()))
+
+
+def telescoped_at(levels, mean_Y, x: float, y: float) -> np.ndarray:
+    """MLMC estimates of E[c] at the point (x, y) truncated after each level:
+    entry L is the sum over l <= L of level l's mean difference field at the
+    cell containing the point (the partial sums of the telescoping estimator
+    eq:A that Fig. 11 compares with the reference).  mean_Y[l] is level l's
+    field on grid l, as mlmc_run returns it."""
+    vals = [float(mean_Y[l][point_cell(levels[l], x, y)].item()) for l in range(len(levels))]
+    return np.cumsum(vals)

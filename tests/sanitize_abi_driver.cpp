@@ -4,6 +4,7 @@
 // arguments, and the compute entry points' argument validation, which runs
 // before anything touches a device.  Exits 0 when every call returns the
 // expected code; the sanitizers abort on a memory error.
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -32,6 +33,27 @@ int main() {
     EXPECT(henry_sample_xi(7, 0, 0, 17, 3, nullptr) == HENRY_EINVAL);
     EXPECT(henry_sample_xi_kl(7, 6, 3, 5, xk.data()) == HENRY_OK);
     EXPECT(henry_sample_xi_kl(7, 6, 3, -1, xk.data()) == HENRY_EINVAL);
+
+    // QMC points, up to the largest index the call accepts
+    std::vector<double> hq(64 * 16);
+    const double sh[3] = {0.25, 0.5, 0.999};
+    EXPECT(henry_qmc_points(1, 64, 16, nullptr, hq.data()) == HENRY_OK);
+    EXPECT(henry_qmc_points(((int64_t)1 << 31) - 64, 64, 3, sh, hq.data()) == HENRY_OK);
+    EXPECT(henry_qmc_points(((int64_t)1 << 31) - 63, 64, 3, sh, hq.data()) == HENRY_EINVAL);
+    EXPECT(henry_qmc_points(INT64_MAX, 1, 3, nullptr, hq.data()) == HENRY_EINVAL);
+    EXPECT(henry_qmc_points(1, 4, 17, nullptr, hq.data()) == HENRY_EINVAL);
+
+    // MLMC planning
+    {
+        const double V[4] = {1e-3, 1e-4, 2e-5, 4e-6}, s[4] = {1.0, 4.0, 16.0, 64.0};
+        const double mean[4] = {0.5, 0.02, 0.01, 0.005};
+        int64_t mm[4];
+        double cost = 0.0, a = 0.0, bt = 0.0, bias = 0.0;
+        EXPECT(henry_mlmc_allocate(4, V, s, 1e-6, mm, &cost) == HENRY_OK && mm[0] > mm[3]);
+        EXPECT(henry_mlmc_allocate(4, V, s, 0.0, mm, &cost) == HENRY_EINVAL);
+        EXPECT(henry_mlmc_rates(4, mean, V, 1, &a, &bt, &bias) == HENRY_OK && a > 0.0);
+        EXPECT(henry_mlmc_rates(65, mean, V, 1, &a, &bt, &bias) == HENRY_EINVAL);
+    }
 
     // KL basis on small grids, and its argument checks
     for (int ny : {1, 2, 8, 16}) {

@@ -2,7 +2,11 @@
 counts are eq:M_ell of the driver's own pilot variances and measured costs
 (the oracle's allocation), and the estimate E[Q], the estimator variance
 and the fitted rates equal those of oracle solves of the same samples (keys
-(seed, l, i), FP64 path at tol 1e-10: Q agrees to ~1e-11)."""
+(seed, l, i), FP64 path at tol 1e-10: Q agrees to ~1e-11).  The estimates
+truncated after each level at the point (1.60, -0.95) of Fig. 11 equal the
+oracle's level means of c there.  The randomly shifted Halton reference
+(qmc_run) equals the mean of oracle solves of the oracle's own shifted
+Halton points: E[Q], each rule's mean and the E[c] field."""
 import numpy as np
 import pytest
 
@@ -46,9 +50,11 @@ def test_adaptive_mlmc_matches_oracle(torch_cuda):
                 where.append((l, 1))
                 jobs.append((*levels[l - 1], xi[i]))
     refs = oracle.solve_many(hi.PHYS, jobs)
-    q = {}
+    q, cp = {}, {}
     for (l, side), r in zip(where, refs):
         q.setdefault((l, side), []).append(r["qoi"])
+        ny = r["c"].shape[0]
+        cp.setdefault((l, side), []).append(r["c"][int(0.05 * ny), int(1.60 * ny)])  # cell of (1.60, -0.95)
     means, vars_ = [], []
     for l in range(len(levels)):
         mean, var = oracle.level_stats(np.array(q[(l, 0)]), np.array(q[(l, 1)]) if l > 0 else None)
@@ -60,3 +66,44 @@ def test_adaptive_mlmc_matches_oracle(torch_cuda):
     lev = np.arange(1, len(levels))
     assert res["alpha"] == pytest.approx(-np.polyfit(lev, np.log2(np.abs(means[1:])), 1)[0], rel=1e-6)
     assert res["beta"] == pytest.approx(-np.polyfit(lev, np.log2(vars_[1:]), 1)[0], rel=1e-6)
+
+    # truncated estimates at the point of Fig. 11
+    pm = [float(oracle.level_stats(np.array(cp[(l, 0)]), np.array(cp[(l, 1)]) if l > 0 else None)[0])
+          for l in range(len(levels))]
+    tel = hm.telescoped_at(levels, res["mean_Y"], 1.60, -0.95)
+    np.testing.assert_allclose(tel, np.cumsum(pm), rtol=1e-8, atol=1e-11)
+    print(f"E[c(1.60, -0.95)] truncated after each level: {tel}")
+
+
+def test_qmc_reference_matches_oracle(torch_cuda):
+    grid, n = (16, 8, 50), 24
+    shifts = [np.array([0.11, 0.52, 0.93]), np.array([0.77, 0.05, 0.38]), np.array([0.0, 0.0, 0.0])]
+    ctx = hm.Context(hi.PHYS, 0)
+    res = hm.qmc_run(ctx, grid, n, shifts=shifts, opts=hm.make_opts(prec=hm.PREC_FP64, tol=1e-10, max_outer=60))
+    Ec = res["Ec"].cpu().numpy()
+    ctx.close()
+    assert res["nonconverged"] == 0
+    jobs = [(*grid, x) for sh in shifts for x in oracle.qmc_xi(n, 3, 1, sh)]
+    refs = oracle.solve_many(hi.PHYS, jobs)
+    q = np.array([r["qoi"] for r in refs])
+    c = np.array([r["c"].ravel() for r in refs])
+    np.testing.assert_allclose(res["EQ_shift"], q.reshape(len(shifts), n).mean(axis=1), rtol=1e-9)
+    assert res["EQ"] == pytest.approx(q.mean(), rel=1e-9)
+    assert res["se"] == pytest.approx(q.reshape(len(shifts), n).mean(axis=1).std(ddof=1) / np.sqrt(len(shifts)),
+                                      rel=1e-5)
+    np.testing.assert_allclose(Ec, c.mean(axis=0), rtol=0, atol=1e-9)
+    print(f"QMC E[Q] = {res['EQ']:.8f} +- {res['se']:.2e}")
+
+
+def test_telescoped_sum_of_all_levels_is_the_finest_mean(torch_cuda):
+    """The estimate after the last level equals the finest E[c] field's
+    value at the point: the point functional commutes with the injection."""
+    levels = [(16, 8, 20), (32, 16, 40), (64, 32, 80)]
+    ctx = hm.Context(hi.PHYS, 0)
+    res = hm.mlmc_run(ctx, levels, 0.5, m_pilot=8, seed=2, max_samples=8,
+                      opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-9, max_outer=60))
+    Ec = res["Ec"].cpu().numpy()
+    ctx.close()
+    for x, y in ((1.60, -0.95), (0.30, -0.20), (1.97, -0.61)):
+        tel = hm.telescoped_at(levels, res["mean_Y"], x, y)
+        assert tel[-1] == pytest.approx(Ec[hm.point_cell(levels[-1], x, y)], rel=1e-12, abs=1e-15)
