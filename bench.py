@@ -167,6 +167,10 @@ def main():
                     help="compare the MLMC estimates truncated after each level with a randomly shifted Halton "
                          "reference (POINTS points x SHIFTS shifts) on 512x256/1600, at (1.60, -0.95) and for E[Q] "
                          "(default 128 4 with the other workloads, ~25 s)")
+    ap.add_argument("--paper-setup", action="store_true",
+                    help="the paper's own set-up (two-layer porosity, Table 1 constants, T = 6016 s, 32x16-based "
+                         "hierarchy with r0 = 188): one-sample solve times per level 0..5 and the MLMC run with "
+                         "Table 3's counts for eps^2 = 1e-7 (~100 s)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of CALIB_BYTES before the batch (HBM-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -479,6 +483,40 @@ def main():
             rel_err_EQ=[float(abs(v - qr["EQ"]) / abs(qr["EQ"])) for v in tel_q])
         log(f"QMC {npts}x{nsh} on {ref_grid}: {qr['seconds']:.1f} s, E[Q] = {qr['EQ']:.6f} +- {qr['se']:.1e}, "
             f"c(1.60,-0.95) = {Ec_ref:.6f}; MLMC by level c: {tel_c}, E[Q]: {tel_q}")
+
+    if args.paper_setup:
+        extras = extras if extras is not None else {}
+        pctx = hm.Context(hi.PHYS_TABLE1, 0)
+        popts = hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60)
+        pxi = torch.tensor(hm.henry_sample_xi(hi.SEED, 30, 0, 1, 3), dtype=torch.float64, device=dev)
+        per_sample = {}
+        for l in range(6):
+            g = hi.paper_level_grid(l)
+            hm.solve(pctx, [(g[0], g[1], 2)], xi=pxi, opts=popts, model="two_layer")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            o = hm.solve(pctx, [g], xi=pxi, opts=popts, model="two_layer")
+            torch.cuda.synchronize()
+            per_sample[f"{g[0]}x{g[1]}/{g[2]}"] = dict(seconds=time.perf_counter() - t,
+                                                       outer_iters_per_step=int(o["iters"].item()) / g[2],
+                                                       status=int(o["status"].item()))
+            log(f"paper set-up, one sample on {g}: {per_sample[f'{g[0]}x{g[1]}/{g[2]}']}")
+            del o
+        m3 = [1714, 344, 78, 14, 4, 2]
+        plevels = [hi.paper_level_grid(l) for l in range(6)]
+        pr = hm.mlmc_fixed(pctx, plevels, m3, seed=hi.SEED, opts=popts, model="two_layer")
+        tel = hm.telescoped_at(plevels, pr["mean_Y"], 1.60, -0.95)
+        vpt = [float(pr["var_Y"][l][hm.point_cell(plevels[l], 1.60, -0.95)].item()) for l in range(6)]
+        extras["paper_setup"] = dict(
+            workload="two-layer porosity (eq:poro_2levels), Kozeny-Carman K, recharge +-50 %, Table 1 constants, "
+                     "T = 6016 s, levels 32x16/188 .. 1024x512/6016",
+            one_sample=per_sample,
+            table3_run=dict(m=m3, seconds=pr["seconds"], nonconverged=pr["nonconverged"], EQ=pr["EQ"],
+                            c_point_by_level=[float(v) for v in tel], V_c_point=vpt,
+                            V_Q=[float(v) for v in pr["V"]], alpha=pr["alpha"], beta=pr["beta"]))
+        log(f"paper set-up, Table 3 counts (eps^2 = 1e-7): {pr['seconds']:.1f} s, {pr['nonconverged']} "
+            f"non-converged, c(1.60,-0.95) by level {tel}, V at the point {vpt}")
+        pctx.close()
 
     res = {
         "metric": "Henry sample solves/s (cell-steps/s) batched vs plain, same 1e-5 E[c] error",

@@ -28,6 +28,19 @@ PHYS_ORDER = ("rho0", "rho1", "mu", "g", "D", "phi0", "k0", "q_in", "T")
 
 SEED = 0
 
+# The paper's own set-up (Table 1 and Sec. 4): Table 1's constants, the
+# recharge 6.6e-2 kg/s read as 6.6e-5 m/s of fresh water, T = 6016 s, and a
+# hierarchy that starts from 32 x 16 cells with r0 = 188 steps (Table 2).
+# Its random fields are the two-layer porosity model (field model
+# "two_layer").
+PHYS_TABLE1 = dict(rho0=1000.0, rho1=1024.99, mu=1e-3, g=9.8, D=18.8571e-6,
+                   phi0=0.35, k0=1.020408e-9, q_in=6.6e-5, T=6016.0)
+
+
+def paper_level_grid(level: int) -> tuple[int, int, int]:
+    """(nx, ny, nsteps) of level `level` of the paper's hierarchy."""
+    return 32 << level, 16 << level, 188 << level
+
 
 def level_grid(level: int) -> tuple[int, int, int]:
     """(nx, ny, nsteps) of hierarchy level `level`."""

@@ -79,10 +79,21 @@ typedef struct {
  *             Z_phi = sum_{k<20} sqrt(lam_k) e_k xi_k, Z_K with xi_{20+k},
  *             q = q_in (1 + 0.2 xi_41); every grid of the call needs a basis.
  *   EXPLICIT: the caller passes packed per-cell phi and log K and a
- *             per-solve recharge q[k] (m/s). */
+ *             per-solve recharge q[k] (m/s).
+ *   TWOLAYER3: xi[k][3], the paper's own model (Sec. 4, eq:poro_2levels,
+ *             eq:poro_2levels_C, e_perm_Kozeny_Carman):
+ *             phi = phi0 (1 + 0.15 (xi2 cos(pi x/2) + xi2 sin(2 pi y)
+ *                   + xi1 cos(2 pi x))) C0, C0 = 1 + 0.2 xi1 below
+ *                   y = -0.75 and 1 - 0.2 xi1 above (a cell face for
+ *                   ny >= 4; the cell centre decides),
+ *             K = kappa phi^3 / (1 - phi^2), kappa = k0 (1 - phi0^2) / phi0^3
+ *                   so that K(phi0) = k0,
+ *             q = q_in (1 + 0.5 xi3).  phi stays within [0.44, 1.74] phi0,
+ *             so the call needs phi0 < 1/1.74 (HENRY_EINVAL otherwise). */
 #define HENRY_FIELD_CLOSED3 0
 #define HENRY_FIELD_KL41 1
 #define HENRY_FIELD_EXPLICIT 2
+#define HENRY_FIELD_TWOLAYER3 3
 
 /* Inner precision of the multigrid / line-relaxation preconditioner.  The
  * outer nonlinear residual, the state, the buoyancy term and every
@@ -214,7 +225,8 @@ int henry_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t ns
  * and step counts share one call.
  *   solves   host [nsolves]
  *   field    HENRY_FIELD_*
- *   xi       device [nsolves][3] (CLOSED3) else ignored
+ *   xi       device [nsolves][3] (CLOSED3, TWOLAYER3), [nsolves][41] (KL41),
+ *            else ignored
  *   phi,logk device packed per-cell fields (EXPLICIT) else ignored
  *   qin      device [nsolves] recharge in m/s (EXPLICIT) else ignored
  *   c0       device packed initial salt mass fraction, or NULL for c = 0
@@ -270,8 +282,8 @@ int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, in
  * steps and recomputes each segment (bitwise the same states) during the
  * reverse sweep.
  *   qoi_out   device [nsolves]
- *   dq_dxi    device [nsolves][3] (CLOSED3) or [nsolves][41] (KL41); must be
- *             NULL for EXPLICIT
+ *   dq_dxi    device [nsolves][3] (CLOSED3, TWOLAYER3) or [nsolves][41]
+ *             (KL41); must be NULL for EXPLICIT
  *   dq_dlogk  device packed per cell, dQ/d(log K), or NULL
  *   dq_dphi   device packed per cell, dQ/dphi, or NULL
  *   dq_dq     device [nsolves], dQ/dq (q in m/s), or NULL
@@ -330,7 +342,7 @@ int henry_mlmc_allocate(int32_t nlevels, const double* V, const double* s, doubl
 int henry_mlmc_rates(int32_t nlevels, const double* mean, const double* var, int32_t first, double* alpha,
                      double* beta, double* bias);
 
-/* Quasi-Monte Carlo points for a reference mean (abstract and Sec. 5,
+/* Quasi-Monte Carlo points for a reference mean (abstract and Sec. 4,
  * Fig. 11: the paper checks MLMC against a QMC mean on its finest mesh; its
  * set-up names the Halton sequence).  For k = 0..count-1, d = 0..dim-1:
  *   xi[k][d] = 2 frac(phi_{b_d}(first + k) + shift[d]) - 1   in [-1, 1),

@@ -117,6 +117,47 @@ def fields_closed(phys, nx, ny, xi):
     return phi, K, float(q[0])
 
 
+def fields_two_layer(phys, nx, ny, xi):
+    """The paper's own random inputs (Sec. 4: eq:poro_2levels,
+    eq:poro_2levels_C; Sec. 2.2: e_perm_Kozeny_Carman), at cell centres:
+    porosity in two horizontal layers split at y = -0.75, each scaled by its
+    own factor C0(xi1); a Kozeny-Carman permeability whose scale makes
+    K(phi0) = k0; the recharge with a +-50 % amplitude."""
+    h = 1.0 / ny
+    x = (np.arange(nx) + 0.5) * h
+    y = -1.0 + (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    x1, x2, x3 = (float(v) for v in xi)
+    C0 = np.where(Y < -0.75, 1.0 + 0.2 * x1, 1.0 - 0.2 * x1)
+    phi = phys["phi0"] * (1.0 + 0.15 * (x2 * np.cos(np.pi * X / 2) + x2 * np.sin(2 * np.pi * Y)
+                                        + x1 * np.cos(2 * np.pi * X))) * C0
+    kappa = phys["k0"] * (1.0 - phys["phi0"] ** 2) / phys["phi0"] ** 3
+    K = kappa * phi ** 3 / (1.0 - phi ** 2)
+    return phi, K, phys["q_in"] * (1.0 + 0.5 * x3)
+
+
+def field_derivs_two_layer(phys, nx, ny, xi):
+    """d(phi)/d(xi_k) and d(K)/d(xi_k) per cell for k = 1, 2 ([2][ny][nx]
+    each) and d(q)/d(xi3) of the two-layer model, by the product and chain
+    rules on fields_two_layer's formulas."""
+    h = 1.0 / ny
+    x = (np.arange(nx) + 0.5) * h
+    y = -1.0 + (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    x1, x2 = float(xi[0]), float(xi[1])
+    a = np.cos(np.pi * X / 2) + np.sin(2 * np.pi * Y)
+    b = np.cos(2 * np.pi * X)
+    s = np.where(Y < -0.75, 0.2, -0.2)
+    B = 1.0 + 0.15 * (x2 * a + x1 * b)
+    C0 = 1.0 + s * x1
+    phi0 = phys["phi0"]
+    dphi = np.array([phi0 * (0.15 * b * C0 + B * s), phi0 * 0.15 * a * C0])
+    phi = phi0 * B * C0
+    kappa = phys["k0"] * (1.0 - phi0 ** 2) / phi0 ** 3
+    dK_dphi = kappa * (3 * phi ** 2 * (1 - phi ** 2) + 2 * phi ** 4) / (1 - phi ** 2) ** 2
+    return dphi, dK_dphi * dphi, phys["q_in"] * 0.5
+
+
 # ---------------------------------------------------------------- discrete operator
 def residual(phys, nsteps, phi, K, q, p, c, cn):
     lib = _load()
@@ -177,14 +218,17 @@ def solve(phys, nsteps, phi, K, q, c0=None, trajectory=False):
     return out
 
 
-def solve_xi(phys, nx, ny, nsteps, xi):
-    phi, K, q = fields_closed(phys, nx, ny, xi)
+def solve_xi(phys, nx, ny, nsteps, xi, model=None):
+    """Solve with the closed-form fields of xi, or with model="two_layer"
+    the two-layer porosity model."""
+    fields = fields_two_layer if model == "two_layer" else fields_closed
+    phi, K, q = fields(phys, nx, ny, xi)
     return solve(phys, nsteps, phi, K, q)
 
 
 def solve_many(phys, jobs, threads=None):
-    """jobs: list of (nx, ny, nsteps, xi).  One job per thread (ctypes drops
-    the GIL during the C call).  Returns list of result dicts."""
+    """jobs: list of (nx, ny, nsteps, xi[, model]).  One job per thread
+    (ctypes drops the GIL during the C call).  Returns list of result dicts."""
     threads = threads or len(_os.sched_getaffinity(0))
     with _cf.ThreadPoolExecutor(max_workers=threads) as ex:
         return list(ex.map(lambda jb: solve_xi(phys, *jb), jobs))
@@ -223,8 +267,15 @@ def field_derivs_closed(phys, nx, ny, xi):
     return dphi, dK, dq
 
 
-def adjoint_xi(phys, nx, ny, nsteps, xi):
-    """Q, dQ/dxi (3,), dQ/dlog K per cell [ny][nx] for the closed-form fields."""
+def adjoint_xi(phys, nx, ny, nsteps, xi, model=None):
+    """Q, dQ/dxi (3,), dQ/dlog K per cell [ny][nx] for the closed-form fields
+    (model="two_layer": the two-layer porosity model)."""
+    if model == "two_layer":
+        phi, K, q = fields_two_layer(phys, nx, ny, xi)
+        Q, gphi, gK, gq = adjoint(phys, nsteps, phi, K, q)
+        dphi, dK, dq = field_derivs_two_layer(phys, nx, ny, xi)
+        g = np.array([(gphi * dphi[k]).sum() + (gK * dK[k]).sum() for k in range(2)] + [gq * dq])
+        return Q, g, gK * K
     phi, K, q = fields_closed(phys, nx, ny, xi)
     Q, gphi, gK, gq = adjoint(phys, nsteps, phi, K, q)
     dphi, dK, dq = field_derivs_closed(phys, nx, ny, xi)
@@ -289,7 +340,7 @@ def optimal_samples(V, s, eps2):
 def radical_inverse(k: int, base: int) -> float:
     """Van der Corput radical inverse: the base-`base` digits of k mirrored
     about the radix point, summed digit by digit (the QMC reference of the
-    abstract and of Sec. 5, Fig. 11, whose set-up names Halton points)."""
+    abstract and of Sec. 4, Fig. 11, whose set-up names Halton points)."""
     f, r = 1.0, 0.0
     while k > 0:
         f /= base

@@ -20,7 +20,7 @@ _DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlm
 
 HENRY_OK, HENRY_EINVAL, HENRY_ENOMEM, HENRY_EHIP, HENRY_ENOCONV, HENRY_ENONFINITE = 0, -1, -2, -3, -4, -5
 STATUS_OK, STATUS_NOCONV, STATUS_NONFINITE, STATUS_SYNC = 0, 1, 2, 3
-FIELD_CLOSED3, FIELD_KL41, FIELD_EXPLICIT = 0, 1, 2
+FIELD_CLOSED3, FIELD_KL41, FIELD_EXPLICIT, FIELD_TWOLAYER3 = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 
 # every symbol the header declares
@@ -265,7 +265,7 @@ def henry_residual_batch(ctx: Context, solves, field, xi=None, phi=None, logk=No
     _chk(rc, "henry_residual_batch")
 
 
-def residual(ctx: Context, solves, p, c, cn, xi=None, phi=None, logk=None, qin=None, stream=None):
+def residual(ctx: Context, solves, p, c, cn, xi=None, phi=None, logk=None, qin=None, stream=None, model=None):
     """R^p, R^c (packed device tensors) of each solve's discrete equations at
     the state (p, c) with previous time level cn (packed device tensors)."""
     import torch
@@ -277,7 +277,7 @@ def residual(ctx: Context, solves, p, c, cn, xi=None, phi=None, logk=None, qin=N
     ws = ws[off:off + (ws_bytes + 7) // 8]
     rp = torch.empty(cells, dtype=torch.float64, device=dev)
     rc = torch.empty(cells, dtype=torch.float64, device=dev)
-    henry_residual_batch(ctx, solves, _field_of(xi), xi=xi, phi=phi, logk=logk, qin=qin, p=p, c=c, cn=cn,
+    henry_residual_batch(ctx, solves, _field_of(xi, model), xi=xi, phi=phi, logk=logk, qin=qin, p=p, c=c, cn=cn,
                          rp_out=rp, rc_out=rc, workspace=ws, stream=stream)
     return rp, rc
 
@@ -331,18 +331,26 @@ def mlmc_level_estimate(ctx: Context, fine_grids, m, c_fine, c_coarse, q_fine, q
 
 
 # ------------------------------------------------------------------ convenience layer
-def _field_of(xi):
+def _field_of(xi, model=None):
+    """HENRY_FIELD_* of a call: no xi -> explicit fields, 41 coefficients ->
+    KL, 3 -> the closed-form fields, or with model="two_layer" the two-layer
+    porosity model with Kozeny-Carman permeability."""
     if xi is None:
         return FIELD_EXPLICIT
-    return FIELD_KL41 if xi.shape[-1] == 41 else FIELD_CLOSED3
+    if xi.shape[-1] == 41:
+        return FIELD_KL41
+    if model not in (None, "closed", "two_layer"):
+        raise ValueError(f"unknown field model {model!r}")
+    return FIELD_TWOLAYER3 if model == "two_layer" else FIELD_CLOSED3
 
 
 def solve(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, c0=None, opts: Opts | None = None,
-          want_p=False, stream=None):
+          want_p=False, stream=None, model=None):
     """Allocate outputs/workspace with torch and run one batch.
     solves: list of (nx, ny, nsteps).  xi [n][3] selects the closed-form
-    fields, xi [n][41] the KL fields (Context.set_kl for every grid), no xi
-    the explicit fields.  Returns dict of device tensors."""
+    fields (model="two_layer": the two-layer porosity model), xi [n][41]
+    the KL fields (Context.set_kl for every grid), no xi the explicit
+    fields.  Returns dict of device tensors."""
     import torch
     dev = torch.device("cuda", ctx.device)
     opts = opts or opts_default()
@@ -357,7 +365,7 @@ def solve(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, c0=None,
                status=torch.empty(len(solves), dtype=torch.int32, device=dev),
                iters=torch.empty(len(solves), dtype=torch.int32, device=dev))
     out["p"] = torch.empty(cells, dtype=torch.float64, device=dev) if want_p else None
-    field = _field_of(xi)
+    field = _field_of(xi, model)
     henry_solve_batch(ctx, solves, field, xi=xi, phi=phi, logk=logk, qin=qin, c0=c0, opts=opts, c_out=out["c"],
                       p_out=out["p"], qoi_out=out["qoi"], status=out["status"], iters=out["iters"], workspace=ws,
                       stream=stream)
@@ -407,7 +415,7 @@ def _aligned_workspace(nbytes, dev):
 
 
 def adjoint(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, opts: Opts | None = None,
-            ckpt_every=20, adj_tol=1e-10, adj_max_it=60, stream=None):
+            ckpt_every=20, adj_tol=1e-10, adj_max_it=60, stream=None, model=None):
     """Allocate outputs and run the adjoint; returns dict of device tensors
     (qoi, dq_dxi for closed-form fields, dq_dlogk, dq_dphi, dq_dq, status)."""
     import torch
@@ -420,7 +428,7 @@ def adjoint(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, opts: 
     out = dict(qoi=torch.empty(ns, **f64), dq_dlogk=torch.empty(cells, **f64), dq_dphi=torch.empty(cells, **f64),
                dq_dq=torch.empty(ns, **f64), status=torch.empty(ns, dtype=torch.int32, device=dev),
                iters=torch.empty(ns, dtype=torch.int32, device=dev))
-    field = _field_of(xi)
+    field = _field_of(xi, model)
     out["dq_dxi"] = torch.empty((ns, xi.shape[-1]), **f64) if xi is not None else None
     henry_adjoint_batch(ctx, solves, field, xi=xi, phi=phi, logk=logk,
                         qin=qin, opts=opts, ckpt_every=ckpt_every, adj_tol=adj_tol, adj_max_it=adj_max_it,
@@ -576,3 +584,9 @@ def telescoped_at(*args, **kwargs):
     """MLMC estimates at a point truncated after each level (see paper_2302_07804_amd.mlmc.telescoped_at)."""
     from .mlmc import telescoped_at as tel
     return tel(*args, **kwargs)
+
+
+def mlmc_fixed(*args, **kwargs):
+    """MLMC estimate with given sample counts (see paper_2302_07804_amd.mlmc.mlmc_fixed)."""
+    from .mlmc import mlmc_fixed as run
+    return run(*args, **kwargs)

@@ -534,6 +534,9 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     const double gq = A.scr[0];
     const double h = S.h;
     double g1 = 0.0, g2 = 0.0;
+    const double x1 = lp.field_kind == 3 ? lp.xi[3 * d.index] : 0.0;
+    const double x2 = lp.field_kind == 3 ? lp.xi[3 * d.index + 1] : 0.0;
+    const double kappa = ph.k0 * (1.0 - ph.phi0 * ph.phi0) / (ph.phi0 * ph.phi0 * ph.phi0);
     for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
         const double KP = S.K[idx];
         if (al.dq_dlogk) al.dq_dlogk[d.field_off + idx] = A.gK[idx] * KP;
@@ -544,6 +547,19 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
             // derivatives of the closed-form fields with respect to xi1, xi2
             g1 += A.gphi[idx] * ph.phi0 * 0.2 * cos(M_PI * x / 2.0) * cos(M_PI * y);
             g2 += A.gK[idx] * KP * 0.5 * sin(M_PI * x / 2.0);
+        } else if (lp.field_kind == 3) {
+            // two-layer porosity: phi = phi0 B C0 with B = 1 + 0.15 (xi2 a + xi1 b),
+            // C0 = 1 +- 0.2 xi1; K = kappa phi^3 / (1 - phi^2), so
+            // dK/dphi = kappa phi^2 (3 - phi^2) / (1 - phi^2)^2
+            const int i = idx % S.nx, j = idx / S.nx;
+            const double x = (i + 0.5) * h, y = -1.0 + (j + 0.5) * h;
+            const double a = cos(M_PI * x / 2.0) + sin(2.0 * M_PI * y), b = cos(2.0 * M_PI * x);
+            const double sg = y < -0.75 ? 0.2 : -0.2;
+            const double B = 1.0 + 0.15 * (x2 * a + x1 * b), C0 = 1.0 + sg * x1;
+            const double fP = S.phi[idx], f2 = fP * fP;
+            const double gphi = A.gphi[idx] + A.gK[idx] * kappa * f2 * (3.0 - f2) / ((1.0 - f2) * (1.0 - f2));
+            g1 += gphi * ph.phi0 * (0.15 * b * C0 + B * sg);
+            g2 += gphi * ph.phi0 * 0.15 * a * C0;
         }
     }
     g1 = block_sum(g1, red);
@@ -571,10 +587,10 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
         lp.status[d.index] = status;
         if (lp.iters) lp.iters[d.index] = (int32_t)(fiters + aiters);
         if (al.dq_dq) al.dq_dq[d.index] = gq;
-        if (al.dq_dxi && lp.field_kind == 0) {
+        if (al.dq_dxi && (lp.field_kind == 0 || lp.field_kind == 3)) {
             al.dq_dxi[3 * d.index + 0] = g1;
             al.dq_dxi[3 * d.index + 1] = g2;
-            al.dq_dxi[3 * d.index + 2] = gq * ph.q_in * 0.2;
+            al.dq_dxi[3 * d.index + 2] = gq * ph.q_in * (lp.field_kind == 3 ? 0.5 : 0.2);
         }
     }
 }

@@ -35,6 +35,17 @@ static_assert(kLdsCells >= 2, "the coarsest level (2 x 1) must be in LDS");
 // all, within the 160 KB of one CU.  The FP64 arrays would not fit.
 constexpr int kLdsBlockCellsF32 = 2048;
 int lds_block_cells(int prec) { return prec == HENRY_PREC_MIXED ? kLdsBlockCellsF32 : 0; }
+
+// HENRY_FIELD_* to the fields kernel's branch: 0 closed form, 1 explicit,
+// 2 KL, 3 two-layer porosity
+int field_kind_of(int field) {
+    switch (field) {
+        case HENRY_FIELD_CLOSED3: return 0;
+        case HENRY_FIELD_KL41: return 2;
+        case HENRY_FIELD_TWOLAYER3: return 3;
+        default: return 1;
+    }
+}
 size_t lds_bytes(int nx, int ny, int prec) {
     return (size_t)(prec == HENRY_PREC_MIXED
                         ? henry::lds_level_bytes<float>(nx, ny, kLdsCells, lds_block_cells(prec))
@@ -458,8 +469,9 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     henry_opts_default(&def);
     const henry_opts_t* o = opts ? opts : &def;
     if (int rc = check_opts(o)) return rc;
-    if (field == HENRY_FIELD_CLOSED3) {
+    if (field == HENRY_FIELD_CLOSED3 || field == HENRY_FIELD_TWOLAYER3) {
         if (!xi) return HENRY_EINVAL;
+        if (field == HENRY_FIELD_TWOLAYER3 && !(1.74 * ctx->ph.phi0 < 1.0)) return HENRY_EINVAL;
     } else if (field == HENRY_FIELD_KL41) {
         if (!xi) return HENRY_EINVAL;
         for (int k = 0; k < nsolves; ++k)
@@ -539,7 +551,7 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
     lp.tol = o->tol;
     lp.max_outer = o->max_outer;
-    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : (field == HENRY_FIELD_KL41 ? 2 : 1);
+    lp.field_kind = field_kind_of(field);
     lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
 
     const int ng = (int)order.size();
@@ -620,8 +632,9 @@ int henry_residual_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nso
     if (!ctx || nsolves < 0) return HENRY_EINVAL;
     if (nsolves == 0) return HENRY_OK;
     if (!solves || !p || !c || !cn || !rp_out || !rc_out || !workspace) return HENRY_EINVAL;
-    if (field == HENRY_FIELD_CLOSED3) {
+    if (field == HENRY_FIELD_CLOSED3 || field == HENRY_FIELD_TWOLAYER3) {
         if (!xi) return HENRY_EINVAL;
+        if (field == HENRY_FIELD_TWOLAYER3 && !(1.74 * ctx->ph.phi0 < 1.0)) return HENRY_EINVAL;
     } else if (field == HENRY_FIELD_KL41) {
         if (!xi) return HENRY_EINVAL;
         for (int k = 0; k < nsolves; ++k)
@@ -676,7 +689,7 @@ int henry_residual_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nso
     lp.ws = ws;
     lp.xi = xi; lp.phi_in = phi; lp.logk_in = logk; lp.qin_in = qin;
     std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
-    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : (field == HENRY_FIELD_KL41 ? 2 : 1);
+    lp.field_kind = field_kind_of(field);
     lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
     lp.cluster = 1;
     for (const auto& st : starts) {
@@ -773,8 +786,9 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     const henry_opts_t* o = opts ? opts : &def;
     if (int rc = check_opts(o)) return rc;
     if (o->threads > kAdjMaxThreads) return HENRY_EINVAL;
-    if (field == HENRY_FIELD_CLOSED3) {
+    if (field == HENRY_FIELD_CLOSED3 || field == HENRY_FIELD_TWOLAYER3) {
         if (!xi) return HENRY_EINVAL;
+        if (field == HENRY_FIELD_TWOLAYER3 && !(1.74 * ctx->ph.phi0 < 1.0)) return HENRY_EINVAL;
     } else if (field == HENRY_FIELD_KL41) {
         if (!xi) return HENRY_EINVAL;
         for (int k = 0; k < nsolves; ++k)
@@ -848,7 +862,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
     lp.tol = o->tol;
     lp.max_outer = o->max_outer;
-    lp.field_kind = field == HENRY_FIELD_CLOSED3 ? 0 : (field == HENRY_FIELD_KL41 ? 2 : 1);
+    lp.field_kind = field_kind_of(field);
     lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
     henry::AdjLaunch al{};
     al.ckpt = ckpt_every;

@@ -1635,8 +1635,9 @@ __global__ void __launch_bounds__(1024) henry_residual_kernel(Launch lp, const d
 }
 
 // ------------------------------------------------------------------ random fields
-// Point values at cell centres of the closed-form fields, or the caller's
-// explicit fields; FP64.  One block per solve.
+// Point values at cell centres of the closed-form fields, of the KL
+// expansions, of the two-layer porosity model, or the caller's explicit
+// fields; FP64.  One block per solve.
 __global__ void henry_fields_kernel(Launch lp) {
     const SolveDesc d = lp.descs[blockIdx.x];
     const Phys& ph = lp.ph;
@@ -1671,6 +1672,23 @@ __global__ void henry_fields_kernel(Launch lp) {
             K[idx] = ph.k0 * exp(0.5 * x2 * sin(M_PI * x / 2.0));
         }
         if (threadIdx.x == 0) sp[0] = ph.q_in * (1.0 + 0.2 * x3);
+    } else if (lp.field_kind == 3) {
+        // two porosity layers split at y = -0.75 (eq:poro_2levels, eq:poro_2levels_C),
+        // Kozeny-Carman permeability (e_perm_Kozeny_Carman) scaled so that
+        // K(phi0) = k0, recharge q_in (1 + 0.5 xi3)
+        const double x1 = lp.xi[3 * d.index], x2 = lp.xi[3 * d.index + 1], x3 = lp.xi[3 * d.index + 2];
+        const double kappa = ph.k0 * (1.0 - ph.phi0 * ph.phi0) / (ph.phi0 * ph.phi0 * ph.phi0);
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+            const int i = idx % nx, j = idx / nx;
+            const double x = (i + 0.5) * h, y = -1.0 + (j + 0.5) * h;
+            const double layer = y < -0.75 ? 1.0 + 0.2 * x1 : 1.0 - 0.2 * x1;
+            const double fP =
+                ph.phi0 * (1.0 + 0.15 * (x2 * cos(M_PI * x / 2.0) + x2 * sin(2.0 * M_PI * y) + x1 * cos(2.0 * M_PI * x))) *
+                layer;
+            phi[idx] = fP;
+            K[idx] = kappa * fP * fP * fP / (1.0 - fP * fP);
+        }
+        if (threadIdx.x == 0) sp[0] = ph.q_in * (1.0 + 0.5 * x3);
     } else {
         for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
             phi[idx] = lp.phi_in[d.field_off + idx];

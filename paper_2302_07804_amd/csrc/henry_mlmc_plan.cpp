@@ -1,7 +1,7 @@
 // henry_mlmc_plan.cpp -- host-side planning of an MLMC run (Sec. 3): the
 // sample allocation of eq:M_ell and the convergence-rate fits and bias
 // estimate behind the MSE split eq:MSE; and the quasi-Monte Carlo points of
-// the reference mean (abstract; Sec. 5, Fig. 11).  Plain host arithmetic; the solves
+// the reference mean (abstract; Sec. 4, Fig. 11).  Plain host arithmetic; the solves
 // and the level statistics run on the GPU (henry_solve_batch,
 // mlmc_level_estimate).
 #include <cmath>

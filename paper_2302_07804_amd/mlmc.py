@@ -5,7 +5,7 @@ the sample counts for the estimator variance eps^2 / 2; the final batch
 solves every level's samples at once; the MSE split eq:MSE checks the bias
 of the finest level, estimated from the fitted weak rate.
 
-The quasi-Monte Carlo reference of Sec. 5 (Fig. 11): a randomly shifted
+The quasi-Monte Carlo reference of Sec. 4 (Fig. 11): a randomly shifted
 Halton rule on one fine grid gives E[Q] and E[c] with an error estimate from
 the spread of the shifts; MLMC estimates truncated after each level are
 compared with it at a point.
@@ -41,7 +41,7 @@ def _pairs(levels, m, seed):
     return solves, np.concatenate(xis), ranges
 
 
-def _level_statistics(ctx, levels, m, outs):
+def _level_statistics(ctx, levels, m, outs, with_var=False):
     """mlmc_level_estimate over per-level outputs: outs[l] = (solves, out,
     (f0, c0, c1)) with the fine solves f0..c0-1 and the coarse ones c0..c1-1."""
     import torch
@@ -62,15 +62,19 @@ def _level_statistics(ctx, levels, m, outs):
     mlmc_level_estimate(ctx, levels, m, c_fine, c_coarse, q_fine, q_coarse, mean_Y, var_Y, qstats, Ec, var_est)
     torch.cuda.synchronize(dev)
     qs = qstats.cpu().numpy().reshape(L + 1, 2)
+    if with_var:
+        return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y, var_Y
     return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y
 
 
 def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0, opts: Opts | None = None,
-             max_samples: int | None = None):
+             max_samples: int | None = None, model: str | None = None):
     """Adaptive MLMC estimate of E[Q] to root-mean-square error eps.
 
     levels: fine grids (nx, ny, nsteps) of levels 0..L (nx = 2 ny, each
     twice the one before it); level l > 0 pairs grid l with grid l-1.
+    model: the random fields of the three coefficients (None or "closed":
+    the closed forms; "two_layer": the two-layer porosity model).
     Returns a dict: EQ (sum of the level means), var_est (sum V_l / m_l),
     m, V, s (seconds per sample at each level, fine and coarse solve), the
     level means, alpha, beta, the bias estimate, mse_ok (var_est <= eps^2/2
@@ -89,7 +93,7 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
         xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        out = solve(ctx, sol, xi=xi_d, opts=opts)
+        out = solve(ctx, sol, xi=xi_d, opts=opts, model=model)
         torch.cuda.synchronize(dev)
         s.append((time.perf_counter() - t0) / m_pilot)
         pilot.append((sol, out, rng[l]))
@@ -100,23 +104,42 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
     if max_samples is not None:
         m = np.minimum(m, max_samples)
     # ---- final batch: every level's samples at once
+    res = mlmc_fixed(ctx, levels, m, seed=seed, opts=opts, model=model)
+    half = eps * eps / 2
+    res.update(V_pilot=V, s=np.array(s), planned_cost=cost,
+               mse_ok=bool(res["var_est"] <= half * (1 + 1e-12) and (L < 2 or res["bias"] ** 2 <= half)))
+    return res
+
+
+def mlmc_fixed(ctx: Context, levels, m, seed: int = 0, opts: Opts | None = None, model: str | None = None):
+    """MLMC estimate with given sample counts m[l] (eq:A): every level's
+    pairs solved in one batch, then the level statistics.  Returns a dict:
+    EQ, var_est (sum V_l / m_l), m, V, the level means, alpha, beta and the
+    bias estimate (nan below three levels), the batch's seconds,
+    nonconverged, E[c] on the finest grid and the level mean and variance
+    fields of Y_l = c_l - c_{l-1} (device tensors)."""
+    import torch
+    levels = [tuple(int(v) for v in g) for g in levels]
+    L = len(levels) - 1
+    m = np.asarray(m, dtype=np.int64)
+    if len(m) != L + 1 or (m < 2).any():
+        raise ValueError("one sample count of at least two per level")
+    dev = torch.device("cuda", ctx.device)
     sol, xi, rng = _pairs(levels, m, seed)
     xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    out = solve(ctx, sol, xi=xi_d, opts=opts)
+    out = solve(ctx, sol, xi=xi_d, opts=opts, model=model)
     torch.cuda.synchronize(dev)
     seconds = time.perf_counter() - t0
     status = out["status"].cpu().numpy()
-    mean, var, var_est, Ec, mean_Y = _level_statistics(ctx, levels, m, [(sol, out, r) for r in rng])
+    mean, var, var_est, Ec, mean_Y, var_Y = _level_statistics(ctx, levels, m, [(sol, out, r) for r in rng],
+                                                              with_var=True)
     alpha = beta = bias = float("nan")
     if L >= 2:
         alpha, beta, bias = henry_mlmc_rates(mean, var, 1)
-    half = eps * eps / 2
-    return dict(EQ=float(mean.sum()), var_est=var_est, m=m, V=var, V_pilot=V, s=np.array(s), mean=mean,
-                alpha=alpha, beta=beta, bias=bias, planned_cost=cost,
-                mse_ok=bool(var_est <= half * (1 + 1e-12) and (L < 2 or bias * bias <= half)),
-                seconds=seconds, nonconverged=int((status != 0).sum()), Ec=Ec, mean_Y=mean_Y)
+    return dict(EQ=float(mean.sum()), var_est=var_est, m=m, V=var, mean=mean, alpha=alpha, beta=beta, bias=bias,
+                seconds=seconds, nonconverged=int((status != 0).sum()), Ec=Ec, mean_Y=mean_Y, var_Y=var_Y)
 
 
 def point_cell(grid, x: float, y: float) -> int:
@@ -134,7 +157,8 @@ def point_cell(grid, x: float, y: float) -> int:
     return int(v) * nx + int(u)
 
 
-def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts | None = None):
+def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts | None = None,
+            model: str | None = None):
     """Quasi-Monte Carlo estimate of E[Q] and E[c] on one grid (nx, ny,
     nsteps): R = len(shifts) Halton rules of n points each, rule r rotated
     by shifts[r] (values in [0, 1); None: one unshifted rule), all R*n
@@ -155,7 +179,7 @@ def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts 
     sol = [grid] * (R * n)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    out = solve(ctx, sol, xi=xi_d, opts=opts)
+    out = solve(ctx, sol, xi=xi_d, opts=opts, model=model)
     torch.cuda.synchronize(dev)
     seconds = time.perf_counter() - t0
     status = out["status"].cpu().numpy()

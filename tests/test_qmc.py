@@ -1,4 +1,4 @@
-"""Quasi-Monte Carlo points (the reference of the abstract and of Sec. 5,
+"""Quasi-Monte Carlo points (the reference of the abstract and of Sec. 4,
 Fig. 11; the paper's set-up names Halton points).
 
 Pins of the oracle's rule that do not retype it: the stratification of a
