@@ -245,6 +245,58 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
                       double* qoi_out, int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes,
                       void* stream);
 
+/* Batched forward solves that also record a time series of each solve
+ * (Sec. 4: the fresh-water integral eq:integral_fw and c at the points of
+ * eq:12points over time, the inputs of the paper's Figs. 4-7).  Every
+ * argument of henry_solve_batch keeps its meaning; in addition:
+ *   nrec     records per solve, 1 <= nrec <= every solve's nsteps: record k
+ *            (k = 1..nrec) holds the state after step ceil(k nsteps / nrec),
+ *            the first step at or after t = k T / nrec
+ *   npts     0..16 points; points: host [npts][2] (x, y) in the closed
+ *            domain [0,2] x [-1,0]
+ *   c_fresh  threshold of the fresh-water indicator (the paper: 0.012178)
+ *   trace_out device [nsolves][nrec][1 + npts]: per record the fresh-water
+ *            area Q_FW = h^2 #{cells: c <= c_fresh} (m^2; 2 when all of D is
+ *            fresh), then c at each point.  The solution is constant per
+ *            cell; a point on a face between two cells takes the mean of
+ *            both, on a corner of four the mean of the four (the point's
+ *            cell coordinates u = x ny, v = (y + 1) ny decide, in FP64).
+ * A solve that stops early (HENRY_STATUS_NONFINITE or _SYNC) gets NaN in
+ * the records after the step it stopped at.  Errors: those of
+ * henry_solve_batch, and HENRY_EINVAL for nrec, npts, points, c_fresh or
+ * trace_out out of range. */
+int henry_solve_batch_trace(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                            const double* xi, const double* phi, const double* logk, const double* qin,
+                            const double* c0, const henry_opts_t* opts, int32_t nrec, int32_t npts,
+                            const double* points, double c_fresh, double* trace_out, double* c_out, double* p_out,
+                            double* qoi_out, int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes,
+                            void* stream);
+
+/* Sample statistics of nvals quantities over nsamples samples (Sec. 4: the
+ * means, variances and quantiles of Figs. 4 and 6).  x: device
+ * [nsamples][nvals].  Per column v: mean_out[v], the unbiased variance
+ * var_out[v] (0 for one sample), and for each probability probs[k] (host,
+ * nq <= 16 values in [0, 1]) q_out[k][v] = x_(lo) + (h - lo)(x_(lo+1) - x_(lo)),
+ * h = (nsamples - 1) probs[k], lo = floor(h), x_(i) the i-th smallest
+ * (Hyndman and Fan's type 7).  NaN sorts after every number and propagates
+ * into the mean and variance.  1 <= nsamples <= 8192.  Outputs device,
+ * caller-owned.  Deterministic (fixed-order sums, a sort).  Errors:
+ * HENRY_EINVAL. */
+int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, int32_t nq,
+                       const double* probs, double* mean_out, double* var_out, double* q_out, void* stream);
+
+/* First-passage times of sampled series (Sec. 4, Figs. 5 and 7: the first
+ * output time at which Q_FW falls below a level, or c at a point crosses
+ * one).  trace: device [nsamples][nrec][stride] (as henry_solve_batch_trace
+ * writes it); for each sample s, t_out[s] (device) = the first record
+ * k = 1..nrec whose value in column col is < threshold (below != 0) or
+ * > threshold (below == 0), or 0 if no record is; hist_out (device
+ * [nrec + 1], or NULL) = the number of samples with each value of t_out.
+ * Errors: HENRY_EINVAL. */
+int henry_first_passage(henry_ctx* ctx, int32_t nsamples, int32_t nrec, int32_t stride, int32_t col,
+                        const double* trace, double threshold, int32_t below, int32_t* t_out, int32_t* hist_out,
+                        void* stream);
+
 /* Tuning cache of a context: threads per solve-workgroup for grids of
  * width nx at precision prec, used by henry_solve_batch and
  * henry_adjoint_batch when opts->threads == 0.  threads = 0 clears the

@@ -283,6 +283,66 @@ def adjoint_xi(phys, nx, ny, nsteps, xi, model=None):
     return Q, g, gK * K
 
 
+# ---------------------------------------------------------------- time series (Sec. 4)
+FRESH = 0.012178  # c threshold of the fresh-water indicator in eq:integral_fw
+
+
+def fresh_area(c, c_fresh=FRESH):
+    """eq:integral_fw on the cell grid: the area of the cells with
+    c <= c_fresh (cells of area h^2 = 1/ny^2)."""
+    ny = c.shape[0]
+    return np.count_nonzero(c <= c_fresh) / ny ** 2
+
+
+def point_value(c, x, y):
+    """c [ny][nx] at the point (x, y): the mean over every cell whose closed
+    square holds the point (one cell inside, two on a face, four at a
+    corner), found by testing each cell, in the cell coordinates
+    u = x ny, v = (y + 1) ny."""
+    ny, nx = c.shape
+    u, v = x * ny, (y + 1.0) * ny
+    vals = [c[j, i] for j in range(ny) for i in range(nx) if i <= u <= i + 1 and j <= v <= j + 1]
+    return float(np.mean(vals))
+
+
+def record_steps(nsteps, nrec):
+    """Steps after which records k = 1..nrec are taken: the first step at or
+    after t = k T / nrec, i.e. ceil(k nsteps / nrec)."""
+    return [-(-k * nsteps // nrec) for k in range(1, nrec + 1)]
+
+
+def trace(phys, nsteps, phi, K, q, nrec, points, c_fresh=FRESH):
+    """Time series of one solve: [nrec][1 + len(points)], each record the
+    fresh-water area and c at the points, and the solve's result dict."""
+    out = solve(phys, nsteps, phi, K, q, trajectory=True)
+    rec = []
+    for st in record_steps(nsteps, nrec):
+        c = out["c_traj"][st]
+        rec.append([fresh_area(c, c_fresh)] + [point_value(c, x, y) for x, y in points])
+    return np.array(rec), out
+
+
+def quantile7(x, p):
+    """Quantile of Hyndman and Fan's type 7: with the sample sorted
+    ascending, x_(lo) + (h - lo)(x_(lo+1) - x_(lo)) at h = (n - 1) p,
+    lo = floor(h)."""
+    xs = np.sort(np.asarray(x, dtype=np.float64))
+    n = len(xs)
+    h = (n - 1) * p
+    lo = int(np.floor(h))
+    hi = min(lo + 1, n - 1)
+    return xs[lo] + (h - lo) * (xs[hi] - xs[lo])
+
+
+def first_passage(series, threshold, below=True):
+    """First record k = 1.. of the series below (or above) the threshold;
+    0 if none (the first-passage times of Figs. 5 and 7)."""
+    for k, a in enumerate(series):
+        if (a < threshold) if below else (a > threshold):
+            return k + 1
+    return 0
+
+
 # ---------------------------------------------------------------- MLMC statistics (Sec. 3)
 def inject(c_coarse, factor):
     """Piecewise-constant injection of a cell field to a grid `factor` times

@@ -28,7 +28,8 @@ EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opt
            "henry_workspace_bytes", "henry_solve_batch", "henry_profile_last", "henry_tune_set", "henry_tune_get",
            "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
            "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch", "henry_mlmc_allocate",
-           "henry_mlmc_rates", "henry_qmc_points")
+           "henry_mlmc_rates", "henry_qmc_points", "henry_solve_batch_trace", "henry_sample_stats",
+           "henry_first_passage")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -104,6 +105,11 @@ def lib():
     L.henry_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), ct.POINTER(ct.c_size_t)]
     L.henry_solve_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), vp, vp,
                                     vp, vp, vp, vp, ct.c_size_t, vp]
+    L.henry_solve_batch_trace.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), i32,
+                                          i32, ct.POINTER(ct.c_double), dbl, vp, vp, vp, vp, vp, vp, vp, ct.c_size_t,
+                                          vp]
+    L.henry_sample_stats.argtypes = [vp, i32, i32, vp, i32, ct.POINTER(ct.c_double), vp, vp, vp, vp]
+    L.henry_first_passage.argtypes = [vp, i32, i32, i32, i32, vp, dbl, i32, vp, vp, vp]
     L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
     L.henry_mlmc_allocate.argtypes = [i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), dbl,
                                       ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
@@ -254,6 +260,53 @@ def henry_solve_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None,
     _chk(rc, "henry_solve_batch")
 
 
+def henry_solve_batch_trace(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, c0=None,
+                            opts: Opts | None = None, nrec=1, points=(), c_fresh=0.012178, trace_out=None, c_out=None,
+                            p_out=None, qoi_out=None, status=None, iters=None, workspace=None, stream=None):
+    """Thin wrapper: tensors are device tensors owned by the caller; points
+    is a host sequence of (x, y)."""
+    import numpy as np
+    g = grids(solves)
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 2))
+    rc = lib().henry_solve_batch_trace(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk),
+                                       _ptr(qin), _ptr(c0), ct.byref(opts) if opts else None, int(nrec), len(pts),
+                                       pts.ctypes.data_as(ct.POINTER(ct.c_double)), float(c_fresh), _ptr(trace_out),
+                                       _ptr(c_out), _ptr(p_out), _ptr(qoi_out), _ptr(status), _ptr(iters),
+                                       _ptr(workspace),
+                                       workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                       _stream_of(stream))
+    _chk(rc, "henry_solve_batch_trace")
+
+
+def henry_sample_stats(ctx: Context, x, probs=(), stream=None):
+    """Mean, unbiased variance and type-7 quantiles of each column of the
+    device tensor x [nsamples][nvals]; returns device tensors (mean [nvals],
+    var [nvals], q [len(probs)][nvals])."""
+    import numpy as np
+    import torch
+    ns, nv = int(x.shape[0]), int(x.shape[1]) if x.dim() > 1 else 1
+    f64 = dict(dtype=torch.float64, device=x.device)
+    mean, var = torch.empty(nv, **f64), torch.empty(nv, **f64)
+    pr = np.ascontiguousarray(probs, dtype=np.float64)
+    q = torch.empty((len(pr), nv), **f64)
+    _chk(lib().henry_sample_stats(ctx.handle, ns, nv, _ptr(x), len(pr), pr.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                  _ptr(mean), _ptr(var), _ptr(q), _stream_of(stream)), "henry_sample_stats")
+    return mean, var, q
+
+
+def henry_first_passage(ctx: Context, trace, col, threshold, below=True, stream=None):
+    """First record per sample at which column col of trace [nsamples][nrec]
+    [stride] falls below (below=True) or rises above threshold, 0 if none,
+    and the histogram of those record numbers [nrec + 1]; device tensors."""
+    import torch
+    ns, nrec, stride = (int(v) for v in trace.shape)
+    t = torch.empty(ns, dtype=torch.int32, device=trace.device)
+    hist = torch.empty(nrec + 1, dtype=torch.int32, device=trace.device)
+    _chk(lib().henry_first_passage(ctx.handle, ns, nrec, stride, int(col), _ptr(trace), float(threshold),
+                                   1 if below else 0, _ptr(t), _ptr(hist), _stream_of(stream)), "henry_first_passage")
+    return t, hist
+
+
 def henry_residual_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, p=None, c=None,
                          cn=None, rp_out=None, rc_out=None, workspace=None, stream=None):
     """Thin wrapper: tensors are device tensors owned by the caller."""
@@ -345,12 +398,14 @@ def _field_of(xi, model=None):
 
 
 def solve(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, c0=None, opts: Opts | None = None,
-          want_p=False, stream=None, model=None):
+          want_p=False, stream=None, model=None, trace=None):
     """Allocate outputs/workspace with torch and run one batch.
     solves: list of (nx, ny, nsteps).  xi [n][3] selects the closed-form
     fields (model="two_layer": the two-layer porosity model), xi [n][41]
     the KL fields (Context.set_kl for every grid), no xi the explicit
-    fields.  Returns dict of device tensors."""
+    fields.  trace=(nrec, points[, c_fresh]) also records each solve's time
+    series (out["trace"], [n][nrec][1 + len(points)]).  Returns dict of
+    device tensors."""
     import torch
     dev = torch.device("cuda", ctx.device)
     opts = opts or opts_default()
@@ -366,9 +421,18 @@ def solve(ctx: Context, solves, xi=None, phi=None, logk=None, qin=None, c0=None,
                iters=torch.empty(len(solves), dtype=torch.int32, device=dev))
     out["p"] = torch.empty(cells, dtype=torch.float64, device=dev) if want_p else None
     field = _field_of(xi, model)
-    henry_solve_batch(ctx, solves, field, xi=xi, phi=phi, logk=logk, qin=qin, c0=c0, opts=opts, c_out=out["c"],
-                      p_out=out["p"], qoi_out=out["qoi"], status=out["status"], iters=out["iters"], workspace=ws,
-                      stream=stream)
+    if trace is None:
+        henry_solve_batch(ctx, solves, field, xi=xi, phi=phi, logk=logk, qin=qin, c0=c0, opts=opts, c_out=out["c"],
+                          p_out=out["p"], qoi_out=out["qoi"], status=out["status"], iters=out["iters"],
+                          workspace=ws, stream=stream)
+    else:
+        nrec, points = int(trace[0]), list(trace[1])
+        c_fresh = float(trace[2]) if len(trace) > 2 else 0.012178
+        out["trace"] = torch.empty((len(solves), nrec, 1 + len(points)), dtype=torch.float64, device=dev)
+        henry_solve_batch_trace(ctx, solves, field, xi=xi, phi=phi, logk=logk, qin=qin, c0=c0, opts=opts,
+                                nrec=nrec, points=points, c_fresh=c_fresh, trace_out=out["trace"], c_out=out["c"],
+                                p_out=out["p"], qoi_out=out["qoi"], status=out["status"], iters=out["iters"],
+                                workspace=ws, stream=stream)
     out["workspace"] = ws
     return out
 

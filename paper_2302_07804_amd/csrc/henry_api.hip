@@ -19,6 +19,7 @@
 
 #include "henry.h"
 #include "henry_adjoint.hpp"
+#include "henry_stats.hpp"
 #include "henry_device.hpp"
 #include "henry_kl.hpp"
 #include "henry_mlmc.hpp"
@@ -458,10 +459,59 @@ int henry_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t ns
     return HENRY_OK;
 }
 
+namespace {
+
+// Time-series request of a forward batch (none: nrec == 0).
+struct TraceArgs {
+    int32_t nrec = 0, npts = 0;
+    const double* pts = nullptr;  // host (x, y) pairs
+    double fresh = 0.0;
+    double* out = nullptr;        // device
+};
+
+int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field, const double* xi,
+                     const double* phi, const double* logk, const double* qin, const double* c0,
+                     const henry_opts_t* opts, const TraceArgs& tr, double* c_out, double* p_out, double* qoi_out,
+                     int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes, void* stream);
+
+}  // namespace
+
 int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field, const double* xi,
                       const double* phi, const double* logk, const double* qin, const double* c0,
                       const henry_opts_t* opts, double* c_out, double* p_out, double* qoi_out, int32_t* status,
                       int32_t* iters, void* workspace, size_t ws_bytes, void* stream) {
+    return solve_batch_impl(ctx, solves, nsolves, field, xi, phi, logk, qin, c0, opts, TraceArgs{}, c_out, p_out,
+                            qoi_out, status, iters, workspace, ws_bytes, stream);
+}
+
+int henry_solve_batch_trace(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                            const double* xi, const double* phi, const double* logk, const double* qin,
+                            const double* c0, const henry_opts_t* opts, int32_t nrec, int32_t npts,
+                            const double* points, double c_fresh, double* trace_out, double* c_out, double* p_out,
+                            double* qoi_out, int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes,
+                            void* stream) {
+    if (nrec < 1 || npts < 0 || npts > henry::kMaxTracePoints || (npts > 0 && !points) || !trace_out ||
+        !std::isfinite(c_fresh))
+        return HENRY_EINVAL;
+    for (int k = 0; k < npts; ++k) {
+        const double x = points[2 * k], y = points[2 * k + 1];
+        if (!(x >= 0.0 && x <= 2.0 && y >= -1.0 && y <= 0.0)) return HENRY_EINVAL;
+    }
+    if (solves)
+        for (int k = 0; k < nsolves; ++k)
+            if (solves[k].nsteps < nrec) return HENRY_EINVAL;
+    TraceArgs tr;
+    tr.nrec = nrec; tr.npts = npts; tr.pts = points; tr.fresh = c_fresh; tr.out = trace_out;
+    return solve_batch_impl(ctx, solves, nsolves, field, xi, phi, logk, qin, c0, opts, tr, c_out, p_out, qoi_out,
+                            status, iters, workspace, ws_bytes, stream);
+}
+
+namespace {
+
+int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field, const double* xi,
+                     const double* phi, const double* logk, const double* qin, const double* c0,
+                     const henry_opts_t* opts, const TraceArgs& tr, double* c_out, double* p_out, double* qoi_out,
+                     int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes, void* stream) {
     if (!ctx || nsolves < 0) return HENRY_EINVAL;
     if (nsolves == 0) return HENRY_OK;
     if (!solves) return HENRY_EINVAL;
@@ -553,6 +603,13 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     lp.max_outer = o->max_outer;
     lp.field_kind = field_kind_of(field);
     lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
+    if (tr.nrec > 0) {
+        lp.trace = tr.out;
+        lp.trace_nrec = tr.nrec;
+        lp.trace_npts = tr.npts;
+        lp.trace_fresh = tr.fresh;
+        for (int k = 0; k < 2 * tr.npts; ++k) lp.trace_pts[k] = tr.pts[k];
+    }
 
     const int ng = (int)order.size();
     const bool serial = o->serial_groups != 0;
@@ -590,6 +647,20 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     for (int64_t v : {(int64_t)o->prec, (int64_t)o->max_outer, tolbits, (int64_t)o->threads, (int64_t)spl,
                       (int64_t)o->serial_groups, (int64_t)field, (int64_t)o->cluster, (int64_t)o->cluster_wait_us})
         key.words.push_back(v);
+    // the time-series request is part of the captured kernel arguments
+    key.words.push_back((int64_t)(uintptr_t)tr.out);
+    key.words.push_back(tr.nrec);
+    key.words.push_back(tr.npts);
+    for (int k = 0; k < 2 * tr.npts; ++k) {
+        int64_t b;
+        std::memcpy(&b, &tr.pts[k], 8);
+        key.words.push_back(b);
+    }
+    {
+        int64_t b;
+        std::memcpy(&b, &tr.fresh, 8);
+        key.words.push_back(b);
+    }
     hipStream_t cs = ctx->cap_stream;
     if (hipEventRecord(ctx->cap_in, s0) != hipSuccess) return HENRY_EHIP;
     if (hipStreamWaitEvent(cs, ctx->cap_in, 0) != hipSuccess) return HENRY_EHIP;
@@ -624,6 +695,8 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
     if (hipStreamWaitEvent(s0, ctx->cap_out, 0) != hipSuccess) return HENRY_EHIP;
     return HENRY_OK;
 }
+
+}  // namespace
 
 int henry_residual_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
                          const double* xi, const double* phi, const double* logk, const double* qin,
@@ -944,6 +1017,47 @@ int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, con
     }
     hipLaunchKernelGGL(henry::mlmc_combine_kernel, dim3(1), dim3(1024), 0, s0, lp, L, fine[L].nx, fine[L].ny,
                        qstats, Ec_finest, var_est);
+    if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    return HENRY_OK;
+}
+
+int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, int32_t nq,
+                       const double* probs, double* mean_out, double* var_out, double* q_out, void* stream) {
+    if (!ctx || nsamples < 1 || nsamples > henry::kMaxStatSamples || nvals < 0 || nq < 0 ||
+        nq > henry::kMaxQuantiles || (nq > 0 && (!probs || !q_out)) || !x || !mean_out || !var_out)
+        return HENRY_EINVAL;
+    henry::Probs pr{};
+    pr.n = nq;
+    for (int k = 0; k < nq; ++k) {
+        if (!(probs[k] >= 0.0 && probs[k] <= 1.0)) return HENRY_EINVAL;
+        pr.p[k] = probs[k];
+    }
+    if (nvals == 0) return HENRY_OK;
+    int P = 1;
+    while (P < nsamples) P <<= 1;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(henry::sample_stats_kernel, dim3(nvals), dim3(256), (size_t)P * sizeof(double), s0, x,
+                       nsamples, nvals, P, pr, mean_out, var_out, q_out);
+    if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    return HENRY_OK;
+}
+
+int henry_first_passage(henry_ctx* ctx, int32_t nsamples, int32_t nrec, int32_t stride, int32_t col,
+                        const double* trace, double threshold, int32_t below, int32_t* t_out, int32_t* hist_out,
+                        void* stream) {
+    if (!ctx || nsamples < 0 || nrec < 1 || stride < 1 || col < 0 || col >= stride || !trace || !t_out ||
+        !std::isfinite(threshold))
+        return HENRY_EINVAL;
+    if (nsamples == 0 && !hist_out) return HENRY_OK;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    if (nsamples > 0)
+        hipLaunchKernelGGL(henry::first_passage_kernel, dim3((nsamples + 255) / 256), dim3(256), 0, s0, trace,
+                           nsamples, nrec, stride, col, threshold, below, t_out);
+    if (hist_out)
+        hipLaunchKernelGGL(henry::passage_hist_kernel, dim3((nrec + 64) / 64), dim3(64), 0, s0, t_out, nsamples,
+                           nrec, hist_out);
     if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
     return HENRY_OK;
 }

@@ -87,7 +87,17 @@ struct Launch {
     int32_t nsolves;         // solves of this launch (descs[0 .. nsolves-1])
     int32_t cluster;         // workgroups per solve (1, 2, 4 or 8)
     uint64_t cluster_wait;   // bound of one cluster-barrier wait, ticks of the 100 MHz wall clock
+    // time series (forward solves only; trace == nullptr: none): record k =
+    // 1..trace_nrec after step ceil(k nsteps / trace_nrec), holding the
+    // fresh-water area and c at trace_npts points, at
+    // trace[index][k-1][0 .. trace_npts]
+    double* trace;
+    int32_t trace_nrec, trace_npts;
+    double trace_fresh;             // c threshold of the fresh-water indicator
+    double trace_pts[2 * 16];       // (x, y) of each point
 };
+
+constexpr int kMaxTracePoints = 16;
 
 // ------------------------------------------------------------------ layout
 __host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
@@ -1498,6 +1508,36 @@ __device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
     return block_sum(part, red) * S.h * S.h;
 }
 
+// ------------------------------------------------------------------ time series
+// Value of the piecewise-constant solution at (x, y): the cell that holds
+// the point; on a face between two cells the mean of both, at a corner of
+// four the mean of the four (the mean of the one-sided limits).
+__device__ inline double point_value(const double* c, int nx, int ny, double x, double y) {
+    const double u = x * ny, v = (y + 1.0) * ny;
+    int i0 = (int)floor(u), j0 = (int)floor(v);
+    int i1 = i0, j1 = j0;
+    if (u == (double)i0) i0 -= 1;  // a vertical face: the cells on both sides
+    if (v == (double)j0) j0 -= 1;
+    i0 = min(max(i0, 0), nx - 1); i1 = min(max(i1, 0), nx - 1);
+    j0 = min(max(j0, 0), ny - 1); j1 = min(max(j1, 0), ny - 1);
+    return 0.25 * ((c[j0 * nx + i0] + c[j0 * nx + i1]) + (c[j1 * nx + i0] + c[j1 * nx + i1]));
+}
+
+// One record of a solve's time series (eq:integral_fw, eq:12points), by the
+// whole workgroup of the leader: the fresh-water area h^2 #{c <= c_fresh}
+// (an integer count, so the sum is exact in any order) and c at the points.
+template <typename T>
+__device__ void record_trace(const Launch& lp, Solve<T>& S, int index, int k, double* red) {
+    double* out = lp.trace + ((int64_t)index * lp.trace_nrec + (k - 1)) * (1 + lp.trace_npts);
+    double cnt = 0.0;
+    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) cnt += S.c[idx] <= lp.trace_fresh ? 1.0 : 0.0;
+    cnt = block_sum(cnt, red);
+    if (threadIdx.x == 0) out[0] = cnt * S.h * S.h;
+    if (threadIdx.x < lp.trace_npts)
+        out[1 + threadIdx.x] =
+            point_value(S.c, S.nx, S.ny, lp.trace_pts[2 * threadIdx.x], lp.trace_pts[2 * threadIdx.x + 1]);
+}
+
 // ------------------------------------------------------------------ the solve kernel
 // Cluster levels of a solve shared by K workgroups: level 0, then every
 // level of >= 2048 K cells (>= 2048 per member) whose coarser neighbour is
@@ -1568,7 +1608,9 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
     ClusterTeam::sync();
     PhaseClock pc;
     pc.init();
-    for (int s = s_begin; s < s_end && status != 2 && !g_cl.failed; ++s) {
+    const int64_t N = d.nsteps, nrec = lp.trace ? lp.trace_nrec : 0;
+    int s = s_begin;
+    for (; s < s_end && status != 2 && !g_cl.failed; ++s) {
         // extrapolate only through converged states: a step that stopped at
         // max_outer restarts the history
         const int order = good - 1 < 3 ? (good - 1 > 0 ? good - 1 : 0) : 3;
@@ -1576,10 +1618,28 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
         if (st == 2) status = 2;
         else if (st == 1 && status == 0) status = 1;
         good = st == 0 ? (good < 4 ? good + 1 : 4) : 0;
+        if (nrec && st != 2) {
+            // the record whose step is s + 1, if any (nrec <= N: at most one)
+            const int64_t k = (int64_t)(s + 1) * nrec / N;
+            if (k >= 1 && (k * N + nrec - 1) / nrec == s + 1) {
+                if (member == 0) record_trace(lp, S, d.index, (int)k, red);
+                ClusterTeam::sync();  // the others keep c until the leader has read it
+            }
+        }
     }
     ClusterTeam::sync();
     if (g_cl.failed) status = 3;
     if (member != 0) return;
+    if (nrec && (status == 2 || status == 3)) {
+        // NaN in the records of step s (the step the solve stopped in, or
+        // the first step of this launch) and later: the first such record is
+        // k0 = floor((s - 1) nrec / N) + 1
+        const int rw = 1 + lp.trace_npts;
+        const int64_t k0 = s > 0 ? (int64_t)(s - 1) * nrec / N + 1 : 1;
+        for (int64_t k = k0; k <= nrec; ++k)
+            for (int v = threadIdx.x; v < rw; v += blockDim.x)
+                lp.trace[((int64_t)d.index * nrec + (k - 1)) * rw + v] = __builtin_nan("");
+    }
     if (threadIdx.x == 0) {
         sp[3] = (double)good;
         sp[1] = (double)status;
