@@ -516,6 +516,30 @@ def main():
                             V_Q=[float(v) for v in pr["V"]], alpha=pr["alpha"], beta=pr["beta"]))
         log(f"paper set-up, Table 3 counts (eps^2 = 1e-7): {pr['seconds']:.1f} s, {pr['nonconverged']} "
             f"non-converged, c(1.60,-0.95) by level {tel}, V at the point {vpt}")
+        # Figs. 4-7: 600 QMC realisations of the time series on the coarsest grid
+        from paper_2302_07804_amd.mlmc import POINTS12, QUANTILES
+        g0 = hi.paper_level_grid(0)
+        nrec = 47  # records every 4 steps of 188: t = 128 s .. T
+        pas = ((0, 1.2, True), (0, 1.7, True), (4, 0.9, False))
+        sr = hm.series_run(pctx, g0, hm.henry_qmc_points(1, 600, 3), nrec, passages=pas, opts=popts, model="two_layer")
+        q = sr["q"].cpu().numpy()
+        mean = sr["mean"].cpu().numpy()
+        fp = {}
+        for (col, thr, below), (t, hist) in zip(pas, sr["passage"]):
+            hh = hist.cpu().numpy()
+            k = np.arange(len(hh))
+            fp[f"{'Q_FW' if col == 0 else 'c(1.85,-0.95)'} {'<' if below else '>'} {thr}"] = dict(
+                mean_record=float((k[1:] * hh[1:]).sum() / max(hh[1:].sum(), 1)), never=int(hh[0]),
+                hist=[int(v) for v in hh])
+        extras["paper_setup"]["series_600"] = dict(
+            workload="600 Halton samples, 32x16/188, 47 records (every 4 steps, 128 s apart), Q_FW and c at the "
+                     "12 points", seconds=sr["seconds"], nonconverged=sr["nonconverged"],
+            Q_FW_mean=[float(v) for v in mean[:, 0]],
+            Q_FW_quantiles={str(p): [float(v) for v in q[k, :, 0]] for k, p in enumerate(QUANTILES)},
+            c_1p85_m0p95_quantiles_at_T={str(p): float(q[k, -1, 4]) for k, p in enumerate(QUANTILES)},
+            first_passage=fp)
+        log(f"paper set-up, 600-sample series: {sr['seconds']:.2f} s, first passage (records of 128 s): "
+            f"{ {k: round(v['mean_record'], 2) for k, v in fp.items()} }")
         pctx.close()
 
     res = {

@@ -654,3 +654,9 @@ def mlmc_fixed(*args, **kwargs):
     """MLMC estimate with given sample counts (see paper_2302_07804_amd.mlmc.mlmc_fixed)."""
     from .mlmc import mlmc_fixed as run
     return run(*args, **kwargs)
+
+
+def series_run(*args, **kwargs):
+    """Time-series statistics of an ensemble (see paper_2302_07804_amd.mlmc.series_run)."""
+    from .mlmc import series_run as run
+    return run(*args, **kwargs)

@@ -19,8 +19,8 @@ import time
 
 import numpy as np
 
-from . import (FIELD_CLOSED3, Context, Opts, henry_mlmc_allocate, henry_mlmc_rates, henry_qmc_points,
-               henry_sample_xi, mlmc_level_estimate, solve)
+from . import (FIELD_CLOSED3, Context, Opts, henry_first_passage, henry_mlmc_allocate, henry_mlmc_rates,
+               henry_qmc_points, henry_sample_stats, henry_sample_xi, mlmc_level_estimate, solve)
 
 
 def _pairs(levels, m, seed):
@@ -205,3 +205,40 @@ def telescoped_at(levels, mean_Y, x: float, y: float) -> np.ndarray:
     field on grid l, as mlmc_run returns it."""
     vals = [float(mean_Y[l][point_cell(levels[l], x, y)].item()) for l in range(len(levels))]
     return np.cumsum(vals)
+
+
+# the paper's output points (eq:12points) and quantiles (Figs. 4 and 6)
+POINTS12 = ((1.10, -0.95), (1.35, -0.95), (1.60, -0.95), (1.85, -0.95), (1.10, -0.75), (1.35, -0.75),
+            (1.60, -0.75), (1.85, -0.75), (1.10, -0.50), (1.35, -0.50), (1.60, -0.50), (1.85, -0.50))
+QUANTILES = (0.025, 0.25, 0.5, 0.75, 0.975)
+
+
+def series_run(ctx: Context, grid, xi, nrec: int, points=POINTS12, probs=QUANTILES, passages=(),
+               c_fresh: float = 0.012178, opts: Opts | None = None, model: str | None = None):
+    """Time-series statistics of an ensemble on one grid (Sec. 4, Figs. 4-7):
+    every sample xi[k] solved with nrec records of the fresh-water area and
+    c at the points, then per record and quantity the mean, variance and
+    quantiles over the samples, and for each (col, threshold, below) in
+    passages the first-passage record of every sample and their histogram
+    (col 0 is the fresh-water area, col 1 + i point i).  Returns a dict of
+    device tensors (trace [n][nrec][1 + npts], mean and var [nrec][1 + npts],
+    q [len(probs)][nrec][1 + npts], passage list of (t, hist)), the batch's
+    seconds and the number of solves that did not converge."""
+    import torch
+    grid = tuple(int(v) for v in grid)
+    dev = torch.device("cuda", ctx.device)
+    xi_d = torch.as_tensor(np.ascontiguousarray(xi, dtype=np.float64), device=dev)
+    n = int(xi_d.shape[0])
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    out = solve(ctx, [grid] * n, xi=xi_d, opts=opts, model=model, trace=(nrec, list(points), c_fresh))
+    torch.cuda.synchronize(dev)
+    seconds = time.perf_counter() - t0
+    tr = out["trace"]
+    nv = nrec * (1 + len(points))
+    mean, var, q = henry_sample_stats(ctx, tr.view(n, nv), probs)
+    pas = [henry_first_passage(ctx, tr, col, thr, below) for col, thr, below in passages]
+    torch.cuda.synchronize(dev)
+    shape = (nrec, 1 + len(points))
+    return dict(trace=tr, mean=mean.view(shape), var=var.view(shape), q=q.view((len(probs),) + shape),
+                passage=pas, seconds=seconds, nonconverged=int((out["status"].cpu().numpy() != 0).sum()))

@@ -164,3 +164,30 @@ def test_first_passage_matches_oracle(torch_cuda):
         assert list(t.cpu().numpy()) == want
         assert list(hist.cpu().numpy()) == list(np.bincount(want, minlength=49))
     ctx.close()
+
+
+def test_series_run_statistics(torch_cuda):
+    """The ensemble driver's layout: its mean, variance, quantiles and
+    first-passage histograms are those of its own trace, per record and
+    quantity."""
+    torch = torch_cuda
+    ctx = hm.Context(hi.PHYS_TABLE1, 0)
+    xi = hm.henry_qmc_points(1, 40, 3)
+    pas = ((0, 1.7, True), (4, 0.5, False))
+    res = hm.series_run(ctx, (32, 16, 188), xi, 47, passages=pas, model="two_layer",
+                        opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-9, max_outer=60))
+    torch.cuda.synchronize()
+    ctx.close()
+    assert res["nonconverged"] == 0
+    tr = res["trace"].cpu().numpy()
+    assert tr.shape == (40, 47, 13)
+    np.testing.assert_allclose(res["mean"].cpu().numpy(), tr.mean(axis=0), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(res["var"].cpu().numpy(), tr.var(axis=0, ddof=1), rtol=1e-11, atol=1e-18)
+    q = res["q"].cpu().numpy()
+    for k, p in enumerate((0.025, 0.25, 0.5, 0.75, 0.975)):
+        want = np.array([[oracle.quantile7(tr[:, r, c], p) for c in range(13)] for r in range(47)])
+        np.testing.assert_allclose(q[k], want, rtol=0, atol=1e-15)
+    for (col, thr, below), (t, hist) in zip(pas, res["passage"]):
+        want = [oracle.first_passage(tr[s, :, col], thr, below) for s in range(40)]
+        assert list(t.cpu().numpy()) == want
+        assert list(hist.cpu().numpy()) == list(np.bincount(want, minlength=48))
