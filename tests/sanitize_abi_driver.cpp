@@ -98,6 +98,23 @@ int main() {
     int32_t m[2] = {4, 4};
     EXPECT(mlmc_level_estimate(nullptr, 1, ok.data(), m, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr) == HENRY_EINVAL);
+    // time series and statistics: argument checks (an empty batch with a
+    // placeholder handle passes them and returns before touching it)
+    {
+        henry_ctx* handle = reinterpret_cast<henry_ctx*>(&d);
+        const double pts[4] = {1.6, -0.95, 1.85, -0.95}, far[2] = {2.5, -0.5}, probs[2] = {0.25, 0.75};
+        EXPECT(henry_solve_batch_trace(handle, ok.data(), 0, HENRY_FIELD_CLOSED3, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, &o, 10, 2, pts, 0.012178, &d, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr, 0, nullptr) == HENRY_OK);
+        EXPECT(henry_solve_batch_trace(handle, ok.data(), 0, HENRY_FIELD_CLOSED3, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, &o, 10, 1, far, 0.012178, &d, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr, 0, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_solve_batch_trace(nullptr, ok.data(), 1, HENRY_FIELD_CLOSED3, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, &o, 51, 2, pts, 0.012178, &d, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr, 0, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_sample_stats(handle, 8193, 3, &d, 2, probs, &d, &d, &d, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_first_passage(handle, 10, 5, 3, 3, &d, 0.5, 1, &st, &st, nullptr) == HENRY_EINVAL);
+    }
     int32_t t = 0;
     EXPECT(henry_tune_set(nullptr, 16, HENRY_PREC_MIXED, 128) == HENRY_EINVAL);
     EXPECT(henry_tune_get(nullptr, 16, HENRY_PREC_MIXED, &t) == HENRY_EINVAL);

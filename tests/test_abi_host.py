@@ -136,3 +136,43 @@ def test_kl_entry_points_reject_bad_arguments(L):
     assert L.henry_kl_basis(16, 9, 20, 0.3, 200, dp(lam), dp(modes)) == hm.HENRY_EINVAL
     assert L.henry_ctx_set_kl(None, 16, 8, 0.3, 0.1, 0.5) == hm.HENRY_EINVAL
     assert L.henry_sample_xi_kl(0, 0, 0, -1, dp(lam)) == hm.HENRY_EINVAL
+
+
+def test_time_series_entry_points_reject_bad_arguments(L):
+    """Argument checks of the time-series and statistics calls run before
+    any device work (no GPU needed).  An empty batch returns at once once
+    its arguments pass, so a placeholder context handle (never dereferenced
+    on these paths) tells the checks apart from the missing-context one."""
+    g = hm.grids([(16, 8, 50)])
+    D = ct.POINTER(ct.c_double)
+    pts = (ct.c_double * 4)(1.6, -0.95, 1.85, -0.95)
+    far = (ct.c_double * 2)(2.5, -0.5)
+    tr = ct.c_void_p(8)  # never dereferenced
+    handle = ct.c_void_p(16)
+
+    def trace(ctx=handle, nsolves=0, nrec=10, npts=2, points=pts, fresh=0.012178, out=tr):
+        return L.henry_solve_batch_trace(ctx, g, nsolves, 0, None, None, None, None, None, None, nrec, npts,
+                                         ct.cast(points, D) if points is not None else None, fresh, out, None, None,
+                                         None, None, None, None, 0, None)
+
+    assert trace() == hm.HENRY_OK  # valid request, empty batch
+    assert trace(ctx=None) == hm.HENRY_EINVAL
+    assert trace(nrec=0) == hm.HENRY_EINVAL
+    assert trace(npts=17) == hm.HENRY_EINVAL
+    assert trace(npts=-1) == hm.HENRY_EINVAL
+    assert trace(points=None) == hm.HENRY_EINVAL
+    assert trace(points=far, npts=1) == hm.HENRY_EINVAL
+    assert trace(fresh=float("nan")) == hm.HENRY_EINVAL
+    assert trace(out=None) == hm.HENRY_EINVAL
+    assert trace(ctx=None, nsolves=1, nrec=51) == hm.HENRY_EINVAL  # more records than steps
+    probs = (ct.c_double * 2)(0.25, 0.75)
+    bad = (ct.c_double * 2)(0.25, 1.5)
+    x = ct.c_void_p(8)
+    for args in ((0, 3, x, 2, probs), (8193, 3, x, 2, probs), (10, -1, x, 2, probs), (10, 3, x, 17, probs),
+                 (10, 3, x, 2, bad), (10, 3, None, 2, probs)):
+        assert L.henry_sample_stats(handle, *args, x, x, x, None) == hm.HENRY_EINVAL, args
+    assert L.henry_sample_stats(None, 10, 3, x, 2, probs, x, x, x, None) == hm.HENRY_EINVAL
+    for args in ((-1, 5, 3, 1), (10, 0, 3, 1), (10, 5, 0, 0), (10, 5, 3, 3), (10, 5, 3, -1)):
+        assert L.henry_first_passage(handle, *args, x, 0.5, 1, x, x, None) == hm.HENRY_EINVAL, args
+    assert L.henry_first_passage(handle, 10, 5, 3, 1, x, float("inf"), 1, x, x, None) == hm.HENRY_EINVAL
+    assert L.henry_first_passage(handle, 0, 5, 3, 1, x, 0.5, 1, x, None, None) == hm.HENRY_OK  # nothing to do
