@@ -540,6 +540,19 @@ def main():
             first_passage=fp)
         log(f"paper set-up, 600-sample series: {sr['seconds']:.2f} s, first passage (records of 128 s): "
             f"{ {k: round(v['mean_record'], 2) for k, v in fp.items()} }")
+        # the MLMC estimate of the mean series with Table 3's counts (Figs. 8-10)
+        ms = hm.mlmc_series(pctx, plevels, m3, nrec, seed=hi.SEED, opts=popts, model="two_layer")
+        ip = 1 + POINTS12.index((1.60, -0.95))
+        extras["paper_setup"]["mlmc_series_table3"] = dict(
+            workload="Table 3 counts for eps^2 = 1e-7, levels 32x16/188 .. 1024x512/6016, 47 records",
+            seconds=ms["seconds"], nonconverged=ms["nonconverged"],
+            Q_FW_mean=[float(v) for v in ms["mean"][:, 0]],
+            c_1p60_m0p95_mean=[float(v) for v in ms["mean"][:, ip]],
+            c_1p60_m0p95_level_mean=[[float(v) for v in ms["level_mean"][l, :, ip]] for l in range(6)],
+            c_1p60_m0p95_level_var=[[float(v) for v in ms["level_var"][l, :, ip]] for l in range(6)],
+            Q_FW_level_var=[[float(v) for v in ms["level_var"][l, :, 0]] for l in range(6)])
+        log(f"paper set-up, MLMC series (Table 3 counts): {ms['seconds']:.1f} s, {ms['nonconverged']} non-converged; "
+            f"V_l of c(1.60,-0.95) at record 14: {[float(ms['level_var'][l, 13, ip]) for l in range(6)]}")
         pctx.close()
 
     res = {

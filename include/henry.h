@@ -273,8 +273,11 @@ int henry_solve_batch_trace(henry_ctx* ctx, const henry_grid_t* solves, int32_t 
                             void* stream);
 
 /* Sample statistics of nvals quantities over nsamples samples (Sec. 4: the
- * means, variances and quantiles of Figs. 4 and 6).  x: device
- * [nsamples][nvals].  Per column v: mean_out[v], the unbiased variance
+ * means, variances and quantiles of Figs. 4 and 6; with x_sub the level
+ * differences Y_l of paired samples, Sec. 3 eq:A, for MLMC estimates of
+ * time series).  x: device [nsamples][nvals]; x_sub: device, the same
+ * shape, or NULL; the statistics are of x - x_sub (of x when NULL).
+ * Per column v: mean_out[v], the unbiased variance
  * var_out[v] (0 for one sample), and for each probability probs[k] (host,
  * nq <= 16 values in [0, 1]) q_out[k][v] = x_(lo) + (h - lo)(x_(lo+1) - x_(lo)),
  * h = (nsamples - 1) probs[k], lo = floor(h), x_(i) the i-th smallest
@@ -282,8 +285,9 @@ int henry_solve_batch_trace(henry_ctx* ctx, const henry_grid_t* solves, int32_t 
  * into the mean and variance.  1 <= nsamples <= 8192.  Outputs device,
  * caller-owned.  Deterministic (fixed-order sums, a sort).  Errors:
  * HENRY_EINVAL. */
-int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, int32_t nq,
-                       const double* probs, double* mean_out, double* var_out, double* q_out, void* stream);
+int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, const double* x_sub,
+                       int32_t nq, const double* probs, double* mean_out, double* var_out, double* q_out,
+                       void* stream);
 
 /* First-passage times of sampled series (Sec. 4, Figs. 5 and 7: the first
  * output time at which Q_FW falls below a level, or c at a point crosses

@@ -108,7 +108,7 @@ def lib():
     L.henry_solve_batch_trace.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), i32,
                                           i32, ct.POINTER(ct.c_double), dbl, vp, vp, vp, vp, vp, vp, vp, ct.c_size_t,
                                           vp]
-    L.henry_sample_stats.argtypes = [vp, i32, i32, vp, i32, ct.POINTER(ct.c_double), vp, vp, vp, vp]
+    L.henry_sample_stats.argtypes = [vp, i32, i32, vp, vp, i32, ct.POINTER(ct.c_double), vp, vp, vp, vp]
     L.henry_first_passage.argtypes = [vp, i32, i32, i32, i32, vp, dbl, i32, vp, vp, vp]
     L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
     L.henry_mlmc_allocate.argtypes = [i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), dbl,
@@ -278,10 +278,10 @@ def henry_solve_batch_trace(ctx: Context, solves, field, xi=None, phi=None, logk
     _chk(rc, "henry_solve_batch_trace")
 
 
-def henry_sample_stats(ctx: Context, x, probs=(), stream=None):
+def henry_sample_stats(ctx: Context, x, probs=(), stream=None, x_sub=None):
     """Mean, unbiased variance and type-7 quantiles of each column of the
-    device tensor x [nsamples][nvals]; returns device tensors (mean [nvals],
-    var [nvals], q [len(probs)][nvals])."""
+    device tensor x [nsamples][nvals] (of x - x_sub when x_sub is given);
+    returns device tensors (mean [nvals], var [nvals], q [len(probs)][nvals])."""
     import numpy as np
     import torch
     ns, nv = int(x.shape[0]), int(x.shape[1]) if x.dim() > 1 else 1
@@ -289,8 +289,11 @@ def henry_sample_stats(ctx: Context, x, probs=(), stream=None):
     mean, var = torch.empty(nv, **f64), torch.empty(nv, **f64)
     pr = np.ascontiguousarray(probs, dtype=np.float64)
     q = torch.empty((len(pr), nv), **f64)
-    _chk(lib().henry_sample_stats(ctx.handle, ns, nv, _ptr(x), len(pr), pr.ctypes.data_as(ct.POINTER(ct.c_double)),
-                                  _ptr(mean), _ptr(var), _ptr(q), _stream_of(stream)), "henry_sample_stats")
+    if x_sub is not None and tuple(x_sub.shape) != tuple(x.shape):
+        raise ValueError("x_sub must have the shape of x")
+    _chk(lib().henry_sample_stats(ctx.handle, ns, nv, _ptr(x), _ptr(x_sub), len(pr),
+                                  pr.ctypes.data_as(ct.POINTER(ct.c_double)), _ptr(mean), _ptr(var), _ptr(q),
+                                  _stream_of(stream)), "henry_sample_stats")
     return mean, var, q
 
 
@@ -659,4 +662,10 @@ def mlmc_fixed(*args, **kwargs):
 def series_run(*args, **kwargs):
     """Time-series statistics of an ensemble (see paper_2302_07804_amd.mlmc.series_run)."""
     from .mlmc import series_run as run
+    return run(*args, **kwargs)
+
+
+def mlmc_series(*args, **kwargs):
+    """MLMC estimate of mean time series (see paper_2302_07804_amd.mlmc.mlmc_series)."""
+    from .mlmc import mlmc_series as run
     return run(*args, **kwargs)

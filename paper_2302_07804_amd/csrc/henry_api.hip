@@ -1021,8 +1021,9 @@ int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, con
     return HENRY_OK;
 }
 
-int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, int32_t nq,
-                       const double* probs, double* mean_out, double* var_out, double* q_out, void* stream) {
+int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, const double* x_sub,
+                       int32_t nq, const double* probs, double* mean_out, double* var_out, double* q_out,
+                       void* stream) {
     if (!ctx || nsamples < 1 || nsamples > henry::kMaxStatSamples || nvals < 0 || nq < 0 ||
         nq > henry::kMaxQuantiles || (nq > 0 && (!probs || !q_out)) || !x || !mean_out || !var_out)
         return HENRY_EINVAL;
@@ -1038,7 +1039,7 @@ int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const do
     DeviceGuard dg(ctx->device);
     hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(henry::sample_stats_kernel, dim3(nvals), dim3(256), (size_t)P * sizeof(double), s0, x,
-                       nsamples, nvals, P, pr, mean_out, var_out, q_out);
+                       x_sub, nsamples, nvals, P, pr, mean_out, var_out, q_out);
     if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
     return HENRY_OK;
 }

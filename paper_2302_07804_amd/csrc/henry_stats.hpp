@@ -31,18 +31,24 @@ __device__ inline double block_sum256(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// One 256-thread block per column v of x[nsamples][nvals]: mean, unbiased
+// One 256-thread block per column v of x[nsamples][nvals] (minus x_sub, the
+// same shape, when given: level differences of paired samples): mean, unbiased
 // variance and the quantiles of Hyndman and Fan's type 7 (the linear
 // interpolation between order statistics x_(lo) and x_(lo+1) at
 // h = (n - 1) p).  P (a power of two >= nsamples) doubles of dynamic LDS.
-__global__ void __launch_bounds__(256) sample_stats_kernel(const double* x, int nsamples, int nvals, int P,
-                                                           Probs probs, double* mean, double* var, double* q) {
+__global__ void __launch_bounds__(256) sample_stats_kernel(const double* x, const double* x_sub, int nsamples,
+                                                           int nvals, int P, Probs probs, double* mean, double* var,
+                                                           double* q) {
     extern __shared__ double buf[];
     __shared__ double red[4];
     const int v = blockIdx.x;
     double s = 0.0;
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        const double a = i < nsamples ? x[(size_t)i * nvals + v] : __builtin_nan("");
+        double a = __builtin_nan("");
+        if (i < nsamples) {
+            a = x[(size_t)i * nvals + v];
+            if (x_sub) a -= x_sub[(size_t)i * nvals + v];
+        }
         buf[i] = a;
         if (i < nsamples) s += a;
     }

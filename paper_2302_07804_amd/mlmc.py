@@ -242,3 +242,45 @@ def series_run(ctx: Context, grid, xi, nrec: int, points=POINTS12, probs=QUANTIL
     shape = (nrec, 1 + len(points))
     return dict(trace=tr, mean=mean.view(shape), var=var.view(shape), q=q.view((len(probs),) + shape),
                 passage=pas, seconds=seconds, nonconverged=int((out["status"].cpu().numpy() != 0).sum()))
+
+
+def mlmc_series(ctx: Context, levels, m, nrec: int, points=POINTS12, seed: int = 0, c_fresh: float = 0.012178,
+                opts: Opts | None = None, model: str | None = None):
+    """MLMC estimate of mean time series (Sec. 4: the paper estimates the
+    mean of Q_FW(t) and of c at points by MLMC): the telescoping sum eq:A
+    per record and quantity, level l's differences Y_l = g_l - g_{l-1}
+    taken between the fine and coarse solves of its pairs (keys (seed, l,
+    i)).  Each level's nsteps should be a multiple of nrec so that the
+    records of all levels fall at the same times k T / nrec.  Returns a
+    dict: mean [nrec][1 + npts] (the estimate), var_est (sum_l V_l / m_l,
+    same shape), level_mean and level_var [L+1][nrec][1 + npts], the
+    batch's seconds and the number of non-converged solves."""
+    import torch
+    levels = [tuple(int(v) for v in g) for g in levels]
+    L = len(levels) - 1
+    m = np.asarray(m, dtype=np.int64)
+    if len(m) != L + 1 or (m < 2).any():
+        raise ValueError("one sample count of at least two per level")
+    dev = torch.device("cuda", ctx.device)
+    sol, xi, rng = _pairs(levels, m, seed)
+    xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    out = solve(ctx, sol, xi=xi_d, opts=opts, model=model, trace=(nrec, list(points), c_fresh))
+    torch.cuda.synchronize(dev)
+    seconds = time.perf_counter() - t0
+    tr = out["trace"]
+    nv = nrec * (1 + len(points))
+    lm, lv = [], []
+    for l, (f0, c0, c1) in enumerate(rng):
+        fine = tr[f0:c0].reshape(c0 - f0, nv)
+        coarse = tr[c0:c1].reshape(c1 - c0, nv) if l > 0 else None
+        mean, var, _ = henry_sample_stats(ctx, fine, (), x_sub=coarse)
+        lm.append(mean)
+        lv.append(var)
+    torch.cuda.synchronize(dev)
+    shape = (nrec, 1 + len(points))
+    lm = np.stack([v.cpu().numpy().reshape(shape) for v in lm])
+    lv = np.stack([v.cpu().numpy().reshape(shape) for v in lv])
+    return dict(mean=lm.sum(axis=0), var_est=(lv / m[:, None, None]).sum(axis=0), level_mean=lm, level_var=lv,
+                m=m, seconds=seconds, nonconverged=int((out["status"].cpu().numpy() != 0).sum()))

@@ -112,7 +112,7 @@ int main() {
         EXPECT(henry_solve_batch_trace(nullptr, ok.data(), 1, HENRY_FIELD_CLOSED3, nullptr, nullptr, nullptr, nullptr,
                                        nullptr, &o, 51, 2, pts, 0.012178, &d, nullptr, nullptr, nullptr, nullptr,
                                        nullptr, nullptr, 0, nullptr) == HENRY_EINVAL);
-        EXPECT(henry_sample_stats(handle, 8193, 3, &d, 2, probs, &d, &d, &d, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_sample_stats(handle, 8193, 3, &d, nullptr, 2, probs, &d, &d, &d, nullptr) == HENRY_EINVAL);
         EXPECT(henry_first_passage(handle, 10, 5, 3, 3, &d, 0.5, 1, &st, &st, nullptr) == HENRY_EINVAL);
     }
     int32_t t = 0;

@@ -170,8 +170,8 @@ def test_time_series_entry_points_reject_bad_arguments(L):
     x = ct.c_void_p(8)
     for args in ((0, 3, x, 2, probs), (8193, 3, x, 2, probs), (10, -1, x, 2, probs), (10, 3, x, 17, probs),
                  (10, 3, x, 2, bad), (10, 3, None, 2, probs)):
-        assert L.henry_sample_stats(handle, *args, x, x, x, None) == hm.HENRY_EINVAL, args
-    assert L.henry_sample_stats(None, 10, 3, x, 2, probs, x, x, x, None) == hm.HENRY_EINVAL
+        assert L.henry_sample_stats(handle, *args[:3], None, *args[3:], x, x, x, None) == hm.HENRY_EINVAL, args
+    assert L.henry_sample_stats(None, 10, 3, x, None, 2, probs, x, x, x, None) == hm.HENRY_EINVAL
     for args in ((-1, 5, 3, 1), (10, 0, 3, 1), (10, 5, 0, 0), (10, 5, 3, 3), (10, 5, 3, -1)):
         assert L.henry_first_passage(handle, *args, x, 0.5, 1, x, x, None) == hm.HENRY_EINVAL, args
     assert L.henry_first_passage(handle, 10, 5, 3, 1, x, float("inf"), 1, x, x, None) == hm.HENRY_EINVAL

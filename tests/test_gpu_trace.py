@@ -191,3 +191,44 @@ def test_series_run_statistics(torch_cuda):
         want = [oracle.first_passage(tr[s, :, col], thr, below) for s in range(40)]
         assert list(t.cpu().numpy()) == want
         assert list(hist.cpu().numpy()) == list(np.bincount(want, minlength=48))
+
+
+def test_mlmc_series_matches_oracle(torch_cuda):
+    """MLMC of the time series on two levels (16x8/50 and 32x16/100, 10
+    records at the same times on both): every level's mean and variance of
+    Y_l per record and quantity, the telescoped mean and the estimator
+    variance equal the oracle's statistics of oracle traces of the same
+    samples (FP64 path at tol 1e-10: 1e-8)."""
+    torch = torch_cuda
+    levels = [(16, 8, 50), (32, 16, 100)]
+    m, seed, nrec = [6, 4], 3, 10
+    ctx = hm.Context(hi.PHYS, 0)
+    res = hm.mlmc_series(ctx, levels, m, nrec, points=PTS12, seed=seed,
+                         opts=hm.make_opts(prec=hm.PREC_FP64, tol=1e-10, max_outer=60))
+    ctx.close()
+    assert res["nonconverged"] == 0
+    lm, lv = [], []
+    for l, ml in enumerate(m):
+        xi = oracle.sample_xi(seed, l, 0, ml, 3)
+        fine = [oracle.trace(hi.PHYS, levels[l][2], *oracle.fields_closed(hi.PHYS, *levels[l][:2], x), nrec,
+                             PTS12)[0].ravel() for x in xi]
+        coarse = None
+        if l > 0:
+            coarse = [oracle.trace(hi.PHYS, levels[l - 1][2], *oracle.fields_closed(hi.PHYS, *levels[l - 1][:2], x),
+                                   nrec, PTS12)[0].ravel() for x in xi]
+        a, b = oracle.level_stats(np.array(fine), None if coarse is None else np.array(coarse))
+        lm.append(a)
+        lv.append(b)
+    E, var = oracle.mlmc_estimate(lm, lv, m)
+    shape = (nrec, 13)
+    lm, lv = np.array(lm).reshape((2,) + shape), np.array(lv).reshape((2,) + shape)
+    E, var = E.reshape(shape), var.reshape(shape)
+    # c at the points: to the FP64 path's accuracy
+    np.testing.assert_allclose(res["level_mean"][..., 1:], lm[..., 1:], rtol=0, atol=1e-8)
+    np.testing.assert_allclose(res["level_var"][..., 1:], lv[..., 1:], rtol=1e-6, atol=1e-14)
+    np.testing.assert_allclose(res["mean"][:, 1:], E[:, 1:], rtol=0, atol=1e-8)
+    np.testing.assert_allclose(res["var_est"][:, 1:], var[:, 1:], rtol=1e-6, atol=1e-14)
+    # Q_FW counts cells: equal, unless a cell within the solves' error of the
+    # threshold falls on the other side (at most a cell or two per solve)
+    assert np.abs(res["level_mean"][..., 0] - lm[..., 0]).max() <= 2 / 64 / min(m)
+    assert np.abs(res["mean"][:, 0] - E[:, 0]).max() <= 4 / 64 / min(m)
