@@ -134,6 +134,16 @@ typedef struct {
                                  microseconds; 0 = 10 s.  A member that waits
                                  longer stops its cluster: the solve reports
                                  HENRY_STATUS_SYNC.                              */
+    int32_t predictor;        /* start of each step's iteration, extrapolated
+                                 through the last converged states: 1 = the
+                                 interpolating polynomial through up to four;
+                                 2 = the same, then the least-squares cubic
+                                 through five once five are there (it
+                                 amplifies the states' own errors, of the size
+                                 of tol, less); 0 = built-in: 2 for solves of
+                                 200 steps or more at tol >= 1e-8, else 1.
+                                 The choice changes only the iteration count,
+                                 not what a step converges to (within tol).      */
 } henry_opts_t;
 
 /* Timing of one grid group of the last henry_solve_batch call made with
@@ -319,7 +329,7 @@ int henry_profile_last(henry_ctx* ctx, henry_group_time_t* out, int32_t cap, int
 
 /* Workspace for henry_adjoint_batch: the forward workspace plus, per solve,
  * FP64 adjoint state and checkpoints:
- * 8 (16 n + 8 + ceil(r/k) (8 n + 8) + (k + 1) 2 n) bytes for n cells,
+ * 8 (16 n + 8 + ceil(r/k) (10 n + 8) + (k + 1) 2 n) bytes for n cells,
  * r steps, checkpoint interval k. */
 int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves,
                                   const henry_opts_t* opts, int32_t ckpt_every, size_t* bytes_out);
@@ -334,7 +344,7 @@ int henry_adjoint_workspace_bytes(henry_ctx* ctx, const henry_grid_t* solves, in
  * defect correction to max |r|/diag <= adj_tol * max |b|/diag (at most
  * adj_max_it iterations) with the forward V-cycles (opts->prec inner
  * precision) as preconditioner.  The forward pass keeps (p, c) and the
- * three older states of its extrapolated initial guess every ckpt_every
+ * four older states of its extrapolated initial guess every ckpt_every
  * steps and recomputes each segment (bitwise the same states) during the
  * reverse sweep.
  *   qoi_out   device [nsolves]

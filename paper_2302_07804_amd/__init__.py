@@ -70,7 +70,7 @@ class Grid(ct.Structure):
 class Opts(ct.Structure):
     _fields_ = [("prec", ct.c_int32), ("max_outer", ct.c_int32), ("tol", ct.c_double), ("threads", ct.c_int32),
                 ("steps_per_launch", ct.c_int32), ("profile", ct.c_int32), ("serial_groups", ct.c_int32),
-                ("cluster", ct.c_int32), ("cluster_wait_us", ct.c_int32)]
+                ("cluster", ct.c_int32), ("cluster_wait_us", ct.c_int32), ("predictor", ct.c_int32)]
 
 
 class GroupTime(ct.Structure):

@@ -41,8 +41,8 @@ struct AdjLaunch {
 __host__ __device__ inline int num_ckpts(int nsteps, int k) { return (nsteps + k - 1) / k; }
 
 // Doubles per checkpoint: p, c and the extrapolation history pp, cn, p2,
-// c2, p3, c3 (n each), then the converged-state counter (8 doubles).
-__host__ __device__ inline int64_t ckpt_doubles(int64_t n) { return 8 * n + 8; }
+// c2, p3, c3, p4, c4 (n each), then the converged-state counter (8 doubles).
+__host__ __device__ inline int64_t ckpt_doubles(int64_t n) { return 10 * n + 8; }
 
 // FP64 adjoint region: mu_p, mu_c, lam_p, lam_c, dinv_p, dinv_c (inverse
 // diagonals of the two blocks at the current step, for the scaled norm),
@@ -410,8 +410,10 @@ __device__ void save_ckpt(const Solve<T>& S, double* dst, int good) {
         dst[5 * n + idx] = S.c2[idx];
         dst[6 * n + idx] = S.p3[idx];
         dst[7 * n + idx] = S.c3[idx];
+        dst[8 * n + idx] = S.p4[idx];
+        dst[9 * n + idx] = S.c4[idx];
     }
-    if (g_cl.member == 0 && threadIdx.x == 0) dst[8 * n] = (double)good;
+    if (g_cl.member == 0 && threadIdx.x == 0) dst[10 * n] = (double)good;
     ClusterTeam::sync();
 }
 
@@ -427,13 +429,16 @@ __device__ int load_ckpt(Solve<T>& S, const double* src) {
         S.c2[idx] = src[5 * n + idx];
         S.p3[idx] = src[6 * n + idx];
         S.c3[idx] = src[7 * n + idx];
+        S.p4[idx] = src[8 * n + idx];
+        S.c4[idx] = src[9 * n + idx];
     }
     ClusterTeam::sync();
-    return (int)src[8 * n];
+    return (int)src[10 * n];
 }
 
-// Extrapolation order of a step after `good` converged states in a row.
-__device__ inline int extrap_order(int good) { return good - 1 < 3 ? (good - 1 > 0 ? good - 1 : 0) : 3; }
+// Extrapolation order of a transposed solve's start after `good` converged
+// solutions in a row (polynomials through up to four, mu_extrapolate).
+__device__ inline int mu_order(int good) { return good - 1 < 3 ? (good - 1 > 0 ? good - 1 : 0) : 3; }
 
 template <typename T>
 __device__ void load_state(Solve<T>& S, const double* src, const double* prev) {
@@ -476,15 +481,16 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     // ---- forward pass with checkpoints (each step starts from the same
     // extrapolated guess as the forward solve kernel's)
     const int64_t ck = ckpt_doubles(n);
+    const int top = max_order(lp.predictor, N, lp.tol);
     initial_state(ph, S, nullptr);
     ClusterTeam::sync();
     int good = 1;
     for (int s = 0; s < N && !g_cl.failed; ++s) {
         if (s % k == 0) save_ckpt(S, A.ckpt + (int64_t)(s / k) * ck, good);
-        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, fiters, pc, extrap_order(good));
+        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, fiters, pc, start_order(good, top));
         if (st == 2) { status = 2; break; }
         if (st == 1 && status == 0) status = 1;
-        good = st == 0 ? (good < 4 ? good + 1 : 4) : 0;
+        good = next_good(good, st);
     }
     // (the leader's block reduction, as with one workgroup)
     const double Q = member == 0 ? qoi_of(ph, S, red) : 0.0;
@@ -512,13 +518,13 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
         save_state(S, A.seg);
         for (int s = s0; s < s1; ++s) {
             double dummy = 0.0;
-            const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, dummy, pc, extrap_order(g));
-            g = st == 0 ? (g < 4 ? g + 1 : 4) : 0;
+            const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, dummy, pc, start_order(g, top));
+            g = next_good(g, st);
             save_state(S, A.seg + (int64_t)(s - s0 + 1) * 2 * n);
         }
         for (int m = s1; m > s0; --m) {
             load_state(S, A.seg + (int64_t)(m - s0) * 2 * n, A.seg + (int64_t)(m - 1 - s0) * 2 * n);
-            mu_extrapolate(S, A, extrap_order(agood));
+            mu_extrapolate(S, A, mu_order(agood));
             const int st = adjoint_step(ph, S, A, red, al.max_it, al.tol, aiters);
             agood = st == 0 ? (agood < 4 ? agood + 1 : 4) : 0;
             if (st == 2) { status = 2; break; }

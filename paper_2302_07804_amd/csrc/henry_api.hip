@@ -137,6 +137,7 @@ int check_opts(const henry_opts_t* o) {
     if (o->serial_groups != 0 && o->serial_groups != 1) return HENRY_EINVAL;
     if (o->cluster != 0 && (o->cluster > henry::kMaxCluster || !pow2(o->cluster))) return HENRY_EINVAL;
     if (o->cluster_wait_us < 0) return HENRY_EINVAL;
+    if (o->predictor < 0 || o->predictor > 2) return HENRY_EINVAL;
     return HENRY_OK;
 }
 
@@ -601,6 +602,7 @@ int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves
     std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
     lp.tol = o->tol;
     lp.max_outer = o->max_outer;
+    lp.predictor = o->predictor;
     lp.field_kind = field_kind_of(field);
     lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
     if (tr.nrec > 0) {
@@ -645,7 +647,8 @@ int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves
     int64_t tolbits;
     std::memcpy(&tolbits, &o->tol, 8);
     for (int64_t v : {(int64_t)o->prec, (int64_t)o->max_outer, tolbits, (int64_t)o->threads, (int64_t)spl,
-                      (int64_t)o->serial_groups, (int64_t)field, (int64_t)o->cluster, (int64_t)o->cluster_wait_us})
+                      (int64_t)o->serial_groups, (int64_t)field, (int64_t)o->cluster, (int64_t)o->cluster_wait_us,
+                      (int64_t)o->predictor})
         key.words.push_back(v);
     // the time-series request is part of the captured kernel arguments
     key.words.push_back((int64_t)(uintptr_t)tr.out);
@@ -935,6 +938,7 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     std::memcpy(&lp.ph, &ctx->ph, sizeof(lp.ph));
     lp.tol = o->tol;
     lp.max_outer = o->max_outer;
+    lp.predictor = o->predictor;
     lp.field_kind = field_kind_of(field);
     lp.xi_dim = field == HENRY_FIELD_KL41 ? 41 : 3;
     henry::AdjLaunch al{};

@@ -76,6 +76,7 @@ struct Launch {
     Phys ph;
     double tol;
     int32_t max_outer;
+    int32_t predictor;       // henry_opts_t.predictor
     int32_t field_kind;
     int32_t g_begin, g_end;  // global step range of this launch
     int32_t g_total;         // global steps of the whole batch (max nsteps)
@@ -127,13 +128,13 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
 //   wx, wy  east / north face phi_f D (harmonic phi; 2 phi_P D on the
 //           seawater face; 0 above the top row),
 //   isc     residual scale tau / (h^2 phi_P rho0),
-// then the two older states c2, p2 (u^{n-2}) and c3, p3 (u^{n-3}) of the
-// extrapolated initial guess, then kScratch doubles of scratch: [0] recharge, [1] status, [2] outer
+// then the older states c2, p2 (u^{n-2}), c3, p3 (u^{n-3}) and c4, p4
+// (u^{n-4}) of the extrapolated initial guess, then kScratch doubles of scratch: [0] recharge, [1] status, [2] outer
 // iterations, [3] converged states in a row, [8..31] phase timers of builds with
 // HENRY_PHASE_TIMERS, [32..63] the state of a cluster of workgroups sharing the solve (the members'
 // 32-bit arrival counts in [32..35], the error flag in [36], barriers passed [37], the members' XCD
 // ids [40..47], their partial residual norms [48..63]).
-enum : int { kP, kC, kCn, kPhi, kK, kPp, kTx, kTy, kWx, kWy, kIsc, kC2, kP2, kC3, kP3, kF64Arrays };
+enum : int { kP, kC, kCn, kPhi, kK, kPp, kTx, kTy, kWx, kWy, kIsc, kC2, kP2, kC3, kP3, kC4, kP4, kF64Arrays };
 constexpr int kScratch = 64;
 constexpr int kClusterFlags = 32, kClusterErr = 36, kClusterGen = 37, kClusterXcc = 40, kClusterSlots = 48;
 constexpr int kMaxCluster = 8;
@@ -188,7 +189,7 @@ struct Solve {
     int hand;      // level lc is in LDS and fed by the cluster through its global copy hg
     double h, tau;
     double q;  // recharge (m/s)
-    double *p, *c, *cn, *phi, *K, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *scratch;
+    double *p, *c, *cn, *phi, *K, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *c4, *p4, *scratch;
     Level<T> lv[kMaxLevels];
     Level<T> hg;  // the global-memory arrays of level lb
     double *rout_p, *rout_c;  // residual outputs (henry_residual_kernel)
@@ -230,7 +231,8 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, ui
     auto arr = [&](int k) { return f + (int64_t)k * n; };
     S.p = arr(kP); S.c = arr(kC); S.cn = arr(kCn); S.phi = arr(kPhi); S.K = arr(kK); S.pp = arr(kPp);
     S.tx = arr(kTx); S.ty = arr(kTy); S.wx = arr(kWx); S.wy = arr(kWy); S.isc = arr(kIsc);
-    S.c2 = arr(kC2); S.p2 = arr(kP2); S.c3 = arr(kC3); S.p3 = arr(kP3); S.scratch = arr(kF64Arrays);
+    S.c2 = arr(kC2); S.p2 = arr(kP2); S.c3 = arr(kC3); S.p3 = arr(kP3); S.c4 = arr(kC4); S.p4 = arr(kP4);
+    S.scratch = arr(kF64Arrays);
     uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
     uint8_t* ql = lds;
     int lx = nx, ly = ny;
@@ -1422,11 +1424,14 @@ __device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr, bool coarse_coeffs
 // One implicit Euler step (Sec. 2.3) from the state u^n = (S.p, S.c):
 // saves u^n in S.cn / S.pp (c^n is the previous time level of the
 // residual), shifts the older states, and runs the defect correction until
-// both scaled residual max norms are <= tol.  The iteration starts from the
-// polynomial extrapolation of order `order` (0..3) through the last
-// order + 1 states (backward differences: u^n; 2u^n - u^{n-1};
-// 3u^n - 3u^{n-1} + u^{n-2}; 4u^n - 6u^{n-1} + 4u^{n-2} - u^{n-3}); on
-// entry S.cn/pp, c2/p2, c3/p3 hold u^{n-1}, u^{n-2}, u^{n-3}.  The start
+// both scaled residual max norms are <= tol.  The iteration starts from an
+// extrapolation through the last states, by `order`: 0..3 the polynomial
+// through the last order + 1 states (u^n; 2u^n - u^{n-1};
+// 3u^n - 3u^{n-1} + u^{n-2}; 4u^n - 6u^{n-1} + 4u^{n-2} - u^{n-3}), 4 the
+// least-squares cubic through the last five, (16u^n - 14u^{n-1} - 4u^{n-2}
+// + 11u^{n-3} - 4u^{n-4}) / 5, which amplifies the states' own errors (of
+// the size of the tolerance) less than the interpolating cubic does; on
+// entry S.cn/pp, c2/p2, c3/p3, c4/p4 hold u^{n-1} .. u^{n-4}.  The start
 // only changes how many iterations a step takes, not what it converges to.
 // Returns 0 converged, 1 max_outer reached, 2 non-finite residual; adds the
 // iterations used to `iters`.
@@ -1448,7 +1453,12 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
         } else if (order == 3) {
             S.c[idx] = 4.0 * c0 - 6.0 * c1 + 4.0 * c2 - S.c3[idx];
             S.p[idx] = 4.0 * p0 - 6.0 * p1 + 4.0 * p2 - S.p3[idx];
+        } else if (order == 4) {
+            S.c[idx] = (16.0 * c0 - 14.0 * c1 - 4.0 * c2 + 11.0 * S.c3[idx] - 4.0 * S.c4[idx]) * 0.2;
+            S.p[idx] = (16.0 * p0 - 14.0 * p1 - 4.0 * p2 + 11.0 * S.p3[idx] - 4.0 * S.p4[idx]) * 0.2;
         }
+        S.c4[idx] = S.c3[idx];
+        S.p4[idx] = S.p3[idx];
         S.c3[idx] = c2;
         S.p3[idx] = p2;
         S.c2[idx] = c1;
@@ -1507,6 +1517,18 @@ __device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
         if ((idx % S.nx) < S.nx / 2) part += S.phi[idx] * rho_of(ph, S.c[idx]) * S.c[idx];
     return block_sum(part, red) * S.h * S.h;
 }
+
+// Start of a step after `good` converged states in a row (the initial state
+// counts as one): the extrapolation order grows with the history, up to the
+// interpolating cubic (predictor 1) or the least-squares cubic through five
+// states (predictor 2).  Predictor 0 takes 2 where the states' own errors,
+// of the size of tol, outweigh the cubic's interpolation error: solves of
+// 200 steps or more at tol >= 1e-8; 1 elsewhere.
+__device__ inline int max_order(int predictor, int nsteps, double tol) {
+    return predictor == 2 || (predictor == 0 && nsteps >= 200 && tol >= 1e-8) ? 4 : 3;
+}
+__device__ inline int start_order(int good, int top) { return min(max(good - 1, 0), top); }
+__device__ inline int next_good(int good, int st) { return st == 0 ? min(good + 1, 5) : 0; }
 
 // ------------------------------------------------------------------ time series
 // Value of the piecewise-constant solution at (x, y): the cell that holds
@@ -1609,15 +1631,15 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
     PhaseClock pc;
     pc.init();
     const int64_t N = d.nsteps, nrec = lp.trace ? lp.trace_nrec : 0;
+    const int top = max_order(lp.predictor, d.nsteps, lp.tol);
     int s = s_begin;
     for (; s < s_end && status != 2 && !g_cl.failed; ++s) {
         // extrapolate only through converged states: a step that stopped at
         // max_outer restarts the history
-        const int order = good - 1 < 3 ? (good - 1 > 0 ? good - 1 : 0) : 3;
-        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, iters, pc, order);
+        const int st = implicit_step(ph, S, red, lp.max_outer, lp.tol, iters, pc, start_order(good, top));
         if (st == 2) status = 2;
         else if (st == 1 && status == 0) status = 1;
-        good = st == 0 ? (good < 4 ? good + 1 : 4) : 0;
+        good = next_good(good, st);
         if (nrec && st != 2) {
             // the record whose step is s + 1, if any (nrec <= N: at most one)
             const int64_t k = (int64_t)(s + 1) * nrec / N;

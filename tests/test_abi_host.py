@@ -80,7 +80,8 @@ def test_workspace_validation(L):
         assert e.value.code == hm.HENRY_EINVAL
     for kw in [dict(prec=7), dict(max_outer=0), dict(tol=0.0), dict(tol=float("nan")), dict(threads=96),
                dict(steps_per_launch=-1), dict(prec=hm.PREC_FP64, threads=1024), dict(threads=2048),
-               dict(cluster=3), dict(cluster=16), dict(cluster=-1), dict(cluster_wait_us=-1)]:
+               dict(cluster=3), dict(cluster=16), dict(cluster=-1), dict(cluster_wait_us=-1), dict(predictor=3),
+               dict(predictor=-1)]:
         with pytest.raises(hm.HenryError):
             hm.henry_workspace_bytes(ok, hm.make_opts(**kw))
     assert hm.henry_workspace_bytes(ok, hm.make_opts(prec=hm.PREC_MIXED, threads=1024)) > 0
