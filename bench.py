@@ -168,9 +168,11 @@ def main():
                          "reference (POINTS points x SHIFTS shifts) on 512x256/1600, at (1.60, -0.95) and for E[Q] "
                          "(default 128 4 with the other workloads, ~25 s)")
     ap.add_argument("--paper-setup", action="store_true",
-                    help="the paper's own set-up (two-layer porosity, Table 1 constants, T = 6016 s, 32x16-based "
-                         "hierarchy with r0 = 188): one-sample solve times per level 0..5 and the MLMC run with "
-                         "Table 3's counts for eps^2 = 1e-7 (~100 s)")
+                    help="run the paper-set-up workloads even with --no-extras")
+    ap.add_argument("--no-paper-setup", action="store_true",
+                    help="skip the paper's own set-up (two-layer porosity, Table 1 constants, T = 6016 s, "
+                         "32x16-based hierarchy with r0 = 188): one-sample solve times per level 0..5, the MLMC "
+                         "run with Table 3's counts for eps^2 = 1e-7, 600 time series and their MLMC mean (~50 s)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of CALIB_BYTES before the batch (HBM-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -484,7 +486,7 @@ def main():
         log(f"QMC {npts}x{nsh} on {ref_grid}: {qr['seconds']:.1f} s, E[Q] = {qr['EQ']:.6f} +- {qr['se']:.1e}, "
             f"c(1.60,-0.95) = {Ec_ref:.6f}; MLMC by level c: {tel_c}, E[Q]: {tel_q}")
 
-    if args.paper_setup:
+    if args.paper_setup or not (args.no_extras or args.no_paper_setup):
         extras = extras if extras is not None else {}
         pctx = hm.Context(hi.PHYS_TABLE1, 0)
         popts = hm.make_opts(prec=hm.PREC_MIXED, tol=args.tol, max_outer=60)
