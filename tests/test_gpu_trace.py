@@ -232,3 +232,40 @@ def test_mlmc_series_matches_oracle(torch_cuda):
     # threshold falls on the other side (at most a cell or two per solve)
     assert np.abs(res["level_mean"][..., 0] - lm[..., 0]).max() <= 2 / 64 / min(m)
     assert np.abs(res["mean"][:, 0] - E[:, 0]).max() <= 4 / 64 / min(m)
+
+
+@pytest.mark.parametrize("grid,nrec", [((2, 1, 6), 6), ((4, 2, 5), 5), ((1024, 512, 3), 3)])
+def test_trace_edge_grids(torch_cuda, grid, nrec):
+    """Edge cases of the time series: the smallest grids (one and two rows,
+    where most points fall on faces or corners), a record after every step,
+    16 points (the most a call takes), thresholds that make every cell fresh
+    or none, and the largest grid (three steps of 1024x512 at tau = T/3200,
+    on a cluster of workgroups) against the oracle's point values and
+    counts."""
+    torch = torch_cuda
+    nx, ny, r = grid
+    pts = PTS[:13] + [(0.5, -0.5), (1.5, -0.25), (0.0, 0.0)]
+    assert len(pts) == 16
+    phys = hi.PHYS if nx < 1024 else dict(hi.PHYS, T=hi.PHYS["T"] * 3 / 3200)
+    xi = hm.henry_sample_xi(0, 43, 0, 1, 3)
+    ctx = hm.Context(phys, 0)
+    opts = hm.make_opts(prec=hm.PREC_MIXED if nx >= 1024 else hm.PREC_FP64, tol=1e-9, max_outer=60)
+    outs = {f: hm.solve(ctx, [grid], xi=dev(torch, xi), opts=opts, trace=(nrec, pts, f)) for f in (-1.0, 2.0, 0.012178)}
+    torch.cuda.synchronize()
+    ctx.close()
+    assert (outs[-1.0]["trace"][..., 0] == 0.0).all()
+    assert (outs[2.0]["trace"][..., 0] == 2.0).all()
+    phi, K, q = oracle.fields_closed(phys, nx, ny, xi[0])
+    if nx < 1024:
+        ref, o = oracle.trace(phys, r, phi, K, q, nrec, pts)
+        tr = outs[0.012178]["trace"][0].cpu().numpy()
+        near = max(int(np.count_nonzero(np.abs(o["c_traj"][st] - oracle.FRESH) < 1e-6))
+                   for st in oracle.record_steps(r, nrec))
+        check_trace(tr, ref, None, nx, ny, 1e-8, near)
+    else:
+        # the last record against the oracle's point rule on the solve's own final state
+        out = outs[0.012178]
+        c = out["c"].cpu().numpy().reshape(ny, nx)
+        tr = out["trace"][0, -1].cpu().numpy()
+        assert tr[0] == oracle.fresh_area(c)
+        np.testing.assert_allclose(tr[1:], [oracle.point_value(c, x, y) for x, y in pts], rtol=0, atol=1e-15)
