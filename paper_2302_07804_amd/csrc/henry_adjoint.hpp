@@ -19,7 +19,7 @@
 // pressure block on the recomputed residual.
 //
 // Time reversal by checkpointing: the forward pass stores its state every
-// `ckpt` steps, with the three older states and the counter its
+// `ckpt` steps, with the four older states and the counter its
 // extrapolated initial guess draws on; each segment is recomputed from its
 // checkpoint (bitwise the same states) and then walked backwards.
 #pragma once

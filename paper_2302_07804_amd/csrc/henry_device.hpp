@@ -17,8 +17,9 @@
 //     c += dc                                                         FP64
 //   until both scaled residual norms <= tol
 //
-// Each step starts from the polynomial extrapolation of the last converged
-// states (up to cubic).
+// Each step starts from an extrapolation through the last converged states
+// (interpolating polynomials up to cubic, then on long solves the
+// least-squares cubic through five states; see implicit_step).
 //
 // A_pp = -div(rho K / mu grad .) with the seawater Dirichlet face.  The salt
 // block is driven by S = R^c - c R^p, an exact recombination of the two
