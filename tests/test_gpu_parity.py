@@ -428,3 +428,28 @@ def test_predictors_converge_to_the_same_states(torch_cuda, ctx):
     b = run(torch, ctx, solves, xi, hm.PREC_MIXED, tol=1e-7, predictor=2)
     assert (a["c"] - b["c"]).abs().max().item() <= 1e-6
     assert b["iters"].sum().item() < a["iters"].sum().item()
+
+
+def test_resume_from_a_stored_state(torch_cuda):
+    """Checkpoint / resume: a solve of N steps equals one of s steps (to
+    s T / N) followed by N - s steps (over the rest of the horizon) started
+    from the stored c field, to the tolerance's reach.  p needs no storing:
+    given c and c^n, the fluid balance fixes it."""
+    torch = torch_cuda
+    nx, ny, N, s = 64, 32, 200, 70
+    xi = hm.henry_sample_xi(0, 18, 0, 1, 3)
+    xi_d = torch.tensor(xi, dtype=torch.float64, device="cuda")
+    opts = hm.make_opts(prec=hm.PREC_FP64, tol=1e-11, max_outer=80)
+    full_ctx = hm.Context(hi.PHYS, 0)
+    full = hm.solve(full_ctx, [(nx, ny, N)], xi=xi_d, opts=opts)
+    tau = hi.PHYS["T"] / N
+    first_ctx = hm.Context(dict(hi.PHYS, T=s * tau), 0)
+    first = hm.solve(first_ctx, [(nx, ny, s)], xi=xi_d, opts=opts)
+    rest_ctx = hm.Context(dict(hi.PHYS, T=(N - s) * tau), 0)
+    rest = hm.solve(rest_ctx, [(nx, ny, N - s)], xi=xi_d, c0=first["c"], opts=opts)
+    torch.cuda.synchronize()
+    for c in (full_ctx, first_ctx, rest_ctx):
+        c.close()
+    assert full["status"].item() == first["status"].item() == rest["status"].item() == hm.STATUS_OK
+    assert (full["c"] - rest["c"]).abs().max().item() <= 1e-9
+    assert abs(full["qoi"].item() - rest["qoi"].item()) <= 1e-9 * abs(full["qoi"].item())
