@@ -311,6 +311,37 @@ int henry_first_passage(henry_ctx* ctx, int32_t nsamples, int32_t nrec, int32_t 
                         const double* trace, double threshold, int32_t below, int32_t* t_out, int32_t* hist_out,
                         void* stream);
 
+/* One multigrid level's smoothing on a caller's linear system A x = b, with
+ * the device functions the solves run in every V-cycle (the multigrid
+ * preconditioning of Sec. 2.3, redesigned: RB Gauss-Seidel for the
+ * pressure, zebra line relaxation for the transport), for checking each on
+ * its own.  nx x ny as for a solve; fields [ny][nx] device FP64; x is the
+ * start on entry and the result on return (converted to the inner type of
+ * prec and back).
+ *   kind 0: `sweeps` red-black Gauss-Seidel sweeps, red cells ((i + j) even)
+ *           first, on the pressure operator
+ *             (A x)_P = sum over P's interior faces f of t_f (x_P - x_Q)
+ *                       + te_P x_P on the last column (the seawater face),
+ *           coef [2][ny][nx] = te (east face; on the last column the
+ *           seawater face), tn (north face; the top row's is ignored).
+ *   kind 1 / 2: `sweeps` zebra sweeps of x-lines (rows 0, 2, .. then 1, 3,
+ *           ..) or y-lines (columns, likewise), each line solved exactly, on
+ *           the transport operator (A x)_P = d_P x_P - sum_Q a_PQ x_Q: a
+ *           neighbour couples through the inflow across the shared face plus
+ *           diffusion, a_PE = max(-mx_P, 0) + dx_P, a_PW = max(mx_W, 0) + dx_W,
+ *           a_PN = max(-my_P, 0) + dy_P, a_PS = max(my_S, 0) + dy_S; d_P =
+ *           acc_P + the sum of P's couplings + on the last column
+ *           max(-mr_j, 0) + dr_j, on the first dl_j + ml_j.
+ *           coef [5][ny][nx] = acc, mx, my, dx, dy (mass flux and diffusion
+ *           of the east / north face; the last column's mx and the top row's
+ *           my unused), then [4][ny] = mr, dr, dl, ml.
+ * workspace: device, 256-byte aligned, >= e (10 nx ny + 4 ny) bytes, e = 4
+ * (HENRY_PREC_MIXED) or 8 (HENRY_PREC_FP64).  One workgroup.  Errors:
+ * HENRY_EINVAL, HENRY_ENOMEM (workspace too small), HENRY_EHIP. */
+int henry_level_smooth(henry_ctx* ctx, int32_t nx, int32_t ny, int32_t kind, int32_t prec, int32_t sweeps,
+                       const double* coef, const double* b, double* x, void* workspace, size_t ws_bytes,
+                       void* stream);
+
 /* Tuning cache of a context: threads per solve-workgroup for grids of
  * width nx at precision prec, used by henry_solve_batch and
  * henry_adjoint_batch when opts->threads == 0.  threads = 0 clears the

@@ -283,6 +283,107 @@ def adjoint_xi(phys, nx, ny, nsteps, xi, model=None):
     return Q, g, gK * K
 
 
+# ---------------------------------------------------------------- multigrid smoothers
+def pressure_operator(te, tn):
+    """Sparse matrix of the pressure operator on an [ny][nx] grid (the
+    fluid balance's flux form, Sec. 2.3): every interior face couples its
+    two cells with its coefficient (east faces te, north faces tn), and the
+    last column's te is the seawater face's, on the diagonal only."""
+    import scipy.sparse as sp
+    ny, nx = te.shape
+    rows, cols, vals = [], [], []
+    diag = np.zeros(nx * ny)
+    for j in range(ny):
+        for i in range(nx):
+            P = j * nx + i
+            if i + 1 < nx:
+                E = P + 1
+                t = te[j, i]
+                rows += [P, E, P, E]; cols += [E, P, P, E]; vals += [-t, -t, t, t]
+            else:
+                diag[P] += te[j, i]
+            if j + 1 < ny:
+                N = P + nx
+                t = tn[j, i]
+                rows += [P, N, P, N]; cols += [N, P, P, N]; vals += [-t, -t, t, t]
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(nx * ny, nx * ny)).tocsr()
+    return (A + sp.diags(diag)).tocsr()
+
+
+def transport_operator(acc, mx, my, dx, dy, mr, dr, dl, ml):
+    """Sparse matrix of the upwind transport operator on an [ny][nx] grid:
+    a cell takes from a neighbour the mass flowing in across their face
+    (mx, my: flux leaving the cell east / north) plus the face's diffusion
+    (dx, dy); its diagonal is its accumulation plus everything it couples
+    to, and on the last and first column the boundary inflow / diffusion
+    terms (mr, dr at the sea side, dl, ml at the recharge side)."""
+    import scipy.sparse as sp
+    ny, nx = acc.shape
+    pos = lambda a: max(a, 0.0)
+    rows, cols, vals = [], [], []
+    for j in range(ny):
+        for i in range(nx):
+            P = j * nx + i
+            d = acc[j, i]
+            nb = []
+            if i + 1 < nx:
+                nb.append((P + 1, pos(-mx[j, i]) + dx[j, i]))
+            else:
+                d += pos(-mr[j]) + dr[j]
+            if i > 0:
+                nb.append((P - 1, pos(mx[j, i - 1]) + dx[j, i - 1]))
+            else:
+                d += dl[j] + ml[j]
+            if j + 1 < ny:
+                nb.append((P + nx, pos(-my[j, i]) + dy[j, i]))
+            if j > 0:
+                nb.append((P - nx, pos(my[j - 1, i]) + dy[j - 1, i]))
+            for Q, a in nb:
+                rows.append(P); cols.append(Q); vals.append(-a)
+                d += a
+            rows.append(P); cols.append(P); vals.append(d)
+    return sp.coo_matrix((vals, (rows, cols)), shape=(nx * ny, nx * ny)).tocsr()
+
+
+def gauss_seidel_rb(A, b, x, nx, ny, sweeps):
+    """Red-black Gauss-Seidel on A x = b: per sweep every red cell
+    ((i + j) even) is relaxed, x_P = (b_P - sum_{Q != P} A_PQ x_Q) / A_PP, then
+    every black cell with the red values updated."""
+    x = np.array(x, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    A = A.tocsr()
+    colour = np.add.outer(np.arange(ny), np.arange(nx)).ravel() & 1
+    for _ in range(sweeps):
+        for col in (0, 1):
+            new = x.copy()
+            for P in np.flatnonzero(colour == col):
+                lo, hi = A.indptr[P], A.indptr[P + 1]
+                off = sum(A.data[k] * x[A.indices[k]] for k in range(lo, hi) if A.indices[k] != P)
+                new[P] = (b[P] - off) / A[P, P]
+            x = new
+    return x.reshape(ny, nx)
+
+
+def zebra_lines(A, b, x, nx, ny, sweeps, ylines=False):
+    """Zebra line relaxation on A x = b: per sweep the even lines (rows, or
+    columns with ylines), then the odd ones, each solved exactly with the
+    other lines held at their current values."""
+    x = np.array(x, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    A = A.tocsr()
+    nlines = nx if ylines else ny
+    for _ in range(sweeps):
+        for col in (0, 1):
+            for line in range(col, nlines, 2):
+                idx = [j * nx + line for j in range(ny)] if ylines else [line * nx + i for i in range(nx)]
+                mask = np.zeros(nx * ny, bool)
+                mask[idx] = True
+                sub = A[idx][:, idx].toarray()
+                rhs = b[idx] - A[idx][:, ~mask] @ x[~mask]
+                x[idx] = np.linalg.solve(sub, rhs)
+    return x.reshape(ny, nx)
+
+
 # ---------------------------------------------------------------- time series (Sec. 4)
 FRESH = 0.012178  # c threshold of the fresh-water indicator in eq:integral_fw
 

@@ -29,7 +29,7 @@ EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opt
            "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
            "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch", "henry_mlmc_allocate",
            "henry_mlmc_rates", "henry_qmc_points", "henry_solve_batch_trace", "henry_sample_stats",
-           "henry_first_passage")
+           "henry_first_passage", "henry_level_smooth")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -110,6 +110,7 @@ def lib():
                                           vp]
     L.henry_sample_stats.argtypes = [vp, i32, i32, vp, vp, i32, ct.POINTER(ct.c_double), vp, vp, vp, vp]
     L.henry_first_passage.argtypes = [vp, i32, i32, i32, i32, vp, dbl, i32, vp, vp, vp]
+    L.henry_level_smooth.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, ct.c_size_t, vp]
     L.henry_profile_last.argtypes = [vp, ct.POINTER(GroupTime), i32, ct.POINTER(i32)]
     L.henry_mlmc_allocate.argtypes = [i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), dbl,
                                       ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
@@ -308,6 +309,18 @@ def henry_first_passage(ctx: Context, trace, col, threshold, below=True, stream=
     _chk(lib().henry_first_passage(ctx.handle, ns, nrec, stride, int(col), _ptr(trace), float(threshold),
                                    1 if below else 0, _ptr(t), _ptr(hist), _stream_of(stream)), "henry_first_passage")
     return t, hist
+
+
+def henry_level_smooth(ctx: Context, nx, ny, kind, prec, sweeps, coef, b, x, stream=None):
+    """`sweeps` smoothing sweeps of one multigrid level on A x = b (kind 0
+    pressure red-black Gauss-Seidel, 1 / 2 transport x- / y-line zebra);
+    coef, b, x are device FP64 tensors, x is updated in place."""
+    import torch
+    elt = 4 if prec == PREC_MIXED else 8
+    ws = _aligned_workspace(elt * (10 * nx * ny + 4 * ny), x.device)
+    _chk(lib().henry_level_smooth(ctx.handle, nx, ny, kind, prec, sweeps, _ptr(coef), _ptr(b), _ptr(x), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream_of(stream)), "henry_level_smooth")
+    return x
 
 
 def henry_residual_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, p=None, c=None,

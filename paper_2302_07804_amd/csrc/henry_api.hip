@@ -19,6 +19,7 @@
 
 #include "henry.h"
 #include "henry_adjoint.hpp"
+#include "henry_check.hpp"
 #include "henry_stats.hpp"
 #include "henry_device.hpp"
 #include "henry_kl.hpp"
@@ -1021,6 +1022,28 @@ int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, con
     }
     hipLaunchKernelGGL(henry::mlmc_combine_kernel, dim3(1), dim3(1024), 0, s0, lp, L, fine[L].nx, fine[L].ny,
                        qstats, Ec_finest, var_est);
+    if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    return HENRY_OK;
+}
+
+int henry_level_smooth(henry_ctx* ctx, int32_t nx, int32_t ny, int32_t kind, int32_t prec, int32_t sweeps,
+                       const double* coef, const double* b, double* x, void* workspace, size_t ws_bytes,
+                       void* stream) {
+    henry_grid_t g{nx, ny, 1, 0};
+    if (!ctx || check_grid(g) != HENRY_OK || kind < 0 || kind > 2 || sweeps < 0 || !coef || !b || !x || !workspace)
+        return HENRY_EINVAL;
+    if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
+    const size_t elt = prec == HENRY_PREC_MIXED ? 4 : 8;
+    if (ws_bytes < elt * (10 * (size_t)nx * ny + 4 * (size_t)ny)) return HENRY_ENOMEM;
+    if (((uintptr_t)workspace & 255) != 0) return HENRY_EINVAL;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    if (prec == HENRY_PREC_MIXED)
+        hipLaunchKernelGGL(henry::level_smooth_kernel<float>, dim3(1), dim3(1024), 0, s0, nx, ny, kind, sweeps,
+                           coef, b, x, reinterpret_cast<float*>(workspace));
+    else
+        hipLaunchKernelGGL(henry::level_smooth_kernel<double>, dim3(1), dim3(512), 0, s0, nx, ny, kind, sweeps,
+                           coef, b, x, reinterpret_cast<double*>(workspace));
     if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
     return HENRY_OK;
 }
