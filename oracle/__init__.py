@@ -3,8 +3,10 @@
 Only `tests/`, `__graft_entry__.smoke()` and the benchmark's `cpu_baseline`
 leg may import this package.  It wraps the plain C oracle
 (`henry_oracle.c`: Newton + exact Jacobian + banded LU, FP64) with ctypes
-and adds the MLMC estimator statistics (Sec. 3 of the paper) and a Halton
-quasi-Monte Carlo rule in plain numpy.  It shares no code with the HIP
+and adds, in plain numpy / scipy: the MLMC estimator statistics (Sec. 3 of
+the paper), a Halton quasi-Monte Carlo rule, the paper's two-layer input
+model, the time series and their statistics (Sec. 4), and the multigrid
+smoothers on explicitly assembled level operators.  It shares no code with the HIP
 library in `paper_2302_07804_amd/`.
 
 Parity status of each function is listed in the module docstrings of the

@@ -114,6 +114,12 @@ int main() {
                                        nullptr, nullptr, 0, nullptr) == HENRY_EINVAL);
         EXPECT(henry_sample_stats(handle, 8193, 3, &d, nullptr, 2, probs, &d, &d, &d, nullptr) == HENRY_EINVAL);
         EXPECT(henry_first_passage(handle, 10, 5, 3, 3, &d, 0.5, 1, &st, &st, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_level_smooth(nullptr, 16, 8, 0, HENRY_PREC_MIXED, 1, &d, &d, &d, &d, 4096, nullptr) ==
+               HENRY_EINVAL);
+        EXPECT(henry_level_smooth(handle, 16, 8, 3, HENRY_PREC_MIXED, 1, &d, &d, &d, &d, 4096, nullptr) ==
+               HENRY_EINVAL);
+        EXPECT(henry_level_smooth(handle, 16, 8, 0, HENRY_PREC_MIXED, 1, &d, &d, &d, &d, 64, nullptr) ==
+               HENRY_ENOMEM);
     }
     int32_t t = 0;
     EXPECT(henry_tune_set(nullptr, 16, HENRY_PREC_MIXED, 128) == HENRY_EINVAL);
