@@ -552,9 +552,14 @@ def main():
             c_1p60_m0p95_mean=[float(v) for v in ms["mean"][:, ip]],
             c_1p60_m0p95_level_mean=[[float(v) for v in ms["level_mean"][l, :, ip]] for l in range(6)],
             c_1p60_m0p95_level_var=[[float(v) for v in ms["level_var"][l, :, ip]] for l in range(6)],
-            Q_FW_level_var=[[float(v) for v in ms["level_var"][l, :, 0]] for l in range(6)])
+            Q_FW_level_var=[[float(v) for v in ms["level_var"][l, :, 0]] for l in range(6)],
+            c_1p60_m0p95_level_amplitude=[[float(max(-a, b)) for a, b in zip(ms["level_min"][l, :, ip],
+                                                                              ms["level_max"][l, :, ip])]
+                                          for l in range(6)])
         log(f"paper set-up, MLMC series (Table 3 counts): {ms['seconds']:.1f} s, {ms['nonconverged']} non-converged; "
-            f"V_l of c(1.60,-0.95) at record 14: {[float(ms['level_var'][l, 13, ip]) for l in range(6)]}")
+            f"V_l of c(1.60,-0.95) at record 14: {[float(ms['level_var'][l, 13, ip]) for l in range(6)]}; "
+            f"max |Y_l| there over all records: "
+            f"{[float(np.max(np.maximum(-ms['level_min'][l, :, ip], ms['level_max'][l, :, ip]))) for l in range(6)]}")
         pctx.close()
 
     res = {

@@ -253,8 +253,9 @@ def mlmc_series(ctx: Context, levels, m, nrec: int, points=POINTS12, seed: int =
     i)).  Each level's nsteps should be a multiple of nrec so that the
     records of all levels fall at the same times k T / nrec.  Returns a
     dict: mean [nrec][1 + npts] (the estimate), var_est (sum_l V_l / m_l,
-    same shape), level_mean and level_var [L+1][nrec][1 + npts], the
-    batch's seconds and the number of non-converged solves."""
+    same shape), level_mean, level_var, level_min and level_max (the
+    smallest and largest Y_l over the level's samples) [L+1][nrec][1 + npts],
+    the batch's seconds and the number of non-converged solves."""
     import torch
     levels = [tuple(int(v) for v in g) for g in levels]
     L = len(levels) - 1
@@ -271,16 +272,19 @@ def mlmc_series(ctx: Context, levels, m, nrec: int, points=POINTS12, seed: int =
     seconds = time.perf_counter() - t0
     tr = out["trace"]
     nv = nrec * (1 + len(points))
-    lm, lv = [], []
+    lm, lv, lq = [], [], []
     for l, (f0, c0, c1) in enumerate(rng):
         fine = tr[f0:c0].reshape(c0 - f0, nv)
         coarse = tr[c0:c1].reshape(c1 - c0, nv) if l > 0 else None
-        mean, var, _ = henry_sample_stats(ctx, fine, (), x_sub=coarse)
+        mean, var, q = henry_sample_stats(ctx, fine, (0.0, 1.0), x_sub=coarse)
         lm.append(mean)
         lv.append(var)
+        lq.append(q)
     torch.cuda.synchronize(dev)
     shape = (nrec, 1 + len(points))
     lm = np.stack([v.cpu().numpy().reshape(shape) for v in lm])
     lv = np.stack([v.cpu().numpy().reshape(shape) for v in lv])
+    lq = np.stack([v.cpu().numpy().reshape((2,) + shape) for v in lq])
     return dict(mean=lm.sum(axis=0), var_est=(lv / m[:, None, None]).sum(axis=0), level_mean=lm, level_var=lv,
-                m=m, seconds=seconds, nonconverged=int((out["status"].cpu().numpy() != 0).sum()))
+                level_min=lq[:, 0], level_max=lq[:, 1], m=m, seconds=seconds,
+                nonconverged=int((out["status"].cpu().numpy() != 0).sum()))

@@ -231,6 +231,17 @@ def test_mlmc_series_matches_oracle(torch_cuda):
     # Q_FW counts cells: equal, unless a cell within the solves' error of the
     # threshold falls on the other side (at most a cell or two per solve)
     assert np.abs(res["level_mean"][..., 0] - lm[..., 0]).max() <= 2 / 64 / min(m)
+    # the extremes of the level differences at the points
+    for l, ml in enumerate(m):
+        xi = oracle.sample_xi(seed, l, 0, ml, 3)
+        Y = np.array([oracle.trace(hi.PHYS, levels[l][2], *oracle.fields_closed(hi.PHYS, *levels[l][:2], x), nrec,
+                                   PTS12)[0] for x in xi])
+        if l > 0:
+            Y -= np.array([oracle.trace(hi.PHYS, levels[l - 1][2],
+                                        *oracle.fields_closed(hi.PHYS, *levels[l - 1][:2], x), nrec, PTS12)[0]
+                           for x in xi])
+        np.testing.assert_allclose(res["level_min"][l][:, 1:], Y.min(axis=0)[:, 1:], rtol=0, atol=1e-8)
+        np.testing.assert_allclose(res["level_max"][l][:, 1:], Y.max(axis=0)[:, 1:], rtol=0, atol=1e-8)
     assert np.abs(res["mean"][:, 0] - E[:, 0]).max() <= 4 / 64 / min(m)
 
 
