@@ -556,6 +556,16 @@ def main():
             c_1p60_m0p95_level_amplitude=[[float(max(-a, b)) for a, b in zip(ms["level_min"][l, :, ip],
                                                                               ms["level_max"][l, :, ip])]
                                           for l in range(6)])
+        # the rates of Fig. 10 at the point, record 14 and T (levels 1..4; level 5 has two samples)
+        rates = {}
+        for rec in (13, nrec - 1):
+            try:
+                a_, b_, _ = hm.henry_mlmc_rates(ms["level_mean"][:5, rec, ip], ms["level_var"][:5, rec, ip], 1)
+                rates[f"record {rec + 1}"] = dict(alpha=a_, beta=b_)
+            except hm.HenryError:
+                rates[f"record {rec + 1}"] = None
+        extras["paper_setup"]["mlmc_series_table3"]["rates_c_1p60_m0p95"] = rates
+        log(f"paper set-up, rates at (1.60,-0.95): {rates}")
         log(f"paper set-up, MLMC series (Table 3 counts): {ms['seconds']:.1f} s, {ms['nonconverged']} non-converged; "
             f"V_l of c(1.60,-0.95) at record 14: {[float(ms['level_var'][l, 13, ip]) for l in range(6)]}; "
             f"max |Y_l| there over all records: "
