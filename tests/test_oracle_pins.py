@@ -382,7 +382,7 @@ def test_radical_inverse_values():
 
 
 def test_qmc_mean_agrees_with_mc(phys):
-    """E[Q] on 16x8 with 10 steps: a Halton rule (P:102 names QMC as the
+    """E[Q] on 16x8 with 10 steps: a Halton rule (the abstract names QMC as the
     paper's reference) and plain MC must agree within MC error."""
     n = 256
     hal = 2.0 * oracle.halton(n, 3) - 1.0
