@@ -518,6 +518,17 @@ def main():
                             V_Q=[float(v) for v in pr["V"]], alpha=pr["alpha"], beta=pr["beta"]))
         log(f"paper set-up, Table 3 counts (eps^2 = 1e-7): {pr['seconds']:.1f} s, {pr['nonconverged']} "
             f"non-converged, c(1.60,-0.95) by level {tel}, V at the point {vpt}")
+        # the paper's MLMC target, c at (1.60, -0.95) at T, by the adaptive driver on
+        # levels 0..3 at eps^2 = 1e-6 (Table 3's second row)
+        pa = hm.mlmc_run(pctx, plevels[:4], 1e-3, m_pilot=16, seed=hi.SEED, opts=popts, model="two_layer",
+                         point=(1.60, -0.95))
+        extras["paper_setup"]["mlmc_adaptive_point"] = dict(
+            workload="adaptive MLMC for E[c(1.60,-0.95)] at T, eps^2 = 1e-6, 16-sample pilots, levels 0..3",
+            m=[int(v) for v in pa["m"]], V=[float(v) for v in pa["V"]], seconds_per_sample=[float(v) for v in pa["s"]],
+            E=pa["EQ"], var_est=pa["var_est"], alpha=pa["alpha"], beta=pa["beta"], bias_estimate=pa["bias"],
+            final_batch_seconds=pa["seconds"], mse_within_eps2=pa["mse_ok"], nonconverged=pa["nonconverged"])
+        log(f"paper set-up, adaptive MLMC for c(1.60,-0.95), eps^2 1e-6: m = {list(pa['m'])}, "
+            f"E = {pa['EQ']:.5f}, V = {[float(v) for v in pa['V']]}, {pa['seconds']:.2f} s final batch")
         # Figs. 4-7: 600 QMC realisations of the time series on the coarsest grid
         from paper_2302_07804_amd.mlmc import POINTS12, QUANTILES
         g0 = hi.paper_level_grid(0)

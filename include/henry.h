@@ -292,7 +292,8 @@ int henry_solve_batch_trace(henry_ctx* ctx, const henry_grid_t* solves, int32_t 
  * nq <= 16 values in [0, 1]) q_out[k][v] = x_(lo) + (h - lo)(x_(lo+1) - x_(lo)),
  * h = (nsamples - 1) probs[k], lo = floor(h), x_(i) the i-th smallest
  * (Hyndman and Fan's type 7).  NaN sorts after every number and propagates
- * into the mean and variance.  1 <= nsamples <= 8192.  Outputs device,
+ * into the mean and variance.  1 <= nsamples, and nsamples <= 8192 when
+ * quantiles are asked for (nq > 0; they sort the samples in LDS).  Outputs device,
  * caller-owned.  Deterministic (fixed-order sums, a sort).  Errors:
  * HENRY_EINVAL. */
 int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, const double* x_sub,

@@ -1051,7 +1051,7 @@ int henry_level_smooth(henry_ctx* ctx, int32_t nx, int32_t ny, int32_t kind, int
 int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const double* x, const double* x_sub,
                        int32_t nq, const double* probs, double* mean_out, double* var_out, double* q_out,
                        void* stream) {
-    if (!ctx || nsamples < 1 || nsamples > henry::kMaxStatSamples || nvals < 0 || nq < 0 ||
+    if (!ctx || nsamples < 1 || (nq > 0 && nsamples > henry::kMaxStatSamples) || nvals < 0 || nq < 0 ||
         nq > henry::kMaxQuantiles || (nq > 0 && (!probs || !q_out)) || !x || !mean_out || !var_out)
         return HENRY_EINVAL;
     henry::Probs pr{};
@@ -1061,8 +1061,9 @@ int henry_sample_stats(henry_ctx* ctx, int32_t nsamples, int32_t nvals, const do
         pr.p[k] = probs[k];
     }
     if (nvals == 0) return HENRY_OK;
-    int P = 1;
-    while (P < nsamples) P <<= 1;
+    int P = 0;  // sort buffer, only for quantiles
+    if (nq > 0)
+        for (P = 1; P < nsamples;) P <<= 1;
     DeviceGuard dg(ctx->device);
     hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(henry::sample_stats_kernel, dim3(nvals), dim3(256), (size_t)P * sizeof(double), s0, x,

@@ -42,20 +42,26 @@ __global__ void __launch_bounds__(256) sample_stats_kernel(const double* x, cons
     extern __shared__ double buf[];
     __shared__ double red[4];
     const int v = blockIdx.x;
+    auto value = [&](int i) {
+        double a = x[(size_t)i * nvals + v];
+        if (x_sub) a -= x_sub[(size_t)i * nvals + v];
+        return a;
+    };
+    // P == 0 (no quantiles): no sort buffer, the samples are read twice
     double s = 0.0;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        double a = __builtin_nan("");
-        if (i < nsamples) {
-            a = x[(size_t)i * nvals + v];
-            if (x_sub) a -= x_sub[(size_t)i * nvals + v];
+    if (P > 0) {
+        for (int i = threadIdx.x; i < P; i += blockDim.x) {
+            const double a = i < nsamples ? value(i) : __builtin_nan("");
+            buf[i] = a;
+            if (i < nsamples) s += a;
         }
-        buf[i] = a;
-        if (i < nsamples) s += a;
+    } else {
+        for (int i = threadIdx.x; i < nsamples; i += blockDim.x) s += value(i);
     }
     const double mu = block_sum256(s, red) / nsamples;
     double d2 = 0.0;
     for (int i = threadIdx.x; i < nsamples; i += blockDim.x) {
-        const double d = buf[i] - mu;
+        const double d = (P > 0 ? buf[i] : value(i)) - mu;
         d2 += d * d;
     }
     const double s2 = block_sum256(d2, red);

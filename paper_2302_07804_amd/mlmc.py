@@ -67,9 +67,28 @@ def _level_statistics(ctx, levels, m, outs, with_var=False):
     return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y
 
 
+def _point_statistics(ctx, levels, m, outs):
+    """Level means and variances of c at the trace's one point at T: outs[l]
+    = (out, (f0, c0, c1)) with the fine solves f0..c0-1 and the coarse ones
+    c0..c1-1 of level l (henry_sample_stats on their difference)."""
+    import torch
+    mean, var = [], []
+    for l, (out, (f0, c0, c1)) in enumerate(outs):
+        fine = out["trace"][f0:c0, 0, 1:2].contiguous()
+        coarse = out["trace"][c0:c1, 0, 1:2].contiguous() if l > 0 else None
+        mu, v, _ = henry_sample_stats(ctx, fine, (), x_sub=coarse)
+        mean.append(mu)
+        var.append(v)
+    torch.cuda.synchronize(mean[0].device)
+    mean = np.array([float(t.item()) for t in mean])
+    var = np.array([float(t.item()) for t in var])
+    return mean, var, float((var / np.asarray(m, dtype=np.float64)).sum())
+
+
 def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0, opts: Opts | None = None,
-             max_samples: int | None = None, model: str | None = None):
-    """Adaptive MLMC estimate of E[Q] to root-mean-square error eps.
+             max_samples: int | None = None, model: str | None = None, point=None):
+    """Adaptive MLMC estimate of E[Q] (or, with point = (x, y), of c at that
+    point at T, the paper's own QoI of Table 3) to root-mean-square error eps.
 
     levels: fine grids (nx, ny, nsteps) of levels 0..L (nx = 2 ny, each
     twice the one before it); level l > 0 pairs grid l with grid l-1.
@@ -78,8 +97,11 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
     Returns a dict: EQ (sum of the level means), var_est (sum V_l / m_l),
     m, V, s (seconds per sample at each level, fine and coarse solve), the
     level means, alpha, beta, the bias estimate, mse_ok (var_est <= eps^2/2
-    and bias^2 <= eps^2/2), the final batch's seconds, E[c] on the finest
-    grid and the level mean fields of Y_l = c_l - c_{l-1} (device tensors)."""
+    and bias^2 <= eps^2/2), the final batch's seconds, and for E[Q] also
+    E[c] on the finest grid and the level mean fields of Y_l = c_l - c_{l-1}
+    (device tensors)."""
+    if point is not None:
+        return _mlmc_run_point(ctx, levels, eps, m_pilot, seed, opts, max_samples, model, point)
     import torch
     levels = [tuple(int(v) for v in g) for g in levels]
     L = len(levels) - 1
@@ -109,6 +131,50 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
     res.update(V_pilot=V, s=np.array(s), planned_cost=cost,
                mse_ok=bool(res["var_est"] <= half * (1 + 1e-12) and (L < 2 or res["bias"] ** 2 <= half)))
     return res
+
+
+def _mlmc_run_point(ctx, levels, eps, m_pilot, seed, opts, max_samples, model, point):
+    """mlmc_run for c at a point at T: every solve records one time-series
+    record (the final state) at the point."""
+    import torch
+    levels = [tuple(int(v) for v in g) for g in levels]
+    L = len(levels) - 1
+    if L < 0 or m_pilot < 2:
+        raise ValueError("need at least one level and a pilot of at least two samples")
+    dev = torch.device("cuda", ctx.device)
+    trace = (1, [tuple(point)])
+    pilot, s = [], []
+    for l in range(L + 1):
+        sol, xi, rng = _pairs(levels[:l + 1], [0] * l + [m_pilot], seed)
+        xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        out = solve(ctx, sol, xi=xi_d, opts=opts, model=model, trace=trace)
+        torch.cuda.synchronize(dev)
+        s.append((time.perf_counter() - t0) / m_pilot)
+        pilot.append((out, rng[l]))
+    _, V, _ = _point_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
+    m, cost = henry_mlmc_allocate(V, np.array(s), eps * eps / 2)
+    m = np.maximum(m, m_pilot)
+    if max_samples is not None:
+        m = np.minimum(m, max_samples)
+    sol, xi, rng = _pairs(levels, m, seed)
+    xi_d = torch.tensor(xi, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    out = solve(ctx, sol, xi=xi_d, opts=opts, model=model, trace=trace)
+    torch.cuda.synchronize(dev)
+    seconds = time.perf_counter() - t0
+    status = out["status"].cpu().numpy()
+    mean, var, var_est = _point_statistics(ctx, levels, m, [(out, r) for r in rng])
+    alpha = beta = bias = float("nan")
+    if L >= 2:
+        alpha, beta, bias = henry_mlmc_rates(mean, var, 1)
+    half = eps * eps / 2
+    return dict(EQ=float(mean.sum()), var_est=var_est, m=m, V=var, V_pilot=V, s=np.array(s), mean=mean,
+                alpha=alpha, beta=beta, bias=bias, planned_cost=cost, seconds=seconds,
+                nonconverged=int((status != 0).sum()),
+                mse_ok=bool(var_est <= half * (1 + 1e-12) and (L < 2 or bias * bias <= half)))
 
 
 def mlmc_fixed(ctx: Context, levels, m, seed: int = 0, opts: Opts | None = None, model: str | None = None):

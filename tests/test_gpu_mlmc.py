@@ -107,3 +107,35 @@ def test_telescoped_sum_of_all_levels_is_the_finest_mean(torch_cuda):
     for x, y in ((1.60, -0.95), (0.30, -0.20), (1.97, -0.61)):
         tel = hm.telescoped_at(levels, res["mean_Y"], x, y)
         assert tel[-1] == pytest.approx(Ec[hm.point_cell(levels[-1], x, y)], rel=1e-12, abs=1e-15)
+
+
+def test_adaptive_mlmc_for_c_at_a_point_matches_oracle(torch_cuda):
+    """The paper's QoI of Table 3, c at (1.60, -0.95) at T, as the target of
+    the adaptive driver: eq:M_ell on the pilot's variances and costs, and
+    the estimate and variance against oracle solves of the same samples."""
+    levels = [(16, 8, 50), (32, 16, 100), (64, 32, 200)]
+    eps, m_pilot, seed = 0.02, 8, 6
+    ctx = hm.Context(hi.PHYS, 0)
+    res = hm.mlmc_run(ctx, levels, eps, m_pilot=m_pilot, seed=seed, point=(1.60, -0.95),
+                      opts=hm.make_opts(prec=hm.PREC_FP64, tol=1e-10, max_outer=60))
+    ctx.close()
+    assert res["nonconverged"] == 0
+    m = res["m"]
+    mo, _ = oracle.optimal_samples(res["V_pilot"], res["s"], eps * eps / 2)
+    assert np.array_equal(m, np.maximum(mo, m_pilot)), (m, mo)
+    means, vars_ = [], []
+    for l, ml in enumerate(m):
+        xi = oracle.sample_xi(seed, l, 0, int(ml), 3)
+        fine = oracle.solve_many(hi.PHYS, [(*levels[l], x) for x in xi])
+        f = np.array([oracle.point_value(r["c"], 1.60, -0.95) for r in fine])
+        g = None
+        if l > 0:
+            coarse = oracle.solve_many(hi.PHYS, [(*levels[l - 1], x) for x in xi])
+            g = np.array([oracle.point_value(r["c"], 1.60, -0.95) for r in coarse])
+        mu, v = oracle.level_stats(f, g)
+        means.append(float(mu)); vars_.append(float(v))
+    EQ, var_est = oracle.mlmc_estimate(means, vars_, list(m))
+    print(f"m = {list(m)}, E[c] = {res['EQ']:.6f} (oracle {EQ:.6f})")
+    assert res["EQ"] == pytest.approx(EQ, abs=1e-8)
+    np.testing.assert_allclose(res["mean"], means, rtol=0, atol=1e-8)
+    assert res["var_est"] == pytest.approx(var_est, rel=1e-6, abs=1e-14)

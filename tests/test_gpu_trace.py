@@ -142,6 +142,13 @@ def test_sample_stats_match_oracle(torch_cuda):
     assert q[0, 1] == np.nanmin(x[:, 1])
     with pytest.raises(hm.HenryError):
         hm.henry_sample_stats(ctx, dev(torch, np.zeros((8193, 1))), [0.5])
+    # without quantiles there is no sort and no limit on the sample count
+    x = rng.normal(size=(50000, 3))
+    y = rng.normal(size=(50000, 3))
+    mean, var, _ = hm.henry_sample_stats(ctx, dev(torch, x).view(50000, 3), (), x_sub=dev(torch, y).view(50000, 3))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(mean.cpu().numpy(), (x - y).mean(axis=0), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(var.cpu().numpy(), (x - y).var(axis=0, ddof=1), rtol=1e-12)
     with pytest.raises(hm.HenryError):
         hm.henry_sample_stats(ctx, dev(torch, np.zeros((4, 1))), [1.5])
     ctx.close()
