@@ -81,3 +81,25 @@ def test_planning_rejects_bad_arguments(L):
         hm.henry_mlmc_rates([1.0, 0.5], [1.0, 0.5], 1)  # one level in the fit
     with pytest.raises(hm.HenryError):
         hm.henry_mlmc_rates([1.0, 0.5, 0.0], [1.0, 0.5, 0.2], 1)  # zero mean in the fit
+
+
+def test_allocation_meets_the_variance_target_at_near_optimal_cost(L):
+    """eq:M_ell is the minimiser of the cost sum m_l s_l subject to the
+    estimator variance sum V_l / m_l = eps^2: rounded up, the counts meet
+    the target and cost at most one sample per level more than the
+    continuous optimum, and every randomly perturbed integer allocation
+    that still meets the target costs at least that optimum."""
+    rng = np.random.default_rng(12)
+    for _ in range(200):
+        n = int(rng.integers(1, 7))
+        V = 10.0 ** rng.uniform(-9, -3, n)
+        s = 10.0 ** rng.uniform(-2, 3, n)
+        eps2 = 10.0 ** rng.uniform(-9, -5)
+        m, cost = hm.henry_mlmc_allocate(V, s, eps2)
+        assert (V / m).sum() <= eps2 * (1 + 1e-12)
+        assert cost <= (m * s).sum() <= cost + s.sum() * (1 + 1e-12)
+        # any other integer allocation that meets the target costs at least the continuous optimum
+        for _ in range(5):
+            mm = np.maximum(1, np.round(m * 10.0 ** rng.uniform(-0.3, 0.3, n))).astype(np.int64)
+            if (V / mm).sum() <= eps2:
+                assert (mm * s).sum() >= cost * (1 - 1e-12)
