@@ -97,3 +97,20 @@ def test_adjoint_gradient_against_central_differences():
         qp = oracle.solve_xi(PH, nx, ny, r, xi + e, model="two_layer")["qoi"]
         qm = oracle.solve_xi(PH, nx, ny, r, xi - e, model="two_layer")["qoi"]
         assert g[k] == pytest.approx((qp - qm) / 2e-5, rel=1e-5), k
+
+
+def test_paper_hierarchy_matches_table2():
+    """The paper's hierarchy (henry_inputs.paper_level_grid with T = 6016 s)
+    against Table 2: level l has 32 2^l x 16 2^l cells, i.e. the paper's
+    quadrilaterals, whose (nx + 1)(ny + 1) vertices carry two unknowns each
+    (n_l), r_l steps and tau_l = T / r_l."""
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    rows = [l.split() for l in open(os.path.join(root, "tests", "golden", "table2_hierarchy.txt"))
+            if not l.startswith("#")]
+    for lev, n, r, tau, _ in rows:
+        nx, ny, steps = hi.paper_level_grid(int(lev))
+        assert 2 * (nx + 1) * (ny + 1) == int(n)
+        assert steps == int(r)
+        assert PH["T"] / steps == float(tau)
+    assert PH["T"] == 6016.0
