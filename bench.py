@@ -476,6 +476,8 @@ def main():
                      f"{ref_grid[0]}x{ref_grid[1]}/{ref_grid[2]}; MLMC: the timed batch, truncated after each level",
             seconds=qr["seconds"], nonconverged=qr["nonconverged"],
             qmc_EQ=qr["EQ"], qmc_EQ_se=qr["se"], qmc_c_point=Ec_ref,
+            qmc_c_mean_range=[float(qr["Ec"].min().item()), float(qr["Ec"].max().item())],
+            qmc_c_var_max=float(qr["Varc"].max().item()), qmc_c_var_mean=float(qr["Varc"].mean().item()),
             qmc_c_point_se=float(c_shift.std(ddof=1) / np.sqrt(nsh)) if nsh > 1 else None,
             mlmc_c_point_by_level=[float(v) for v in tel_c], mlmc_EQ_by_level=[float(v) for v in tel_q],
             mlmc_c_point_se_by_level=[float(v) for v in se_c], mlmc_EQ_se_by_level=[float(v) for v in se_q],

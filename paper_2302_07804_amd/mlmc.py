@@ -231,8 +231,9 @@ def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts 
     solves in one batch.  Returns a dict: EQ (mean over all points),
     EQ_shift (the R rule means), se (their standard deviation over sqrt(R),
     the usual error estimate of a randomly shifted rule; nan for R = 1), Ec
-    (mean field) and Ec_shift (each rule's mean field; device tensors),
-    seconds (the batch), nonconverged."""
+    (mean field), Ec_shift (each rule's mean field) and Varc (the sample
+    variance of c per cell over all points; device tensors), seconds (the
+    batch), nonconverged."""
     import torch
     grid = tuple(int(v) for v in grid)
     if n < 2:
@@ -250,7 +251,8 @@ def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts 
     seconds = time.perf_counter() - t0
     status = out["status"].cpu().numpy()
     cells = grid[0] * grid[1]
-    mean, _, _, Ec, _ = _level_statistics(ctx, [grid], [R * n], [(sol, out, (0, R * n, R * n))])
+    mean, _, _, Ec, _, var_Y = _level_statistics(ctx, [grid], [R * n], [(sol, out, (0, R * n, R * n))],
+                                                 with_var=True)
     per, Ec_shift = [], []
     for r in range(R):
         sl = dict(c=out["c"][r * n * cells:(r + 1) * n * cells], qoi=out["qoi"][r * n:(r + 1) * n])
@@ -259,7 +261,7 @@ def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts 
         Ec_shift.append(Er)
     per = np.array(per)
     se = float(per.std(ddof=1) / np.sqrt(R)) if R > 1 else float("nan")
-    return dict(EQ=float(mean[0]), EQ_shift=per, se=se, Ec=Ec, Ec_shift=Ec_shift, seconds=seconds,
+    return dict(EQ=float(mean[0]), EQ_shift=per, se=se, Ec=Ec, Ec_shift=Ec_shift, Varc=var_Y[0], seconds=seconds,
                 nonconverged=int((status != 0).sum()))
 
 

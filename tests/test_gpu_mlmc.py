@@ -81,6 +81,7 @@ def test_qmc_reference_matches_oracle(torch_cuda):
     ctx = hm.Context(hi.PHYS, 0)
     res = hm.qmc_run(ctx, grid, n, shifts=shifts, opts=hm.make_opts(prec=hm.PREC_FP64, tol=1e-10, max_outer=60))
     Ec = res["Ec"].cpu().numpy()
+    Varc = res["Varc"].cpu().numpy()
     ctx.close()
     assert res["nonconverged"] == 0
     jobs = [(*grid, x) for sh in shifts for x in oracle.qmc_xi(n, 3, 1, sh)]
@@ -92,6 +93,7 @@ def test_qmc_reference_matches_oracle(torch_cuda):
     assert res["se"] == pytest.approx(q.reshape(len(shifts), n).mean(axis=1).std(ddof=1) / np.sqrt(len(shifts)),
                                       rel=1e-5)
     np.testing.assert_allclose(Ec, c.mean(axis=0), rtol=0, atol=1e-9)
+    np.testing.assert_allclose(Varc, c.var(axis=0, ddof=1), rtol=1e-6, atol=1e-12)
     print(f"QMC E[Q] = {res['EQ']:.8f} +- {res['se']:.2e}")
 
 
