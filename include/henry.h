@@ -417,6 +417,29 @@ int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, con
                         double* const* mean_Y, double* const* var_Y, double* qstats, double* Ec_finest,
                         double* var_est, void* stream);
 
+/* Partial sums of the telescoping MLMC estimator (Sec. 3, eq:A: the
+ * estimate of E[g_L] is the sum over levels of the sample means of
+ * Y_l = g_l - g_{l-1}) and of its variance sum_l V_l / m_l (the variance
+ * half of eq:MSE), for nvals quantities at once, FP64 on the device in a
+ * fixed order:
+ *   pmean_out[l][v] = sum_{i <= l} mean[i][off[i] + v]
+ *   pvar_out[l][v]  = sum_{i <= l} var[i][off[i] + v] / m[i]
+ * Row nlevels-1 is the estimate and its variance; row l is the estimate
+ * truncated after level l (the partial sums Fig. 11 compares with its
+ * reference).
+ *   mean, var  host arrays [nlevels] of device pointers to level means and
+ *              unbiased variances (henry_sample_stats, mlmc_level_estimate);
+ *              var may be NULL, then pvar_out is not written (may be NULL)
+ *   m          host [nlevels] sample counts, m[l] >= 1
+ *   off        host [nlevels] element offsets into each level's arrays
+ *              (e.g. the cell that holds a point on level l's grid), or NULL
+ *   pmean_out, pvar_out  device [nlevels][nvals], caller-owned
+ * 1 <= nlevels <= 16, nvals >= 0.  Errors: HENRY_EINVAL (NULL pointer,
+ * counts or offsets out of range), HENRY_EHIP. */
+int henry_mlmc_telescope(henry_ctx* ctx, int32_t nlevels, int32_t nvals, const double* const* mean,
+                         const double* const* var, const int32_t* m, const int64_t* off, double* pmean_out,
+                         double* pvar_out, void* stream);
+
 /* Sample allocation of an MLMC run (Sec. 3, eq:M_ell): with per-level
  * variances V[l] of Y_l = g_l - g_{l-1} and costs s[l] > 0 per sample
  * (any unit), the counts that minimise sum m_l s_l at estimator variance

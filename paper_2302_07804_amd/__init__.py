@@ -29,7 +29,7 @@ EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opt
            "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
            "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch", "henry_mlmc_allocate",
            "henry_mlmc_rates", "henry_qmc_points", "henry_solve_batch_trace", "henry_sample_stats",
-           "henry_first_passage", "henry_level_smooth")
+           "henry_first_passage", "henry_level_smooth", "henry_mlmc_telescope")
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -130,6 +130,8 @@ def lib():
     L.henry_sample_xi_kl.argtypes = [ct.c_uint64, i32, i64, i64, ct.POINTER(ct.c_double)]
     L.mlmc_level_estimate.argtypes = [vp, i32, ct.POINTER(Grid), ct.POINTER(i32), ct.POINTER(vp), ct.POINTER(vp),
                                       ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(vp), vp, vp, vp, vp]
+    L.henry_mlmc_telescope.argtypes = [vp, i32, i32, ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(i32),
+                                       ct.POINTER(i64), vp, vp, vp]
     _lib = L
     return L
 
@@ -242,10 +244,57 @@ def _ptr(t):
     return None if t is None else ct.c_void_p(t.data_ptr())
 
 
+def _need(t, n, dtype, what, device=None, optional=False):
+    """Check a caller's tensor before its pointer crosses the ABI: at least
+    n elements of `dtype`, contiguous, on the context's GPU.  The library
+    sees only the pointer, so a short buffer would be written past its end."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{what} is required")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, not {t.dtype}")
+    if not t.is_cuda or (device is not None and t.device.index != device):
+        raise ValueError(f"{what} must be on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{what} has {t.numel()} elements, needs {n}")
+
+
+def _f64t():
+    import torch
+    return torch.float64
+
+
+def _i32t():
+    import torch
+    return torch.int32
+
+
 def _stream_of(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ct.c_void_p(s.cuda_stream)
+
+
+def _check_solve_args(ctx, solves, field, xi, phi, logk, qin, c0, c_out, p_out, qoi_out, status, iters):
+    n = len(solves)
+    cells = sum(int(s[0]) * int(s[1]) for s in solves)
+    f64, i32, d = _f64t(), _i32t(), ctx.device
+    if field in (FIELD_CLOSED3, FIELD_TWOLAYER3, FIELD_KL41):
+        _need(xi, n * (41 if field == FIELD_KL41 else 3), f64, "xi", d)
+    elif field == FIELD_EXPLICIT:
+        _need(phi, cells, f64, "phi", d)
+        _need(logk, cells, f64, "logk", d)
+        _need(qin, n, f64, "qin", d)
+    _need(c0, cells, f64, "c0", d, optional=True)
+    _need(c_out, cells, f64, "c_out", d)
+    _need(p_out, cells, f64, "p_out", d, optional=True)
+    _need(qoi_out, n, f64, "qoi_out", d)
+    _need(status, n, i32, "status", d)
+    _need(iters, n, i32, "iters", d, optional=True)
 
 
 def henry_solve_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, c0=None,
@@ -253,6 +302,7 @@ def henry_solve_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None,
                       workspace=None, stream=None):
     """Thin wrapper: tensors are device tensors owned by the caller."""
     g = grids(solves)
+    _check_solve_args(ctx, solves, field, xi, phi, logk, qin, c0, c_out, p_out, qoi_out, status, iters)
     rc = lib().henry_solve_batch(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk), _ptr(qin),
                                  _ptr(c0), ct.byref(opts) if opts else None, _ptr(c_out), _ptr(p_out),
                                  _ptr(qoi_out), _ptr(status), _ptr(iters), _ptr(workspace),
@@ -268,7 +318,9 @@ def henry_solve_batch_trace(ctx: Context, solves, field, xi=None, phi=None, logk
     is a host sequence of (x, y)."""
     import numpy as np
     g = grids(solves)
+    _check_solve_args(ctx, solves, field, xi, phi, logk, qin, c0, c_out, p_out, qoi_out, status, iters)
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 2))
+    _need(trace_out, len(solves) * int(nrec) * (1 + len(pts)), _f64t(), "trace_out", ctx.device)
     rc = lib().henry_solve_batch_trace(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk),
                                        _ptr(qin), _ptr(c0), ct.byref(opts) if opts else None, int(nrec), len(pts),
                                        pts.ctypes.data_as(ct.POINTER(ct.c_double)), float(c_fresh), _ptr(trace_out),
@@ -390,6 +442,19 @@ def mlmc_level_estimate(ctx: Context, fine_grids, m, c_fine, c_coarse, q_fine, q
                         Ec_finest, var_est, stream=None):
     L = len(fine_grids) - 1
     g = grids(fine_grids)
+    f64, d = _f64t(), ctx.device
+    for l, fg in enumerate(fine_grids):
+        cells, ml = int(fg[0]) * int(fg[1]), int(m[l])
+        _need(c_fine[l], ml * cells, f64, f"c_fine[{l}]", d)
+        _need(q_fine[l], ml, f64, f"q_fine[{l}]", d)
+        if l > 0:
+            _need(c_coarse[l], ml * cells // 4, f64, f"c_coarse[{l}]", d)
+            _need(q_coarse[l], ml, f64, f"q_coarse[{l}]", d)
+        _need(mean_Y[l], cells, f64, f"mean_Y[{l}]", d)
+        _need(var_Y[l], cells, f64, f"var_Y[{l}]", d)
+    _need(qstats, 2 * (L + 1), f64, "qstats", d)
+    _need(Ec_finest, int(fine_grids[-1][0]) * int(fine_grids[-1][1]), f64, "Ec_finest", d)
+    _need(var_est, 2, f64, "var_est", d)
     mm = (ct.c_int32 * (L + 1))(*[int(x) for x in m])
     P = ct.c_void_p * (L + 1)
     arr = lambda ts: P(*[(t.data_ptr() if t is not None else None) for t in ts])
@@ -397,6 +462,50 @@ def mlmc_level_estimate(ctx: Context, fine_grids, m, c_fine, c_coarse, q_fine, q
                                    arr(mean_Y), arr(var_Y), _ptr(qstats), _ptr(Ec_finest), _ptr(var_est),
                                    _stream_of(stream))
     _chk(rc, "mlmc_level_estimate")
+
+
+def henry_mlmc_telescope(ctx: Context, means, vars_=None, m=None, offsets=None, nvals=None, stream=None):
+    """Partial sums over levels 0..l of the level means (eq:A) and of
+    V_l / m_l, for every l: returns device tensors (pmean [L+1][nvals],
+    pvar [L+1][nvals] or None).  means / vars_: per-level device tensors;
+    offsets: per-level element offsets (e.g. the cell of a point)."""
+    import numpy as np
+    import torch
+    nl = len(means)
+    off = [0] * nl if offsets is None else [int(o) for o in offsets]
+    if nvals is None:
+        nvals = min(int(t.numel()) - o for t, o in zip(means, off))
+    f64, d = _f64t(), ctx.device
+    for l in range(nl):
+        _need(means[l], off[l] + nvals, f64, f"means[{l}]", d)
+        if vars_ is not None:
+            _need(vars_[l], off[l] + nvals, f64, f"vars[{l}]", d)
+    mm = np.ones(nl, np.int32) if m is None else np.ascontiguousarray(m, dtype=np.int32)
+    if len(mm) != nl:
+        raise ValueError("one sample count per level")
+    P = ct.c_void_p * nl
+    dev = torch.device("cuda", ctx.device)
+    pm = torch.empty((nl, nvals), dtype=torch.float64, device=dev)
+    pv = torch.empty((nl, nvals), dtype=torch.float64, device=dev) if vars_ is not None else None
+    offs = np.ascontiguousarray(off, dtype=np.int64)
+    rc = lib().henry_mlmc_telescope(ctx.handle, nl, int(nvals), P(*[t.data_ptr() for t in means]),
+                                    P(*[t.data_ptr() for t in vars_]) if vars_ is not None else None,
+                                    mm.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                    offs.ctypes.data_as(ct.POINTER(ct.c_int64)), _ptr(pm), _ptr(pv),
+                                    _stream_of(stream))
+    _chk(rc, "henry_mlmc_telescope")
+    return pm, pv
+
+
+def telescoped_q(ctx: Context, qstats, m=None):
+    """E[Q] truncated after each level from mlmc_level_estimate's qstats
+    ([L+1][2]: mean, variance of Q_l - Q_{l-1}), summed on the device, and
+    sum V_l / m_l likewise when m is given; host arrays."""
+    L1 = int(qstats.numel()) // 2
+    means = [qstats[2 * l:2 * l + 1] for l in range(L1)]
+    vars_ = [qstats[2 * l + 1:2 * l + 2] for l in range(L1)] if m is not None else None
+    pm, pv = henry_mlmc_telescope(ctx, means, vars_, m, nvals=1)
+    return pm[:, 0].cpu().numpy(), (pv[:, 0].cpu().numpy() if pv is not None else None)
 
 
 # ------------------------------------------------------------------ convenience layer
@@ -478,6 +587,23 @@ def henry_adjoint_batch(ctx: Context, solves, field, xi=None, phi=None, logk=Non
                         workspace=None, stream=None):
     """Thin wrapper: tensors are device tensors owned by the caller."""
     g = grids(solves)
+    n = len(solves)
+    cells = sum(int(s[0]) * int(s[1]) for s in solves)
+    f64, d = _f64t(), ctx.device
+    if field in (FIELD_CLOSED3, FIELD_TWOLAYER3, FIELD_KL41):
+        dim = 41 if field == FIELD_KL41 else 3
+        _need(xi, n * dim, f64, "xi", d)
+        _need(dq_dxi, n * dim, f64, "dq_dxi", d, optional=True)
+    elif field == FIELD_EXPLICIT:
+        _need(phi, cells, f64, "phi", d)
+        _need(logk, cells, f64, "logk", d)
+        _need(qin, n, f64, "qin", d)
+    _need(qoi_out, n, f64, "qoi_out", d)
+    _need(dq_dlogk, cells, f64, "dq_dlogk", d, optional=True)
+    _need(dq_dphi, cells, f64, "dq_dphi", d, optional=True)
+    _need(dq_dq, n, f64, "dq_dq", d, optional=True)
+    _need(status, n, _i32t(), "status", d)
+    _need(iters, n, _i32t(), "iters", d, optional=True)
     rc = lib().henry_adjoint_batch(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk), _ptr(qin),
                                    ct.byref(opts) if opts else None, int(ckpt_every), float(adj_tol),
                                    int(adj_max_it), _ptr(qoi_out), _ptr(dq_dxi), _ptr(dq_dlogk), _ptr(dq_dphi),
@@ -485,6 +611,11 @@ def henry_adjoint_batch(ctx: Context, solves, field, xi=None, phi=None, logk=Non
                                    workspace.numel() * workspace.element_size() if workspace is not None else 0,
                                    _stream_of(stream))
     _chk(rc, "henry_adjoint_batch")
+
+
+def aligned_workspace(nbytes, dev):
+    """A 256-byte aligned float64 device view of at least nbytes bytes."""
+    return _aligned_workspace(nbytes, dev)
 
 
 def _aligned_workspace(nbytes, dev):

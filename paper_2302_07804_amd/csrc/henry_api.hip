@@ -1026,6 +1026,29 @@ int mlmc_level_estimate(henry_ctx* ctx, int32_t L, const henry_grid_t* fine, con
     return HENRY_OK;
 }
 
+int henry_mlmc_telescope(henry_ctx* ctx, int32_t nlevels, int32_t nvals, const double* const* mean,
+                         const double* const* var, const int32_t* m, const int64_t* off, double* pmean_out,
+                         double* pvar_out, void* stream) {
+    if (!ctx || nlevels < 1 || nlevels > henry::kMaxTelescopeLevels || nvals < 0 || !mean || !m || !pmean_out ||
+        (var && !pvar_out))
+        return HENRY_EINVAL;
+    henry::TelescopePtrs tp{};
+    for (int l = 0; l < nlevels; ++l) {
+        if (!mean[l] || m[l] < 1 || (var && !var[l]) || (off && off[l] < 0)) return HENRY_EINVAL;
+        tp.mean[l] = mean[l];
+        tp.var[l] = var ? var[l] : nullptr;
+        tp.off[l] = off ? off[l] : 0;
+        tp.m[l] = (double)m[l];
+    }
+    if (nvals == 0) return HENRY_OK;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(henry::mlmc_telescope_kernel, dim3((nvals + 255) / 256), dim3(256), 0, s0, tp, nlevels,
+                       nvals, pmean_out, pvar_out);
+    if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    return HENRY_OK;
+}
+
 int henry_level_smooth(henry_ctx* ctx, int32_t nx, int32_t ny, int32_t kind, int32_t prec, int32_t sweeps,
                        const double* coef, const double* b, double* x, void* workspace, size_t ws_bytes,
                        void* stream) {

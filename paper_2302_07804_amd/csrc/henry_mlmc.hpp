@@ -104,4 +104,28 @@ __global__ void mlmc_combine_kernel(LevelPtrs lp, int L, int nxL, int nyL, const
     }
 }
 
+// Partial sums of the telescoping estimator and of its variance over levels
+// 0..l for every l (fixed order, FP64): one thread per quantity.
+constexpr int kMaxTelescopeLevels = 16;
+struct TelescopePtrs {
+    const double* mean[kMaxTelescopeLevels];
+    const double* var[kMaxTelescopeLevels];
+    long long off[kMaxTelescopeLevels];
+    double m[kMaxTelescopeLevels];
+};
+
+__global__ void mlmc_telescope_kernel(TelescopePtrs tp, int nlevels, int nvals, double* pmean, double* pvar) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvals) return;
+    double e = 0.0, w = 0.0;
+    for (int l = 0; l < nlevels; ++l) {
+        e += tp.mean[l][tp.off[l] + v];
+        pmean[(size_t)l * nvals + v] = e;
+        if (tp.var[0]) {
+            w += tp.var[l][tp.off[l] + v] / tp.m[l];
+            pvar[(size_t)l * nvals + v] = w;
+        }
+    }
+}
+
 }  // namespace henry

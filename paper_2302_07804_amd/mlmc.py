@@ -11,8 +11,11 @@ the spread of the shifts; MLMC estimates truncated after each level are
 compared with it at a point.
 
 Orchestration only: the solves (henry_solve_batch), the level statistics
-(mlmc_level_estimate), the points (henry_qmc_points) and the planning
-arithmetic (henry_mlmc_allocate, henry_mlmc_rates) are calls into libhenry."""
+(mlmc_level_estimate, henry_sample_stats), the estimator sums over levels
+(henry_mlmc_telescope, FP64 on the device), the points (henry_qmc_points)
+and the planning arithmetic (henry_mlmc_allocate, henry_mlmc_rates) are
+calls into libhenry; this module copies results to the host, it does not
+add them up."""
 from __future__ import annotations
 
 import time
@@ -20,7 +23,8 @@ import time
 import numpy as np
 
 from . import (FIELD_CLOSED3, Context, Opts, henry_first_passage, henry_mlmc_allocate, henry_mlmc_rates,
-               henry_qmc_points, henry_sample_stats, henry_sample_xi, mlmc_level_estimate, solve)
+               henry_mlmc_telescope, henry_qmc_points, henry_sample_stats, henry_sample_xi, mlmc_level_estimate,
+               solve, telescoped_q)
 
 
 def _pairs(levels, m, seed):
@@ -60,17 +64,20 @@ def _level_statistics(ctx, levels, m, outs, with_var=False):
     Ec = torch.empty(levels[-1][0] * levels[-1][1], dtype=torch.float64, device=dev)
     var_est = torch.empty(2, dtype=torch.float64, device=dev)
     mlmc_level_estimate(ctx, levels, m, c_fine, c_coarse, q_fine, q_coarse, mean_Y, var_Y, qstats, Ec, var_est)
+    EQ, _ = telescoped_q(ctx, qstats)
     torch.cuda.synchronize(dev)
     qs = qstats.cpu().numpy().reshape(L + 1, 2)
     if with_var:
-        return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y, var_Y
-    return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y
+        return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y, var_Y, float(EQ[-1])
+    return qs[:, 0].copy(), qs[:, 1].copy(), float(var_est[0].item()), Ec, mean_Y, float(EQ[-1])
 
 
 def _point_statistics(ctx, levels, m, outs):
     """Level means and variances of c at the trace's one point at T: outs[l]
     = (out, (f0, c0, c1)) with the fine solves f0..c0-1 and the coarse ones
-    c0..c1-1 of level l (henry_sample_stats on their difference)."""
+    c0..c1-1 of level l (henry_sample_stats on their difference).  Returns
+    the host copies of the level means and variances, and the telescoped
+    estimate and sum V_l / m_l (henry_mlmc_telescope)."""
     import torch
     mean, var = [], []
     for l, (out, (f0, c0, c1)) in enumerate(outs):
@@ -79,10 +86,12 @@ def _point_statistics(ctx, levels, m, outs):
         mu, v, _ = henry_sample_stats(ctx, fine, (), x_sub=coarse)
         mean.append(mu)
         var.append(v)
+    pm, pv = henry_mlmc_telescope(ctx, mean, var, m, nvals=1)
     torch.cuda.synchronize(mean[0].device)
+    est, var_est = float(pm[-1, 0].item()), float(pv[-1, 0].item())
     mean = np.array([float(t.item()) for t in mean])
     var = np.array([float(t.item()) for t in var])
-    return mean, var, float((var / np.asarray(m, dtype=np.float64)).sum())
+    return mean, var, est, var_est
 
 
 def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0, opts: Opts | None = None,
@@ -119,7 +128,7 @@ def mlmc_run(ctx: Context, levels, eps: float, m_pilot: int = 32, seed: int = 0,
         torch.cuda.synchronize(dev)
         s.append((time.perf_counter() - t0) / m_pilot)
         pilot.append((sol, out, rng[l]))
-    mean_p, V, _, _, _ = _level_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
+    mean_p, V, _, _, _, _ = _level_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
     # ---- allocation (eq:M_ell) for the variance half of the MSE (eq:MSE)
     m, cost = henry_mlmc_allocate(V, np.array(s), eps * eps / 2)
     m = np.maximum(m, m_pilot)
@@ -153,7 +162,7 @@ def _mlmc_run_point(ctx, levels, eps, m_pilot, seed, opts, max_samples, model, p
         torch.cuda.synchronize(dev)
         s.append((time.perf_counter() - t0) / m_pilot)
         pilot.append((out, rng[l]))
-    _, V, _ = _point_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
+    _, V, _, _ = _point_statistics(ctx, levels, [m_pilot] * (L + 1), pilot)
     m, cost = henry_mlmc_allocate(V, np.array(s), eps * eps / 2)
     m = np.maximum(m, m_pilot)
     if max_samples is not None:
@@ -166,12 +175,12 @@ def _mlmc_run_point(ctx, levels, eps, m_pilot, seed, opts, max_samples, model, p
     torch.cuda.synchronize(dev)
     seconds = time.perf_counter() - t0
     status = out["status"].cpu().numpy()
-    mean, var, var_est = _point_statistics(ctx, levels, m, [(out, r) for r in rng])
+    mean, var, est, var_est = _point_statistics(ctx, levels, m, [(out, r) for r in rng])
     alpha = beta = bias = float("nan")
     if L >= 2:
         alpha, beta, bias = henry_mlmc_rates(mean, var, 1)
     half = eps * eps / 2
-    return dict(EQ=float(mean.sum()), var_est=var_est, m=m, V=var, V_pilot=V, s=np.array(s), mean=mean,
+    return dict(EQ=est, var_est=var_est, m=m, V=var, V_pilot=V, s=np.array(s), mean=mean,
                 alpha=alpha, beta=beta, bias=bias, planned_cost=cost, seconds=seconds,
                 nonconverged=int((status != 0).sum()),
                 mse_ok=bool(var_est <= half * (1 + 1e-12) and (L < 2 or bias * bias <= half)))
@@ -199,12 +208,12 @@ def mlmc_fixed(ctx: Context, levels, m, seed: int = 0, opts: Opts | None = None,
     torch.cuda.synchronize(dev)
     seconds = time.perf_counter() - t0
     status = out["status"].cpu().numpy()
-    mean, var, var_est, Ec, mean_Y, var_Y = _level_statistics(ctx, levels, m, [(sol, out, r) for r in rng],
-                                                              with_var=True)
+    mean, var, var_est, Ec, mean_Y, var_Y, EQ = _level_statistics(ctx, levels, m, [(sol, out, r) for r in rng],
+                                                                  with_var=True)
     alpha = beta = bias = float("nan")
     if L >= 2:
         alpha, beta, bias = henry_mlmc_rates(mean, var, 1)
-    return dict(EQ=float(mean.sum()), var_est=var_est, m=m, V=var, mean=mean, alpha=alpha, beta=beta, bias=bias,
+    return dict(EQ=EQ, var_est=var_est, m=m, V=var, mean=mean, alpha=alpha, beta=beta, bias=bias,
                 seconds=seconds, nonconverged=int((status != 0).sum()), Ec=Ec, mean_Y=mean_Y, var_Y=var_Y)
 
 
@@ -251,28 +260,33 @@ def qmc_run(ctx: Context, grid, n: int, shifts=None, first: int = 1, opts: Opts 
     seconds = time.perf_counter() - t0
     status = out["status"].cpu().numpy()
     cells = grid[0] * grid[1]
-    mean, _, _, Ec, _, var_Y = _level_statistics(ctx, [grid], [R * n], [(sol, out, (0, R * n, R * n))],
-                                                 with_var=True)
-    per, Ec_shift = [], []
+    mean, _, _, Ec, _, var_Y, _ = _level_statistics(ctx, [grid], [R * n], [(sol, out, (0, R * n, R * n))],
+                                                    with_var=True)
+    Ec_shift = []
     for r in range(R):
         sl = dict(c=out["c"][r * n * cells:(r + 1) * n * cells], qoi=out["qoi"][r * n:(r + 1) * n])
-        mr, _, _, Er, _ = _level_statistics(ctx, [grid], [n], [(sol[:n], sl, (0, n, n))])
-        per.append(float(mr[0]))
+        _, _, _, Er, _, _ = _level_statistics(ctx, [grid], [n], [(sol[:n], sl, (0, n, n))])
         Ec_shift.append(Er)
-    per = np.array(per)
-    se = float(per.std(ddof=1) / np.sqrt(R)) if R > 1 else float("nan")
+    # each rule's mean (column r of the [n][R] view), then the spread of the R means
+    rule_mean, _, _ = henry_sample_stats(ctx, out["qoi"].view(R, n).t().contiguous(), ())
+    se = float("nan")
+    if R > 1:
+        _, rv, _ = henry_sample_stats(ctx, rule_mean.view(R, 1), ())
+        se = float(np.sqrt(rv.item() / R))
+    per = rule_mean.cpu().numpy()
     return dict(EQ=float(mean[0]), EQ_shift=per, se=se, Ec=Ec, Ec_shift=Ec_shift, Varc=var_Y[0], seconds=seconds,
                 nonconverged=int((status != 0).sum()))
 
 
-def telescoped_at(levels, mean_Y, x: float, y: float) -> np.ndarray:
+def telescoped_at(ctx: Context, levels, mean_Y, x: float, y: float) -> np.ndarray:
     """MLMC estimates of E[c] at the point (x, y) truncated after each level:
     entry L is the sum over l <= L of level l's mean difference field at the
     cell containing the point (the partial sums of the telescoping estimator
-    eq:A that Fig. 11 compares with the reference).  mean_Y[l] is level l's
-    field on grid l, as mlmc_run returns it."""
-    vals = [float(mean_Y[l][point_cell(levels[l], x, y)].item()) for l in range(len(levels))]
-    return np.cumsum(vals)
+    eq:A that Fig. 11 compares with the reference), summed on the device.
+    mean_Y[l] is level l's field on grid l, as mlmc_run returns it."""
+    offs = [point_cell(levels[l], x, y) for l in range(len(levels))]
+    pm, _ = henry_mlmc_telescope(ctx, list(mean_Y), None, None, offsets=offs, nvals=1)
+    return pm[:, 0].cpu().numpy()
 
 
 # the paper's output points (eq:12points) and quantiles (Figs. 4 and 6)
@@ -348,11 +362,14 @@ def mlmc_series(ctx: Context, levels, m, nrec: int, points=POINTS12, seed: int =
         lm.append(mean)
         lv.append(var)
         lq.append(q)
+    pm, pv = henry_mlmc_telescope(ctx, lm, lv, m, nvals=nv)
     torch.cuda.synchronize(dev)
     shape = (nrec, 1 + len(points))
+    est = pm[-1].cpu().numpy().reshape(shape)
+    var_est = pv[-1].cpu().numpy().reshape(shape)
     lm = np.stack([v.cpu().numpy().reshape(shape) for v in lm])
     lv = np.stack([v.cpu().numpy().reshape(shape) for v in lv])
     lq = np.stack([v.cpu().numpy().reshape((2,) + shape) for v in lq])
-    return dict(mean=lm.sum(axis=0), var_est=(lv / m[:, None, None]).sum(axis=0), level_mean=lm, level_var=lv,
+    return dict(mean=est, var_est=var_est, level_mean=lm, level_var=lv,
                 level_min=lq[:, 0], level_max=lq[:, 1], m=m, seconds=seconds,
                 nonconverged=int((out["status"].cpu().numpy() != 0).sum()))

@@ -122,7 +122,7 @@ def test_mlmc_L4_full_batch_sampled_against_oracle(torch_cuda, ctx):
     var_Y = [torch.empty(g[0] * g[1], **f64) for g in fine_grids]
     qstats = torch.empty((L + 1, 2), **f64)
     Ec = torch.empty(fine_grids[-1][0] * fine_grids[-1][1], **f64)
-    var_est = torch.empty(1, **f64)
+    var_est = torch.empty(2, **f64)
     hm.mlmc_level_estimate(ctx, fine_grids, m, c_f, c_c, q_f, q_c, mean_Y, var_Y, qstats, Ec, var_est)
     torch.cuda.synchronize()
     for lev in range(L + 1):

@@ -32,7 +32,6 @@ def test_adaptive_mlmc_matches_oracle(torch_cuda):
     ctx = hm.Context(hi.PHYS, 0)
     res = hm.mlmc_run(ctx, levels, eps, m_pilot=m_pilot, seed=seed,
                       opts=hm.make_opts(prec=hm.PREC_FP64, tol=1e-10, max_outer=60))
-    ctx.close()
     assert res["nonconverged"] == 0
     m = res["m"]
     mo, _ = oracle.optimal_samples(res["V_pilot"], res["s"], eps * eps / 2)
@@ -70,7 +69,8 @@ def test_adaptive_mlmc_matches_oracle(torch_cuda):
     # truncated estimates at the point of Fig. 11
     pm = [float(oracle.level_stats(np.array(cp[(l, 0)]), np.array(cp[(l, 1)]) if l > 0 else None)[0])
           for l in range(len(levels))]
-    tel = hm.telescoped_at(levels, res["mean_Y"], 1.60, -0.95)
+    tel = hm.telescoped_at(ctx, levels, res["mean_Y"], 1.60, -0.95)
+    ctx.close()
     np.testing.assert_allclose(tel, np.cumsum(pm), rtol=1e-8, atol=1e-11)
     print(f"E[c(1.60, -0.95)] truncated after each level: {tel}")
 
@@ -105,10 +105,10 @@ def test_telescoped_sum_of_all_levels_is_the_finest_mean(torch_cuda):
     res = hm.mlmc_run(ctx, levels, 0.5, m_pilot=8, seed=2, max_samples=8,
                       opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-9, max_outer=60))
     Ec = res["Ec"].cpu().numpy()
-    ctx.close()
     for x, y in ((1.60, -0.95), (0.30, -0.20), (1.97, -0.61)):
-        tel = hm.telescoped_at(levels, res["mean_Y"], x, y)
+        tel = hm.telescoped_at(ctx, levels, res["mean_Y"], x, y)
         assert tel[-1] == pytest.approx(Ec[hm.point_cell(levels[-1], x, y)], rel=1e-12, abs=1e-15)
+    ctx.close()
 
 
 def test_adaptive_mlmc_for_c_at_a_point_matches_oracle(torch_cuda):
@@ -120,7 +120,6 @@ def test_adaptive_mlmc_for_c_at_a_point_matches_oracle(torch_cuda):
     ctx = hm.Context(hi.PHYS, 0)
     res = hm.mlmc_run(ctx, levels, eps, m_pilot=m_pilot, seed=seed, point=(1.60, -0.95),
                       opts=hm.make_opts(prec=hm.PREC_FP64, tol=1e-10, max_outer=60))
-    ctx.close()
     assert res["nonconverged"] == 0
     m = res["m"]
     mo, _ = oracle.optimal_samples(res["V_pilot"], res["s"], eps * eps / 2)
@@ -141,3 +140,30 @@ def test_adaptive_mlmc_for_c_at_a_point_matches_oracle(torch_cuda):
     assert res["EQ"] == pytest.approx(EQ, abs=1e-8)
     np.testing.assert_allclose(res["mean"], means, rtol=0, atol=1e-8)
     assert res["var_est"] == pytest.approx(var_est, rel=1e-6, abs=1e-14)
+
+
+def test_mlmc_telescope_matches_oracle_estimate(torch_cuda):
+    """henry_mlmc_telescope: the partial sums over levels of the level means
+    and of V_l / m_l (eq:A and the variance half of eq:MSE) equal the
+    oracle's mlmc_estimate of the first l + 1 levels, for many quantities
+    at per-level offsets (same order of additions: bitwise)."""
+    import torch
+    ctx = hm.Context(hi.PHYS, 0)
+    rng = np.random.default_rng(21)
+    nv, off, m = 37, [0, 3, 11, 1, 29], [4096, 1024, 256, 64, 16]
+    means = [rng.normal(size=nv + o) * 10.0 ** -l for l, o in enumerate(off)]
+    vars_ = [rng.uniform(size=nv + o) * 10.0 ** -l for l, o in enumerate(off)]
+    d = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    pm, pv = hm.henry_mlmc_telescope(ctx, [d(a) for a in means], [d(a) for a in vars_], m, offsets=off, nvals=nv)
+    pm, pv = pm.cpu().numpy(), pv.cpu().numpy()
+    for l in range(len(m)):
+        E, V = oracle.mlmc_estimate([a[o:o + nv] for a, o in zip(means[:l + 1], off)],
+                                    [a[o:o + nv] for a, o in zip(vars_[:l + 1], off)], m[:l + 1])
+        assert np.array_equal(pm[l], E), l
+        assert np.array_equal(pv[l], V), l
+    # without variances only the means are summed
+    pm2, pv2 = hm.henry_mlmc_telescope(ctx, [d(a) for a in means], None, m, offsets=off, nvals=nv)
+    assert pv2 is None and np.array_equal(pm2.cpu().numpy(), pm)
+    with pytest.raises(hm.HenryError):
+        hm.henry_mlmc_telescope(ctx, [d(a) for a in means], None, [1, 0, 1, 1, 1], offsets=off, nvals=nv)
+    ctx.close()

@@ -1,0 +1,179 @@
+"""The L = 4 MLMC workload in the benchmark's launch configuration (one
+batch of 6816 solves, mixed precision, tol 1e-7) against oracle solves of
+the same samples (Sec. 3, eq:A: level l pairs grid l with grid l-1 on the
+key (seed 0, l, i)).
+
+The finer levels take the oracle minutes (128x64/400) to hours
+(256x128/800) per solve, so their references are stored:
+tests/golden/oracle_mlmc_L4_level{0..3}.npz hold every sample of levels
+0-3 and oracle_mlmc_L4_level4_sample0.npz sample 0 of level 4, all written
+by tests/golden/make_oracle_refs.py from oracle/ alone (its own Philox
+samples, Newton with a banded LU).  Checked:
+  * every QoI of levels 0-3, fine and coarse, to 1e-5 relative;
+  * each level's mean of Y_l = c_l - I c_{l-1} (l = 0..3) and the
+    telescoped E[c] through level 3 on 128x64 to 1e-5 of max |E[c]| (the
+    metric's error measure), the level variances to 1e-3 of their maximum
+    (a variance of differences amplifies the solves' own 1e-7 errors);
+  * sample 0 of level 4, both its 256x128/800 and its 128x64/400 solve, to
+    1e-5 relative in c and Q;
+  * the last step of a 256x128/800 solve satisfies the oracle's FP64
+    discrete equations to the stopping tolerance (the oracle evaluates its
+    residual at the GPU's final state, with the GPU's state one step
+    earlier as c^n).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import henry_inputs as hi
+import oracle
+import paper_2302_07804_amd as hm
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-7
+
+
+def load(name):
+    with np.load(os.path.join(GOLDEN, name), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible for a gpu-marked test")
+    hm.lib()
+    oracle.build(force=False)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def batch(torch_cuda):
+    """The whole workload in one call, then the library's level statistics."""
+    torch = torch_cuda
+    ctx = hm.Context(hi.PHYS, 0)
+    m_per_level = hi.CONFIGS["mlmc_L4"]["m"]
+    solves, pairs = hi.mlmc_solves(m_per_level)
+    grids = [(s.nx, s.ny, s.nsteps) for s in solves]
+    xi = np.concatenate([hm.henry_sample_xi(hi.SEED, l, 0, m, 3) for l, m in enumerate(m_per_level)
+                         for _ in range(1 if l == 0 else 2)])
+    assert all(np.array_equal(xi[k], hm.henry_sample_xi(hi.SEED, s.level, s.index, 1, 3)[0])
+               for k, s in list(enumerate(solves))[::97])
+    print(f"mlmc_L4: {len(solves)} solves, mixed precision, tol {TOL}", flush=True)
+    out = hm.solve(ctx, grids, xi=torch.tensor(xi, dtype=torch.float64, device="cuda"),
+                   opts=hm.make_opts(prec=hm.PREC_MIXED, tol=TOL, max_outer=60))
+    torch.cuda.synchronize()
+    offs = np.concatenate([[0], np.cumsum([s.cells for s in solves])])
+    f64 = dict(dtype=torch.float64, device="cuda")
+    L = len(pairs) - 1
+    fine_grids = [hi.level_grid(l) for l in range(L + 1)]
+    sl = lambda idx: out["c"][int(offs[idx[0]]):int(offs[idx[-1] + 1])]
+    c_f = [sl(p[0]) for p in pairs]
+    c_c = [None] + [sl(p[1]) for p in pairs[1:]]
+    q_f = [out["qoi"][p[0][0]:p[0][-1] + 1] for p in pairs]
+    q_c = [None] + [out["qoi"][p[1][0]:p[1][-1] + 1] for p in pairs[1:]]
+    mean_Y = [torch.empty(g[0] * g[1], **f64) for g in fine_grids]
+    var_Y = [torch.empty(g[0] * g[1], **f64) for g in fine_grids]
+    qstats = torch.empty(2 * (L + 1), **f64)
+    Ec = torch.empty(fine_grids[-1][0] * fine_grids[-1][1], **f64)
+    var_est = torch.empty(2, **f64)
+    hm.mlmc_level_estimate(ctx, fine_grids, m_per_level, c_f, c_c, q_f, q_c, mean_Y, var_Y, qstats, Ec, var_est)
+    torch.cuda.synchronize()
+    res = dict(solves=solves, pairs=pairs, offs=offs, c=out["c"].cpu().numpy(), q=out["qoi"].cpu().numpy(),
+               status=out["status"].cpu().numpy(), mean_Y=[t.cpu().numpy() for t in mean_Y],
+               var_Y=[t.cpu().numpy() for t in var_Y])
+    ctx.close()
+    return res
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_every_solve_converges(batch):
+    st = batch["status"]
+    assert (st == hm.STATUS_OK).all(), np.unique(st, return_counts=True)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_level_against_stored_oracle(batch, level):
+    z = load(f"oracle_mlmc_L4_level{level}.npz")
+    fi, ci = batch["pairs"][level]
+    m = len(fi)
+    assert int(z["m"]) == m and tuple(z["grid"]) == hi.level_grid(level)
+    q = batch["q"]
+    err_qf = np.abs(q[fi] - z["Q_fine"]) / np.abs(z["Q_fine"])
+    assert err_qf.max() <= 1e-5, (level, err_qf.argmax(), err_qf.max())
+    if ci is not None:
+        err_qc = np.abs(q[ci] - z["Q_coarse"]) / np.abs(z["Q_coarse"])
+        assert err_qc.max() <= 1e-5, (level, err_qc.argmax(), err_qc.max())
+    nx, ny, _ = hi.level_grid(level)
+    mean = batch["mean_Y"][level].reshape(ny, nx)
+    var = batch["var_Y"][level].reshape(ny, nx)
+    # the metric's measure: max-norm error relative to max |E[c]| (about 1)
+    ec_max = np.abs(load("oracle_mlmc_L4_level0.npz")["mean_Y"]).max()
+    e_mean = np.abs(mean - z["mean_Y"]).max() / ec_max
+    e_var = np.abs(var - z["var_Y"]).max() / np.abs(z["var_Y"]).max()
+    k0 = fi[0]
+    e_c0 = rel(batch["c"][batch["offs"][k0]:batch["offs"][k0 + 1]].reshape(ny, nx), z["c_fine0"])
+    print(f"level {level}: Q {err_qf.max():.2e}, mean Y {e_mean:.2e}, var Y {e_var:.2e}, c of sample 0 {e_c0:.2e}",
+          flush=True)
+    assert e_mean <= 1e-5 and e_var <= 1e-3 and e_c0 <= 1e-5
+
+
+def test_telescoped_Ec_through_level_3_against_stored_oracle(batch):
+    E_gpu = E_ora = None
+    for level in range(4):
+        z = load(f"oracle_mlmc_L4_level{level}.npz")
+        nx, ny, _ = hi.level_grid(level)
+        mg = batch["mean_Y"][level].reshape(ny, nx)
+        E_gpu = mg if E_gpu is None else oracle.inject(E_gpu, 2) + mg
+        E_ora = z["mean_Y"] if E_ora is None else oracle.inject(E_ora, 2) + z["mean_Y"]
+    err = np.abs(E_gpu - E_ora).max() / np.abs(E_ora).max()
+    print(f"E[c] through level 3 (128x64): {err:.2e} of max |E[c]|", flush=True)
+    assert err <= 1e-5
+
+
+def test_level4_sample0_against_stored_oracle(batch):
+    z = load("oracle_mlmc_L4_level4_sample0.npz")
+    fi, ci = batch["pairs"][4]
+    offs, c, q = batch["offs"], batch["c"], batch["q"]
+    for k, cref, qref in ((fi[0], z["c_fine0"], z["Q_fine0"]), (ci[0], z["c_coarse0"], z["Q_coarse0"])):
+        s = batch["solves"][k]
+        ck = c[offs[k]:offs[k + 1]].reshape(s.ny, s.nx)
+        e = rel(ck, cref)
+        print(f"level 4 sample 0, {s.nx}x{s.ny}/{s.nsteps}: c {e:.2e}, Q {abs(q[k] - qref) / abs(qref):.2e}",
+              flush=True)
+        assert e <= 1e-5 and abs(q[k] - qref) <= 1e-5 * abs(qref)
+
+
+def test_finest_level_last_step_solves_the_oracle_equations(torch_cuda):
+    """256x128 at tau = T/800: the state after step N and the one after step
+    N - 1 (two runs of the same deterministic steps) satisfy the oracle's
+    FP64 discrete equations of step N to the stopping tolerance."""
+    torch = torch_cuda
+    nx, ny, r = hi.level_grid(4)
+    xi = hm.henry_sample_xi(hi.SEED, 4, 3, 1, 3)
+    runs = {}
+    for steps in (r - 1, r):
+        ph = dict(hi.PHYS)
+        ph["T"] = hi.PHYS["T"] * steps / r
+        ctx = hm.Context(ph, 0)
+        print(f"256x128, {steps} steps of T/800", flush=True)
+        out = hm.solve(ctx, [(nx, ny, steps)], xi=torch.tensor(xi, dtype=torch.float64, device="cuda"),
+                       opts=hm.make_opts(prec=hm.PREC_MIXED, tol=TOL, max_outer=60), want_p=True)
+        torch.cuda.synchronize()
+        assert out["status"].item() == hm.STATUS_OK
+        runs[steps] = (out["p"].cpu().numpy().reshape(ny, nx), out["c"].cpu().numpy().reshape(ny, nx), ph)
+        ctx.close()
+    p2, c2, ph = runs[r]
+    _, c1, _ = runs[r - 1]
+    phi, K, q = oracle.fields_closed(ph, nx, ny, xi[0])
+    Rp, Rc = oracle.residual(ph, r, phi, K, q, p2, c2, c1)
+    sc = (ph["T"] / r) / ((1.0 / ny) ** 2 * phi * ph["rho0"])
+    print(f"scaled residuals: {np.abs(Rp * sc).max():.2e}, {np.abs(Rc * sc).max():.2e}", flush=True)
+    assert np.abs(Rp * sc).max() <= 1.01 * TOL and np.abs(Rc * sc).max() <= 1.01 * TOL
