@@ -136,8 +136,8 @@ def summarize_pmc(fetch_dir, write_dir, workload_name="mlmc_L4", path=None):
     copy_w = max(pick(write, "copy") + pick(write, "Copy") + pick(write, "elementwise"))
     sf = CALIB_BYTES / (copy_f * 1024.0)
     sw = CALIB_BYTES / (copy_w * 1024.0)
-    sol_f = pick(fetch, "henry_solve_kernel")
-    sol_w = pick(write, "henry_solve_kernel")
+    sol_f = pick(fetch, "henry_solve_kernel<float>")
+    sol_w = pick(write, "henry_solve_kernel<float>")
     per_launch = (sum(sol_f) * 1024.0 * sf + sum(sol_w) * 1024.0 * sw) / len(sol_f)
     rec = dict(kernel="henry_solve_kernel<float>", workload=workload_name, kernel_hash=kernel_hash(),
                launches=len(sol_f), fetch_kib=sol_f, write_kib=sol_w, calib_bytes=CALIB_BYTES,

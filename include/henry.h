@@ -343,16 +343,28 @@ int henry_level_smooth(henry_ctx* ctx, int32_t nx, int32_t ny, int32_t kind, int
                        const double* coef, const double* b, double* x, void* workspace, size_t ws_bytes,
                        void* stream);
 
-/* Tuning cache of a context: threads per solve-workgroup for grids of
- * width nx at precision prec, used by henry_solve_batch and
- * henry_adjoint_batch when opts->threads == 0.  threads = 0 clears the
- * entry (back to the built-in default: 128 threads up to 128 cells, 256 up
- * to 512, 512 up to 2048, above that 1024 with PREC_MIXED and 512 with
- * PREC_FP64); threads <= 1024 for PREC_MIXED and <= 512 for PREC_FP64.  The measuring driver that fills it
- * times candidate sizes on short runs of the caller's own batch (Python
- * binding: paper_2302_07804_amd.autotune). */
-int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads);
-int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads);
+/* Tuning cache of a context, per grid width nx and precision prec, used
+ * by henry_solve_batch, henry_solve_batch_trace and henry_adjoint_batch
+ * (the batch plan of the ensemble: how the solves of one grid are packed
+ * onto workgroups and streams, priced by their cost n_l r_l, eq:workpl):
+ *   threads  workgroup size when opts->threads == 0; 0 = built-in (128
+ *            threads up to 128 cells, 256 up to 512, 512 up to 2048, above
+ *            that 1024 with PREC_MIXED and 512 with PREC_FP64);
+ *            <= 1024 for PREC_MIXED and <= 512 for PREC_FP64
+ *   cluster  workgroups per solve (1, 2, 4 or 8) when opts->cluster == 0;
+ *            0 = built-in (see henry_opts_t.cluster); grids of 2048 cells
+ *            or fewer always use 1
+ *   stream   stream (0..3) of the grid's group when it runs one workgroup
+ *            per solve; -1 = built-in plan.  Groups with clusters always
+ *            run on stream 0, one after another.
+ * threads = cluster = 0 and stream = -1 clear the entry.  None of the
+ * choices changes a result (bitwise).  The measuring driver that fills it
+ * times candidates on short runs of the caller's own batch (Python
+ * binding: paper_2302_07804_amd.autotune).  henry_tune_get returns the
+ * effective workgroup size and the stored cluster and stream (0 / -1 =
+ * built-in); cluster and stream may be NULL. */
+int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads, int32_t cluster, int32_t stream);
+int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads, int32_t* cluster, int32_t* stream);
 
 /* Per-group timings of the last profiled henry_solve_batch call: writes up
  * to `cap` entries, returns the group count through *ngroups.  Synchronises

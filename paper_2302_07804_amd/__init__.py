@@ -119,8 +119,8 @@ def lib():
     L.henry_residual_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                        ct.c_size_t, vp]
     L.henry_qmc_points.argtypes = [i64, i64, i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
-    L.henry_tune_set.argtypes = [vp, i32, i32, i32]
-    L.henry_tune_get.argtypes = [vp, i32, i32, ct.POINTER(i32)]
+    L.henry_tune_set.argtypes = [vp, i32, i32, i32, i32, i32]
+    L.henry_tune_get.argtypes = [vp, i32, i32, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)]
     L.henry_adjoint_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), i32,
                                                 ct.POINTER(ct.c_size_t)]
     L.henry_adjoint_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, ct.POINTER(Opts), i32, dbl, i32,
@@ -223,10 +223,13 @@ class Context:
         p = Phys(**{name: float(phys[name]) for name, _ in Phys._fields_})
         _chk(lib().henry_ctx_create(ct.byref(self.handle), ct.byref(p), device), "henry_ctx_create")
         self.device = device
+        self.phys = {name: float(phys[name]) for name, _ in Phys._fields_}
+        self.kl = {}  # grid width -> set_kl arguments (to rebuild a context with other constants)
 
     def set_kl(self, nx: int, ny: int, corr_len: float = 0.3, sigma_phi: float = 0.1, sigma_logk: float = 0.5):
         """Upload the KL basis used by FIELD_KL41 solves on nx x ny grids."""
         _chk(lib().henry_ctx_set_kl(self.handle, nx, ny, corr_len, sigma_phi, sigma_logk), "henry_ctx_set_kl")
+        self.kl[nx] = (nx, ny, corr_len, sigma_phi, sigma_logk)
 
     def close(self):
         if self.handle:
@@ -710,24 +713,71 @@ def __getattr__(name):
 
 
 # ------------------------------------------------------------------ autotuning
-def henry_tune_set(ctx: Context, nx: int, prec: int, threads: int):
-    _chk(lib().henry_tune_set(ctx.handle, nx, prec, threads), "henry_tune_set")
+def henry_tune_set(ctx: Context, nx: int, prec: int, threads: int = 0, cluster: int = 0, stream: int = -1):
+    """Store tuned launch choices for grids of width nx (0 / -1: built-in)."""
+    _chk(lib().henry_tune_set(ctx.handle, nx, prec, threads, cluster, stream), "henry_tune_set")
 
 
-def henry_tune_get(ctx: Context, nx: int, prec: int) -> int:
-    t = ct.c_int32()
-    _chk(lib().henry_tune_get(ctx.handle, nx, prec, ct.byref(t)), "henry_tune_get")
-    return t.value
+def henry_tune_get(ctx: Context, nx: int, prec: int):
+    """(threads, cluster, stream) of grids of width nx: the effective
+    workgroup size and the stored cluster and stream (0 / -1: built-in)."""
+    t, k, st = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _chk(lib().henry_tune_get(ctx.handle, nx, prec, ct.byref(t), ct.byref(k), ct.byref(st)), "henry_tune_get")
+    return t.value, k.value, st.value
+
+
+STREAM_PLANS = ("built-in", "one lane", "spread", "serial")
+TUNE_FRAC_TARGET = 5
+
+
+def _plan_streams(plan, grid_costs):
+    """Stream of each one-workgroup grid under a named plan: 'built-in'
+    leaves the library's plan (-1), 'one lane' puts every such group on
+    stream 1 beside the cluster groups, 'spread' deals them over streams
+    1..3 in cost order, 'serial' runs everything on stream 0."""
+    order = sorted(grid_costs, key=lambda nx: -grid_costs[nx])
+    if plan == "built-in":
+        return {nx: -1 for nx in order}
+    if plan == "one lane":
+        return {nx: 1 for nx in order}
+    if plan == "spread":
+        return {nx: 1 + k % 3 for k, nx in enumerate(order)}
+    return {nx: 0 for nx in order}
+
+
+def _short_batch(solves, target=TUNE_FRAC_TARGET, min_steps=8):
+    """The batch shortened by a common factor f that keeps every solve's
+    time step (its step count divides by f, the horizon is T / f), with f
+    the divisor of the steps' gcd nearest `target` that leaves at least
+    `min_steps` steps per solve; (f, shortened solves)."""
+    import math
+    g = 0
+    for s in solves:
+        g = math.gcd(g, int(s[2]))
+    rmin = min(int(s[2]) for s in solves)
+    divs = [d for d in range(1, g + 1) if g % d == 0 and rmin // d >= min_steps] or [1]
+    f = min(divs, key=lambda d: (abs(d - target), -d))
+    return f, [(int(s[0]), int(s[1]), int(s[2]) // f) for s in solves]
 
 
 def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int = 8, max_solves: int = 1024,
-             candidates=(64, 128, 256, 512, 1024), cache_path: str | None = None):
-    """Choose the threads per solve-workgroup for every grid of `solves` by
-    timing short runs (the first `tune_steps` steps of up to `max_solves`
-    solves of that grid, each candidate twice, HIP-event group time on the
-    stream the kernels run on) and store the fastest in the context's
-    tuning cache; optionally persist the choices as JSON.  Returns
-    {(nx, prec): (threads, {candidate: ms})}."""
+             candidates=(64, 128, 256, 512, 1024), cache_path: str | None = None, clusters=(1, 2, 4, 8),
+             plans=STREAM_PLANS, model=None, reps: int = 2):
+    """Fill the context's tuning cache for the grids of `solves` by timing
+    the candidates on short runs of the caller's own batch:
+      1. threads per solve-workgroup, per grid: the first `tune_steps` steps
+         of up to `max_solves` solves of that grid alone, HIP-event group
+         time on the stream the kernels run on;
+      2. workgroups per solve (cluster) for the grids above 2048 cells, one
+         grid after another in cost order (eq:workpl: n_l r_l), with at
+         most 256 workgroups per group; then the stream plan of the
+         one-workgroup groups (STREAM_PLANS).  Each candidate times the
+         whole batch shortened by a common factor that keeps every time
+         step (_short_batch), between events on the caller's stream.
+    Each candidate runs `reps` times and its fastest run counts.  The
+    choices change no result (bitwise).  With cache_path, choices found
+    there are used as they are and new ones are written back.  Returns
+    {(nx, prec): (threads, cluster, stream, {candidate: ms})}."""
     import json
     import torch
     opts = opts or opts_default()
@@ -740,12 +790,17 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
         with open(cache_path) as f:
             cache = json.load(f)
     result = {}
+    keys = {nx: f"{nx}:{prec}" for nx in by_grid}
+    if all(k in cache for k in keys.values()):
+        for nx, key in keys.items():
+            t, kc, st = (int(v) for v in cache[key])
+            henry_tune_set(ctx, nx, prec, t, kc, st)
+            result[(nx, prec)] = (t, kc, st, {})
+        return result
+    field = _field_of(xi, model)
+    # ---- 1. threads per grid, each grid alone
+    threads = {}
     for nx, ks in sorted(by_grid.items()):
-        key = f"{nx}:{prec}"
-        if key in cache:
-            henry_tune_set(ctx, nx, prec, int(cache[key]))
-            result[(nx, prec)] = (int(cache[key]), {})
-            continue
         ks = ks[:max_solves]
         sub = [(int(solves[k][0]), int(solves[k][1]), min(int(solves[k][2]), tune_steps)) for k in ks]
         xs = xi[ks].contiguous()
@@ -755,21 +810,76 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
         for t in candidates:
             if (t > 64 and t > 2 * cells) or t > tmax:
                 continue
-            o = make_opts(prec=prec, tol=opts.tol, max_outer=opts.max_outer, threads=t, profile=1)
+            o = make_opts(prec=prec, tol=opts.tol, max_outer=opts.max_outer, threads=t, profile=1,
+                          predictor=opts.predictor)
             best = None
-            for _ in range(2):
-                solve(ctx, sub, xi=xs, opts=o)
+            for _ in range(reps):
+                solve(ctx, sub, xi=xs, opts=o, model=model)
                 torch.cuda.synchronize()
                 ms = sum(g["ms"] for g in henry_profile_last(ctx))
                 best = ms if best is None else min(best, ms)
             times[t] = best
-        choice = min(times, key=times.get)
-        henry_tune_set(ctx, nx, prec, choice)
-        cache[key] = choice
-        result[(nx, prec)] = (choice, times)
+        threads[nx] = (min(times, key=times.get), times)
+    # ---- 2. clusters and stream plan on the shortened whole batch
+    f, short = _short_batch(solves)
+    ph = dict(ctx.phys)
+    ph["T"] = ph["T"] / f
+    tctx = Context(ph, ctx.device)
+    for args in ctx.kl.values():
+        tctx.set_kl(*args)
+    costs = {nx: sum(float(solves[k][0]) * solves[k][1] * solves[k][2] for k in ks) for nx, ks in by_grid.items()}
+    choice = {nx: [threads[nx][0], 0, -1] for nx in by_grid}
+    o = make_opts(prec=prec, tol=opts.tol, max_outer=opts.max_outer, predictor=opts.predictor)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def trial():
+        for nx, (t, kc, st) in choice.items():
+            henry_tune_set(tctx, nx, prec, t, kc, st)
+        best = None
+        for _ in range(reps):
+            ev0.record()
+            solve(tctx, short, xi=xi, opts=o, model=model)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    plan_times = {}
+    try:
+        for nx in sorted(by_grid, key=lambda g: -costs[g]):
+            if nx * (nx // 2) <= 2048:
+                continue
+            ktimes = {}
+            for kc in clusters:
+                if kc * len(by_grid[nx]) > 256:
+                    continue
+                choice[nx][1] = kc
+                ktimes[kc] = trial()
+            choice[nx][1] = min(ktimes, key=ktimes.get)
+            threads[nx][1].update({f"cluster {kc}": v for kc, v in ktimes.items()})
+        single = {nx: costs[nx] for nx in by_grid
+                  if nx * (nx // 2) <= 2048 or choice[nx][1] == 1}
+        if single:
+            for plan in plans:
+                for nx, st in _plan_streams(plan, single).items():
+                    choice[nx][2] = st
+                plan_times[plan] = trial()
+            best_plan = min(plan_times, key=plan_times.get)
+            for nx, st in _plan_streams(best_plan, single).items():
+                choice[nx][2] = st
+    finally:
+        tctx.close()
+    for nx in by_grid:
+        t, kc, st = choice[nx]
+        henry_tune_set(ctx, nx, prec, t, kc, st)
+        times = dict(threads[nx][1])
+        times.update({f"plan {p}": v for p, v in plan_times.items()})
+        result[(nx, prec)] = (t, kc, st, times)
+        cache[keys[nx]] = [t, kc, st]
     if cache_path:
-        with open(cache_path, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
+        with open(cache_path, "w") as f_:
+            json.dump(cache, f_, indent=1, sort_keys=True)
     return result
 
 

@@ -56,8 +56,15 @@ size_t lds_bytes(int nx, int ny, int prec) {
 
 struct Group {
     int nx, ny, threads, cluster;
+    int stream = -1;           // tuned stream of a one-workgroup group, -1 = built-in plan
     std::vector<int> members;  // indices into the solve list
     double cost;
+};
+
+// Choices of the tuning cache for one grid width and precision (0 / -1 =
+// the built-in choice).
+struct Tuned {
+    int threads = 0, cluster = 0, stream = -1;
 };
 
 struct PlanKey {
@@ -84,7 +91,7 @@ struct henry_ctx {
     void* pinned = nullptr;      // host staging for descriptor tables
     size_t pinned_bytes = 0;
     hipEvent_t staging_done = nullptr;
-    std::map<long, int> tuned_threads;  // (nx, prec) -> threads
+    std::map<long, Tuned> tuned;  // (nx, prec) -> tuned launch choices
     // profiling of the last batch
     std::vector<henry_group_time_t> prof;
     std::vector<hipEvent_t> prof_ev;  // 2 per group
@@ -174,14 +181,20 @@ int64_t desc_bytes(int nsolves) { return henry::align256((int64_t)nsolves * (int
 
 
 // Stream of each group (see enqueue_groups).
+// A one-workgroup group with a tuned stream takes it; groups with clusters
+// always take stream 0 (see enqueue_groups).
 std::vector<int> stream_plan(const std::vector<Group>& order, int nstreams) {
     bool any_cluster = false;
     for (const Group& G : order) any_cluster |= G.cluster > 1;
     std::vector<int> si(order.size(), 0);
     int next = 0;
-    for (size_t gi = 0; gi < order.size(); ++gi)
-        if (nstreams > 0 && order[gi].cluster == 1)
+    for (size_t gi = 0; gi < order.size(); ++gi) {
+        if (nstreams <= 0 || order[gi].cluster != 1) continue;
+        if (order[gi].stream >= 0)
+            si[gi] = order[gi].stream % nstreams;
+        else
             si[gi] = any_cluster ? (nstreams > 1 ? 1 : 0) : next++ % nstreams;
+    }
     return si;
 }
 
@@ -568,13 +581,13 @@ int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves
     for (auto& G : order) {
         gstart.push_back((int)table.size());
         for (int k : G.members) table.push_back(desc[k]);
+        const auto it = ctx->tuned.find((long)G.nx * 4 + prec);
+        const Tuned tu = it != ctx->tuned.end() ? it->second : Tuned{};
         int t = o->threads;
-        if (t == 0) {
-            auto it = ctx->tuned_threads.find((long)G.nx * 4 + prec);
-            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny, prec);
-        }
+        if (t == 0) t = tu.threads > 0 ? tu.threads : default_threads(G.nx, G.ny, prec);
         G.threads = t;
-        G.cluster = cluster_size(G.nx, G.ny, (int)G.members.size(), o->cluster);
+        G.cluster = cluster_size(G.nx, G.ny, (int)G.members.size(), o->cluster > 0 ? o->cluster : tu.cluster);
+        G.stream = tu.stream;
     }
 
     DeviceGuard dg(ctx->device);
@@ -788,19 +801,17 @@ int henry_residual_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nso
     return HENRY_OK;
 }
 
-int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
+int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads, int32_t cluster, int32_t stream) {
     if (!ctx || nx < 2 || nx > 1024 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
     if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
-    if (threads == 0) {
-        ctx->tuned_threads.erase((long)nx * 4 + prec);
-        if (ctx->graph_exec) {
-            (void)hipGraphExecDestroy(ctx->graph_exec);
-            ctx->graph_exec = nullptr;
-        }
-        return HENRY_OK;
-    }
-    if (threads < 64 || threads > max_threads(prec) || !pow2(threads)) return HENRY_EINVAL;
-    ctx->tuned_threads[(long)nx * 4 + prec] = threads;
+    if (threads != 0 && (threads < 64 || threads > max_threads(prec) || !pow2(threads))) return HENRY_EINVAL;
+    if (cluster != 0 && (cluster > henry::kMaxCluster || !pow2(cluster))) return HENRY_EINVAL;
+    if (stream < -1 || stream >= kStreams) return HENRY_EINVAL;
+    const long key = (long)nx * 4 + prec;
+    if (threads == 0 && cluster == 0 && stream == -1)
+        ctx->tuned.erase(key);
+    else
+        ctx->tuned[key] = Tuned{threads, cluster, stream};
     if (ctx->graph_exec) {  // the cached graph was built with the old choice
         (void)hipGraphExecDestroy(ctx->graph_exec);
         ctx->graph_exec = nullptr;
@@ -808,11 +819,14 @@ int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads) {
     return HENRY_OK;
 }
 
-int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads) {
+int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads, int32_t* cluster, int32_t* stream) {
     if (!ctx || !threads || nx < 2 || nx > 1024 || (nx & (nx - 1)) != 0) return HENRY_EINVAL;
     if (prec != HENRY_PREC_FP64 && prec != HENRY_PREC_MIXED) return HENRY_EINVAL;
-    auto it = ctx->tuned_threads.find((long)nx * 4 + prec);
-    *threads = it != ctx->tuned_threads.end() ? it->second : default_threads(nx, nx / 2, prec);
+    const auto it = ctx->tuned.find((long)nx * 4 + prec);
+    const Tuned tu = it != ctx->tuned.end() ? it->second : Tuned{};
+    *threads = tu.threads > 0 ? tu.threads : default_threads(nx, nx / 2, prec);
+    if (cluster) *cluster = tu.cluster;
+    if (stream) *stream = tu.stream;
     return HENRY_OK;
 }
 
@@ -908,13 +922,13 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
     for (auto& G : order) {
         gstart.push_back((int)table.size());
         for (int k : G.members) table.push_back(desc[k]);
+        const auto it = ctx->tuned.find((long)G.nx * 4 + prec);
+        const Tuned tu = it != ctx->tuned.end() ? it->second : Tuned{};
         int t = o->threads;
-        if (t == 0) {
-            auto it = ctx->tuned_threads.find((long)G.nx * 4 + prec);
-            t = it != ctx->tuned_threads.end() ? it->second : default_threads(G.nx, G.ny, prec);
-        }
+        if (t == 0) t = tu.threads > 0 ? tu.threads : default_threads(G.nx, G.ny, prec);
         G.threads = std::min(t, kAdjMaxThreads);
-        G.cluster = cluster_size(G.nx, G.ny, (int)G.members.size(), o->cluster);
+        G.cluster = cluster_size(G.nx, G.ny, (int)G.members.size(), o->cluster > 0 ? o->cluster : tu.cluster);
+        G.stream = tu.stream;
     }
     DeviceGuard dg(ctx->device);
     hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);

@@ -121,9 +121,23 @@ int main() {
         EXPECT(henry_level_smooth(handle, 16, 8, 0, HENRY_PREC_MIXED, 1, &d, &d, &d, &d, 64, nullptr) ==
                HENRY_ENOMEM);
     }
+    // estimator sums: argument checks, and an empty set of quantities returns
+    // before touching the (placeholder) context
+    {
+        henry_ctx* handle = reinterpret_cast<henry_ctx*>(&d);
+        const double* mp[2] = {&d, &d};
+        const int32_t mm2[2] = {4, 1}, m0[2] = {4, 0};
+        const int64_t off[2] = {0, 3}, boff[2] = {0, -1};
+        EXPECT(henry_mlmc_telescope(handle, 2, 0, mp, mp, mm2, off, &d, &d, nullptr) == HENRY_OK);
+        EXPECT(henry_mlmc_telescope(nullptr, 2, 1, mp, mp, mm2, off, &d, &d, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_mlmc_telescope(handle, 17, 1, mp, mp, mm2, off, &d, &d, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_mlmc_telescope(handle, 2, 1, mp, mp, m0, off, &d, &d, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_mlmc_telescope(handle, 2, 1, mp, mp, mm2, boff, &d, &d, nullptr) == HENRY_EINVAL);
+        EXPECT(henry_mlmc_telescope(handle, 2, 1, mp, mp, mm2, off, &d, nullptr, nullptr) == HENRY_EINVAL);
+    }
     int32_t t = 0;
-    EXPECT(henry_tune_set(nullptr, 16, HENRY_PREC_MIXED, 128) == HENRY_EINVAL);
-    EXPECT(henry_tune_get(nullptr, 16, HENRY_PREC_MIXED, &t) == HENRY_EINVAL);
+    EXPECT(henry_tune_set(nullptr, 16, HENRY_PREC_MIXED, 128, 0, -1) == HENRY_EINVAL);
+    EXPECT(henry_tune_get(nullptr, 16, HENRY_PREC_MIXED, &t, nullptr, nullptr) == HENRY_EINVAL);
     EXPECT(henry_profile_last(nullptr, nullptr, 0, &t) == HENRY_EINVAL);
     EXPECT(henry_ctx_set_kl(nullptr, 16, 8, 0.3, 0.1, 0.5) == HENRY_EINVAL);
 

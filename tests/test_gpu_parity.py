@@ -391,8 +391,8 @@ def test_autotune_picks_a_candidate_and_threads_do_not_change_the_solution(torch
     solves = [(16, 8, 50)] * 6 + [(32, 16, 100)] * 3
     xi = torch.tensor(hm.henry_sample_xi(0, 1, 0, len(solves), 3), dtype=torch.float64, device="cuda")
     res = hm.autotune(ctx, solves, xi, hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60), tune_steps=4)
-    for (nx, prec), (t, times) in res.items():
-        assert t in (64, 128, 256, 512, 1024) and hm.henry_tune_get(ctx, nx, prec) == t
+    for (nx, prec), (t, kc, st, times) in res.items():
+        assert t in (64, 128, 256, 512, 1024) and hm.henry_tune_get(ctx, nx, prec) == (t, kc, st)
     outs = [hm.solve(ctx, solves, xi=xi, opts=hm.make_opts(prec=hm.PREC_MIXED, tol=1e-10, max_outer=60,
                                                            threads=t)) for t in (64, 256, 1024)]
     torch.cuda.synchronize()
@@ -401,6 +401,39 @@ def test_autotune_picks_a_candidate_and_threads_do_not_change_the_solution(torch
         assert torch.allclose(outs[0]["qoi"], o["qoi"], rtol=1e-14, atol=0)
     for nx in (16, 32):
         hm.henry_tune_set(ctx, nx, hm.PREC_MIXED, 0)
+
+
+def test_autotuned_clusters_and_streams_come_from_the_candidates_and_change_no_result(torch_cuda, ctx):
+    """The tuner's second stage picks the workgroups per solve of the grids
+    above 2048 cells (1, 2, 4 or 8, at most 256 workgroups per group) and
+    the stream plan of the one-workgroup groups by timing the shortened
+    batch; the batch solved with the tuned plan equals, bitwise in c and
+    Q, the same batch with one workgroup per solve and the built-in
+    streams at the same workgroup sizes."""
+    torch = torch_cuda
+    solves = [(128, 64, 40)] * 4 + [(64, 32, 40)] * 6 + [(16, 8, 50)] * 24 + [(32, 16, 100)] * 3
+    xi = torch.tensor(hm.henry_sample_xi(0, 2, 0, len(solves), 3), dtype=torch.float64, device="cuda")
+    opts = hm.make_opts(prec=hm.PREC_MIXED, tol=1e-9, max_outer=60)
+    res = hm.autotune(ctx, solves, xi, opts, tune_steps=4)
+    print({k: v[:3] for k, v in res.items()}, flush=True)
+    for (nx, prec), (t, kc, st, times) in res.items():
+        assert t in (64, 128, 256, 512, 1024)
+        assert hm.henry_tune_get(ctx, nx, prec) == (t, kc, st)
+        if nx == 128:
+            assert kc in (1, 2, 4, 8) and {f"cluster {k}" for k in (1, 2, 4, 8)} <= set(times)
+        else:
+            assert kc == 0
+        assert st in (-1, 0, 1, 2, 3)
+    tuned = hm.solve(ctx, solves, xi=xi, opts=opts)
+    for (nx, prec), (t, kc, st, _) in res.items():
+        hm.henry_tune_set(ctx, nx, prec, t, 1, -1)
+    plain = hm.solve(ctx, solves, xi=xi, opts=opts)
+    torch.cuda.synchronize()
+    assert (tuned["status"].cpu().numpy() == 0).all()
+    assert torch.equal(tuned["c"], plain["c"])
+    assert torch.equal(tuned["qoi"], plain["qoi"])
+    for nx in (16, 32, 64, 128):
+        hm.henry_tune_set(ctx, nx, hm.PREC_MIXED, 0, 0, -1)
 
 
 def test_predictors_converge_to_the_same_states(torch_cuda, ctx):
