@@ -255,6 +255,32 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
                       double* qoi_out, int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes,
                       void* stream);
 
+/* Allocation-free variant of henry_solve_batch, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * kernels as henry_solve_batch, without the workspace: the solves' state
+ * (the workspace henry_workspace_bytes sizes) lives in a library-owned
+ * static device buffer of HENRY_STATIC_SCRATCH_BYTES (128 MiB), one per
+ * GPU, held by every GPU the library runs on until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree, hipHostMalloc, graph or
+ * event): the descriptor table reaches the device as kernel arguments.
+ * Limits and errors, besides those of henry_solve_batch:
+ *   - henry_workspace_bytes(solves, opts) > HENRY_STATIC_SCRATCH_BYTES:
+ *     HENRY_ENOMEM, nothing launched (split the batch);
+ *   - opts->steps_per_launch != 0 or opts->profile != 0: HENRY_EINVAL;
+ *   - the buffer's address could not be looked up at context creation:
+ *     HENRY_EHIP.
+ * Every call on one GPU uses that GPU's one buffer, and the buffer keeps
+ * the last call's contents (each call re-initialises what it reads).
+ * Calls that overlap in time on one GPU (on two streams, from two contexts
+ * or host threads) race on it and corrupt each other's solves: order them,
+ * e.g. on one stream. */
+#define HENRY_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+int henry_solve_batch_static(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                             const double* xi, const double* phi, const double* logk, const double* qin,
+                             const double* c0, const henry_opts_t* opts, double* c_out, double* p_out,
+                             double* qoi_out, int32_t* status, int32_t* iters, void* stream);
+
 /* Batched forward solves that also record a time series of each solve
  * (Sec. 4: the fresh-water integral eq:integral_fw and c at the points of
  * eq:12points over time, the inputs of the paper's Figs. 4-7).  Every

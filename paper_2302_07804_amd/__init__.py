@@ -29,7 +29,10 @@ EXPORTS = ("henry_strerror", "henry_ctx_create", "henry_ctx_destroy", "henry_opt
            "henry_adjoint_workspace_bytes", "henry_adjoint_batch", "mlmc_level_estimate", "henry_kl_basis",
            "henry_ctx_set_kl", "henry_sample_xi_kl", "henry_residual_batch", "henry_mlmc_allocate",
            "henry_mlmc_rates", "henry_qmc_points", "henry_solve_batch_trace", "henry_sample_stats",
-           "henry_first_passage", "henry_level_smooth", "henry_mlmc_telescope")
+           "henry_first_passage", "henry_level_smooth", "henry_mlmc_telescope", "henry_solve_batch_static")
+
+# bytes of the static device buffer of henry_solve_batch_static (HENRY_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 128 << 20
 
 
 class HenryLibraryMissing(RuntimeError):
@@ -105,6 +108,8 @@ def lib():
     L.henry_workspace_bytes.argtypes = [vp, ct.POINTER(Grid), i32, ct.POINTER(Opts), ct.POINTER(ct.c_size_t)]
     L.henry_solve_batch.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), vp, vp,
                                     vp, vp, vp, vp, ct.c_size_t, vp]
+    L.henry_solve_batch_static.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts),
+                                           vp, vp, vp, vp, vp, vp]
     L.henry_solve_batch_trace.argtypes = [vp, ct.POINTER(Grid), i32, i32, vp, vp, vp, vp, vp, ct.POINTER(Opts), i32,
                                           i32, ct.POINTER(ct.c_double), dbl, vp, vp, vp, vp, vp, vp, vp, ct.c_size_t,
                                           vp]
@@ -312,6 +317,20 @@ def henry_solve_batch(ctx: Context, solves, field, xi=None, phi=None, logk=None,
                                  workspace.numel() * workspace.element_size() if workspace is not None else 0,
                                  _stream_of(stream))
     _chk(rc, "henry_solve_batch")
+
+
+def henry_solve_batch_static(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, c0=None,
+                             opts: Opts | None = None, c_out=None, p_out=None, qoi_out=None, status=None, iters=None,
+                             stream=None):
+    """Thin wrapper of the allocation-free entry point: henry_solve_batch
+    with the solves' state in the library's static device buffer (no
+    workspace argument; at most STATIC_SCRATCH_BYTES of it)."""
+    g = grids(solves)
+    _check_solve_args(ctx, solves, field, xi, phi, logk, qin, c0, c_out, p_out, qoi_out, status, iters)
+    rc = lib().henry_solve_batch_static(ctx.handle, g, len(solves), field, _ptr(xi), _ptr(phi), _ptr(logk),
+                                        _ptr(qin), _ptr(c0), ct.byref(opts) if opts else None, _ptr(c_out),
+                                        _ptr(p_out), _ptr(qoi_out), _ptr(status), _ptr(iters), _stream_of(stream))
+    _chk(rc, "henry_solve_batch_static")
 
 
 def henry_solve_batch_trace(ctx: Context, solves, field, xi=None, phi=None, logk=None, qin=None, c0=None,

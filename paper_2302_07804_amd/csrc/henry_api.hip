@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -52,6 +53,47 @@ size_t lds_bytes(int nx, int ny, int prec) {
     return (size_t)(prec == HENRY_PREC_MIXED
                         ? henry::lds_level_bytes<float>(nx, ny, kLdsCells, lds_block_cells(prec))
                         : henry::lds_level_bytes<double>(nx, ny, kLdsCells, lds_block_cells(prec)));
+}
+
+// Device memory of the allocation-free entry point (henry_solve_batch_static):
+// every GPU the library runs on holds one copy of this array until the
+// process ends.  Host code never uses the array's name as an address: each
+// device's copy is looked up once with hipGetSymbolAddress (scratch_of) and
+// only that pointer reaches kernels.
+constexpr size_t kStaticScratchBytes = HENRY_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_rc[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// The static scratch of `device` (which must be current), looked up on the
+// first call for that device; nullptr if the lookup failed.
+void* scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* ptr = nullptr;
+        g_scratch_rc[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[device] = g_scratch_rc[device] == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_ptr[device];
+}
+
+// Descriptors of the allocation-free path reach the device as kernel
+// arguments, kDescChunk at a time (no staging buffer, no copy from host memory).
+constexpr int kDescChunk = 32;
+struct DescChunk {
+    henry::SolveDesc d[kDescChunk];
+    int32_t first, count;
+};
+
+__global__ void desc_fill_kernel(DescChunk ch, henry::SolveDesc* table) {
+    const int k = threadIdx.x;
+    if (k < ch.count) table[ch.first + k] = ch.d[k];
 }
 
 struct Group {
@@ -104,6 +146,8 @@ struct henry_ctx {
     hipEvent_t cap_in = nullptr, cap_out = nullptr;
     // KL bases by grid width
     std::map<int, KlGrid> kl;
+    // this device's copy of the static scratch (allocation-free entry point)
+    void* scratch = nullptr;
 };
 
 namespace {
@@ -323,6 +367,10 @@ int henry_ctx_create(henry_ctx** out, const henry_phys_t* phys, int device) {
     ok &= hipEventCreateWithFlags(&c->cap_in, hipEventDisableTiming) == hipSuccess;
     ok &= hipEventCreateWithFlags(&c->cap_out, hipEventDisableTiming) == hipSuccess;
     ok &= hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) == hipSuccess;
+    // set-up of the allocation-free entry point: this device's scratch address
+    // (a failed lookup only disables henry_solve_batch_static, which then
+    // returns HENRY_EHIP)
+    c->scratch = scratch_of(device);
     if (!ok) {
         henry_ctx_destroy(c);
         return HENRY_EHIP;
@@ -487,7 +535,8 @@ struct TraceArgs {
 int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field, const double* xi,
                      const double* phi, const double* logk, const double* qin, const double* c0,
                      const henry_opts_t* opts, const TraceArgs& tr, double* c_out, double* p_out, double* qoi_out,
-                     int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes, void* stream);
+                     int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes, void* stream,
+                     bool static_scratch = false);
 
 }  // namespace
 
@@ -497,6 +546,14 @@ int henry_solve_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolve
                       int32_t* iters, void* workspace, size_t ws_bytes, void* stream) {
     return solve_batch_impl(ctx, solves, nsolves, field, xi, phi, logk, qin, c0, opts, TraceArgs{}, c_out, p_out,
                             qoi_out, status, iters, workspace, ws_bytes, stream);
+}
+
+int henry_solve_batch_static(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
+                             const double* xi, const double* phi, const double* logk, const double* qin,
+                             const double* c0, const henry_opts_t* opts, double* c_out, double* p_out,
+                             double* qoi_out, int32_t* status, int32_t* iters, void* stream) {
+    return solve_batch_impl(ctx, solves, nsolves, field, xi, phi, logk, qin, c0, opts, TraceArgs{}, c_out, p_out,
+                            qoi_out, status, iters, nullptr, 0, stream, true);
 }
 
 int henry_solve_batch_trace(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field,
@@ -526,7 +583,8 @@ namespace {
 int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves, int32_t field, const double* xi,
                      const double* phi, const double* logk, const double* qin, const double* c0,
                      const henry_opts_t* opts, const TraceArgs& tr, double* c_out, double* p_out, double* qoi_out,
-                     int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes, void* stream) {
+                     int32_t* status, int32_t* iters, void* workspace, size_t ws_bytes, void* stream,
+                     bool static_scratch) {
     if (!ctx || nsolves < 0) return HENRY_EINVAL;
     if (nsolves == 0) return HENRY_OK;
     if (!solves) return HENRY_EINVAL;
@@ -546,9 +604,17 @@ int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves
     } else {
         return HENRY_EINVAL;
     }
-    if (!c_out || !qoi_out || !status || !workspace) return HENRY_EINVAL;
+    if (static_scratch) {
+        // nothing that allocates: no graph, no profiling events
+        if (o->steps_per_launch != 0 || o->profile != 0) return HENRY_EINVAL;
+        workspace = ctx->scratch;
+        ws_bytes = kStaticScratchBytes;
+    }
+    if (!c_out || !qoi_out || !status) return HENRY_EINVAL;
     size_t need = 0;
     if (int rc = henry_workspace_bytes(ctx, solves, nsolves, o, &need)) return rc;
+    if (static_scratch && !workspace) return HENRY_EHIP;
+    if (!workspace) return HENRY_EINVAL;
     if (ws_bytes < need) return HENRY_ENOMEM;
     if (((uintptr_t)workspace & 255) != 0) return HENRY_EINVAL;
 
@@ -593,21 +659,32 @@ int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves
     DeviceGuard dg(ctx->device);
     hipStream_t s0 = reinterpret_cast<hipStream_t>(stream);
     const size_t tbytes = sizeof(henry::SolveDesc) * (size_t)nsolves;
-    if (ctx->pinned) {
-        if (hipEventSynchronize(ctx->staging_done) != hipSuccess) return HENRY_EHIP;
-    }
-    if (ctx->pinned_bytes < tbytes) {
-        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-        ctx->pinned = nullptr;
-        ctx->pinned_bytes = 0;
-        if (hipHostMalloc(&ctx->pinned, tbytes, hipHostMallocDefault) != hipSuccess) return HENRY_ENOMEM;
-        ctx->pinned_bytes = tbytes;
-    }
-    std::memcpy(ctx->pinned, table.data(), tbytes);
     uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
     henry::SolveDesc* dtable = reinterpret_cast<henry::SolveDesc*>(ws);
-    if (hipMemcpyAsync(dtable, ctx->pinned, tbytes, hipMemcpyHostToDevice, s0) != hipSuccess) return HENRY_EHIP;
-    if (hipEventRecord(ctx->staging_done, s0) != hipSuccess) return HENRY_EHIP;
+    if (static_scratch) {
+        for (int first = 0; first < nsolves; first += kDescChunk) {
+            DescChunk ch{};
+            ch.first = first;
+            ch.count = std::min(kDescChunk, nsolves - first);
+            for (int k = 0; k < ch.count; ++k) ch.d[k] = table[first + k];
+            hipLaunchKernelGGL(desc_fill_kernel, dim3(1), dim3(kDescChunk), 0, s0, ch, dtable);
+        }
+        if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
+    } else {
+        if (ctx->pinned) {
+            if (hipEventSynchronize(ctx->staging_done) != hipSuccess) return HENRY_EHIP;
+        }
+        if (ctx->pinned_bytes < tbytes) {
+            if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+            ctx->pinned = nullptr;
+            ctx->pinned_bytes = 0;
+            if (hipHostMalloc(&ctx->pinned, tbytes, hipHostMallocDefault) != hipSuccess) return HENRY_ENOMEM;
+            ctx->pinned_bytes = tbytes;
+        }
+        std::memcpy(ctx->pinned, table.data(), tbytes);
+        if (hipMemcpyAsync(dtable, ctx->pinned, tbytes, hipMemcpyHostToDevice, s0) != hipSuccess) return HENRY_EHIP;
+        if (hipEventRecord(ctx->staging_done, s0) != hipSuccess) return HENRY_EHIP;
+    }
 
     henry::Launch lp{};
     lp.ws = ws;

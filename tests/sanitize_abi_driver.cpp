@@ -95,6 +95,8 @@ int main() {
                                 &d, &d, &d, 8, nullptr) == HENRY_EINVAL);
     EXPECT(henry_adjoint_batch(nullptr, ok.data(), 1, HENRY_FIELD_CLOSED3, &d, nullptr, nullptr, nullptr, &o, 10, 1e-8,
                                10, &d, nullptr, nullptr, nullptr, nullptr, &st, nullptr, &d, 8, nullptr) == HENRY_EINVAL);
+    EXPECT(henry_solve_batch_static(nullptr, ok.data(), 1, HENRY_FIELD_CLOSED3, &d, nullptr, nullptr, nullptr,
+                                    nullptr, &o, &d, nullptr, &d, &st, nullptr, nullptr) == HENRY_EINVAL);
     int32_t m[2] = {4, 4};
     EXPECT(mlmc_level_estimate(nullptr, 1, ok.data(), m, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr) == HENRY_EINVAL);
