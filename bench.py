@@ -388,9 +388,15 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs into the committed traffic record and exit")
     ap.add_argument("--pmc-workload", default="mlmc_L4", choices=tuple(TRAFFIC_PATHS))
+    ap.add_argument("--phase-timers", nargs="*", type=int, metavar="K", default=None,
+                    help="time the phases of the outer iteration of the 16 finest solves (256x128/800) alone with "
+                         "the instrumented build (compiled first if missing), for each cluster size K (default 4)")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, workload_name=args.pmc_workload)
+        return
+    if args.phase_timers is not None:
+        phase_timers(args.phase_timers or [4], args.tol)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the ensemble shards by sample across "
@@ -562,6 +568,53 @@ def main():
                 f.write(text + "\n")
     ctx.close()
     print(record_line(rec), flush=True)
+
+
+PHASES = {7: "step start", 13: "c update tail", 23: "residual p pass", 0: "residual p norms (reduction)",
+          1: "coarsen p", 9: "p level 0 down", 10: "p cluster levels down", 11: "p leader levels",
+          12: "p cluster levels up", 14: "p level 0 up", 2: "after p cycle", 15: "p update",
+          21: "residual c pass", 3: "residual c barrier", 4: "coarsen c", 17: "c level 0 down",
+          18: "c cluster levels down", 19: "c leader levels", 20: "c cluster levels up", 22: "c level 0 up",
+          5: "after c cycle", 6: "c update"}
+
+
+def phase_timers(clusters, tol):
+    """Microseconds per outer iteration of each phase of the 256x128/800
+    solves of the L = 4 workload (16 solves alone), on the leader's thread 0,
+    from the HENRY_PHASE_TIMERS build: slots 8..31 of each solve's scratch
+    region (100 MHz wall-clock ticks)."""
+    import paper_2302_07804_amd as hm
+    if not os.path.exists(hm.PHASE_TIMER_LIB_PATH):
+        hm.build(hm.PHASE_TIMER_LIB_PATH, defines=("HENRY_PHASE_TIMERS",))
+    hm.LIB_PATH = hm.PHASE_TIMER_LIB_PATH
+    hm.lib()
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx = hm.Context(hi.PHYS, 0)
+    n, grid = M_PER_LEVEL[-1], hi.level_grid(len(M_PER_LEVEL) - 1)
+    xi = torch.tensor(hm.henry_sample_xi(hi.SEED, 4, 0, n, 3), dtype=torch.float64, device=dev)
+    cells = grid[0] * grid[1]
+    for K in clusters:
+        opts = hm.make_opts(prec=hm.PREC_MIXED, tol=tol, max_outer=60, cluster=K)
+        hm.solve(ctx, [grid] * n, xi=xi, opts=opts)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = hm.solve(ctx, [grid] * n, xi=xi, opts=opts)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        ws = out["workspace"].cpu().numpy()
+        desc = (n * 48 + 255) // 256 * 256
+        sb = hm.henry_workspace_bytes([grid] * 2, opts) - hm.henry_workspace_bytes([grid], opts)
+        acc = np.zeros(24)
+        for k in range(n):
+            off = (desc + k * sb) // 8 + 17 * cells  # the scratch doubles follow the 17 FP64 arrays
+            acc += ws[off + 8:off + 32]
+        acc /= n
+        iters = float(out["iters"].cpu().numpy().mean())
+        per = {PHASES.get(k, str(k)): round(acc[k] * 0.01 / iters, 1) for k in range(24) if acc[k] > 0}
+        print(json.dumps(dict(cluster=K, wall_ms=round(1e3 * wall, 1), outer_per_step=round(iters / grid[2], 3),
+                              us_per_outer=round(acc.sum() * 0.01 / iters, 1), phases=per)), flush=True)
+    ctx.close()
 
 
 def run_kl(hm, torch, dev, args, log):

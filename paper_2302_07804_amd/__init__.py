@@ -45,21 +45,29 @@ class HenryError(RuntimeError):
         self.code = code
 
 
-def hipcc_command(out=LIB_PATH):
+# A build of the library whose solve kernel also accumulates wall-clock time
+# per phase of the outer iteration (HENRY_PHASE_TIMERS) into each solve's
+# scratch region; for measurement only, never the product path.
+PHASE_TIMER_LIB_PATH = os.path.join(_ROOT, "_build", "libhenry_phase_timers.so")
+
+
+def hipcc_command(out=LIB_PATH, defines=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     return [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument",
-            "-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc"),
-            "-o", out] + _SOURCES
+            "-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc")] + \
+        [f"-D{d}" for d in defines] + ["-o", out] + _SOURCES
 
 
-def build() -> str:
-    """Compile libhenry.so for gfx950 (always recompiles)."""
-    tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(hipcc_command(tmp), cwd=_HERE)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+def build(out: str = LIB_PATH, defines=()) -> str:
+    """Compile libhenry.so for gfx950 (always recompiles); `defines` are
+    preprocessor symbols (HENRY_PHASE_TIMERS for the instrumented build)."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    subprocess.check_call(hipcc_command(tmp, defines), cwd=_HERE)
+    os.replace(tmp, out)
+    return out
 
 
 class Phys(ct.Structure):

@@ -559,6 +559,30 @@ __device__ inline FaceFlux flux_left(const Phys& ph, double h, double q, double 
     return f;
 }
 
+// Wall-clock accumulators of the phases of one step (builds with
+// HENRY_PHASE_TIMERS only; wall_clock64 runs at a constant 100 MHz).
+// Slots 0..7, 13, 15, 21, 23: phases of the outer iteration (the residual
+// passes split into the pass and its reduction or barrier); 8..12, 14 and
+// 16..20, 22: parts of the pressure and of the transport V-cycle.
+struct PhaseClock {
+#ifdef HENRY_PHASE_TIMERS
+    uint64_t acc[24];
+    uint64_t last;
+    __device__ void init() {
+        for (int k = 0; k < 24; ++k) acc[k] = 0;
+        last = wall_clock64();
+    }
+    __device__ void tick(int k) {
+        const uint64_t t = wall_clock64();
+        acc[k] += t - last;
+        last = t;
+    }
+#else
+    __device__ void init() {}
+    __device__ void tick(int) {}
+#endif
+};
+
 // ------------------------------------------------------------------ FP64 residual
 // Operands of one cell's residual, loaded from clamped indices before any
 // arithmetic (no loads under boundary branches).
@@ -635,7 +659,8 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
 // The row bands are spread over all threads of the cluster; mode 0 ends
 // with the cluster-wide norms, mode 1 with a cluster barrier only.
 template <typename T>
-__device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out) {
+__device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out,
+                              PhaseClock* pcx = nullptr) {
     const int nx = S.nx, ny = S.ny;
     const int bs = ClusterTeam::size(), rk = ClusterTeam::rank();
     const int cw = nx < bs ? nx : bs;  // both powers of two
@@ -684,6 +709,7 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
             pP = a.pN; cP = a.cN;
         }
     }
+    if (pcx) pcx->tick(mode == 0 ? 23 : 21);
     if (mode == 0) {
         cluster_max2(mp, mc, red, np_out, nc_out);
         __syncthreads();
@@ -1117,7 +1143,11 @@ __device__ __attribute__((noinline)) void line_sweep_m(Level<T>& v0, int col) {
         const int li = g >> stl;
         const bool active = li < nlines;
         const int fixed = col + 2 * (active ? li : 0);
-        T cp[MS], y[MS], u[MS], w[MS];
+        // w (the response to iota_t) is zero above row m-2 before the back
+        // substitution, so afterwards w[q] = w[m-2] * prod_{k=q}^{m-3} (-cp[k]):
+        // it is carried as a running product instead of an array
+        T cp[MS], y[MS], u[MS];
+        T wlast = (T)0;
         T ar = (T)0, br = (T)1, cr = (T)0, dr = (T)0;
         // forward elimination of the interior rows, interface row kept aside
 #pragma unroll
@@ -1146,23 +1176,24 @@ __device__ __attribute__((noinline)) void line_sweep_m(Level<T>& v0, int col) {
                     const T inv = qdiv((T)1, den);
                     const T yprev = (q > 0) ? y[q > 0 ? q - 1 : 0] : (T)0;
                     const T uprev = (q > 0) ? u[q > 0 ? q - 1 : 0] : (T)0;
-                    const T wprev = (q > 0) ? w[q > 0 ? q - 1 : 0] : (T)0;
                     cp[q] = c * inv;
                     y[q] = (rhs - a * yprev) * inv;
                     u[q] = ((q == 0 ? -a : (T)0) - a * uprev) * inv;
-                    w[q] = ((q == m - 2 ? -c : (T)0) - a * wprev) * inv;
+                    if (q == m - 2) wlast = (-c - a * (T)0) * inv;
                 } else {
                     ar = a; br = st.d; cr = c; dr = rhs;
                 }
             }
         }
-        // back substitution of the interior rows (coupling to iota_t sits in w)
+        // back substitution of the interior rows (coupling to iota_t: the
+        // running product wrun, w[q] = 0 - cp[q] w[q + 1])
+        T wrun = wlast;
 #pragma unroll
         for (int q = MS - 2; q >= 0; --q) {
             if (q < m - 2) {
                 y[q] -= cp[q] * y[q + 1];
                 u[q] -= cp[q] * u[q + 1];
-                w[q] -= cp[q] * w[q + 1];
+                wrun = (T)0 - cp[q] * wrun;
             }
         }
         // interior rows next to the interfaces
@@ -1170,9 +1201,9 @@ __device__ __attribute__((noinline)) void line_sweep_m(Level<T>& v0, int col) {
         T yF = (T)0, uF = (T)0, wF = (T)1;  // first row of this lane (m == 1: iota_t itself)
 #pragma unroll
         for (int q = 0; q < MS; ++q) {
-            if (q == m - 2) { yL = y[q]; uL = u[q]; wL = w[q]; }
+            if (q == m - 2) { yL = y[q]; uL = u[q]; wL = wlast; }
         }
-        if (m >= 2) { yF = y[0]; uF = u[0]; wF = w[0]; }
+        if (m >= 2) { yF = y[0]; uF = u[0]; wF = m >= 2 ? wrun : (T)1; }
         // first row of the next lane of the same line
         const bool last = (t == TL - 1);
         const int src = last ? lane : lane + 1;
@@ -1209,12 +1240,15 @@ __device__ __attribute__((noinline)) void line_sweep_m(Level<T>& v0, int col) {
         const T left0 = __shfl(iota, t > 0 ? lane - 1 : lane, kWave);
         const T left = t > 0 ? left0 : (T)0;
         if (active) {
+            // rows from the bottom up, rebuilding w[q] as in the back substitution
+            T wq = wlast;
 #pragma unroll
-            for (int q = 0; q < MS; ++q) {
+            for (int q = MS - 1; q >= 0; --q) {
                 if (q < m) {
                     const int k = t * m + q;
                     const int i = kXLine ? k : fixed, j = kXLine ? fixed : k;
-                    v.x[j * v.nx + i] = (q < m - 1) ? y[q] + u[q] * left + w[q] * iota : iota;
+                    if (q < m - 2) wq = (T)0 - cp[q] * wq;
+                    v.x[j * v.nx + i] = (q < m - 1) ? y[q] + u[q] * left + wq * iota : iota;
                 }
             }
         }
@@ -1260,29 +1294,6 @@ __device__ void line_smooth(Level<T>& v, bool ylines) {
         line_sweep<T, true, kTrans, Team, AS>(v, 1);
     }
 }
-
-// Wall-clock accumulators of the phases of one step (builds with
-// HENRY_PHASE_TIMERS only; wall_clock64 runs at a constant 100 MHz).
-// Slots 0..7: phases of the outer iteration; 8..14 and 16..22: parts of
-// the pressure and of the transport V-cycle.
-struct PhaseClock {
-#ifdef HENRY_PHASE_TIMERS
-    uint64_t acc[24];
-    uint64_t last;
-    __device__ void init() {
-        for (int k = 0; k < 24; ++k) acc[k] = 0;
-        last = wall_clock64();
-    }
-    __device__ void tick(int k) {
-        const uint64_t t = wall_clock64();
-        acc[k] += t - last;
-        last = t;
-    }
-#else
-    __device__ void init() {}
-    __device__ void tick(int) {}
-#endif
-};
 
 // ------------------------------------------------------------------ V-cycles
 // Downward leg on level l (address space AS; level l+1 in ASN): smooth,
@@ -1471,7 +1482,8 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
     pc.tick(7);
     for (int it = 0; it < max_outer; ++it) {
         double np, nc;
-        residual_pass(ph, S, 0, red, np, nc);
+        pc.tick(13);
+        residual_pass(ph, S, 0, red, np, nc, &pc);
         pc.tick(0);
         if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) return 2;
         if (np <= tol && nc <= tol) return 0;
@@ -1485,7 +1497,8 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
             S.p[idx] += (double)S.lv[0].x[pidx(idx - j * S.nx, j, S.nx)];
         }
         ClusterTeam::sync();
-        residual_pass(ph, S, 1, red, np, nc);
+        pc.tick(15);
+        residual_pass(ph, S, 1, red, np, nc, &pc);
         pc.tick(3);
         coarsen_cluster<T, true>(S);
         pc.tick(4);
