@@ -139,6 +139,10 @@ enum : int { kP, kC, kCn, kPhi, kK, kPp, kTx, kTy, kWx, kWy, kIsc, kC2, kP2, kC3
 constexpr int kScratch = 64;
 constexpr int kClusterFlags = 32, kClusterErr = 36, kClusterGen = 37, kClusterXcc = 40, kClusterSlots = 48;
 constexpr int kMaxCluster = 8;
+// the barrier polls the K arrival counts and the error flag in one load:
+// the flag sits past the last count, within one wavefront's lanes
+static_assert((kClusterErr - kClusterFlags) * 2 >= kMaxCluster && (kClusterErr - kClusterFlags) * 2 < 64,
+              "cluster error flag placement");
 
 template <typename T>
 __host__ __device__ inline int64_t solve_bytes(int nx, int ny) {
@@ -373,7 +377,11 @@ __device__ inline int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) 
 // Every workgroup of a cluster waits until all K members have arrived; all
 // memory operations before the call are visible to every member after it.
 // Wavefront 0 publishes the member's arrival count and polls the K counts
-// with one load per lane.
+// and the cluster's error flag with one load per lane (lane k < K: member
+// k's count; the lane at the error flag's offset: the flag), relaxed, so
+// that one poll is one L2 round trip; one acquire fence after the counts
+// are all there makes the members' stores visible.  The wall clock is read
+// every 16 polls only.
 __device__ inline void cluster_barrier() {
     __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached L2
     __syncthreads();
@@ -385,19 +393,24 @@ __device__ inline void cluster_barrier() {
                 if (g_cl.local) __hip_atomic_store(g_cl.flags + g_cl.member, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 else __hip_atomic_store(g_cl.flags + g_cl.member, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
-            const unsigned* f = g_cl.flags + (lane < g_cl.K ? lane : 0);
+            const int eoff = (int)(g_cl.err - g_cl.flags);  // the error flag's offset (>= K)
+            const bool is_err = lane == eoff;
+            const unsigned* f = g_cl.flags + (lane < g_cl.K || is_err ? lane : 0);
             const uint64_t t0 = wall_clock64();
             bool failed = false;
-            while (true) {
-                const unsigned v = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if (__all((int)(v - gen) >= 0)) break;
-                if (__hip_atomic_load(g_cl.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                    wall_clock64() - t0 > g_cl.wait) {
+            for (unsigned polls = 1;; ++polls) {
+                const unsigned v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__any(is_err && v != 0u)) {
                     failed = true;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(1);
+                if (__all(is_err || (int)(v - gen) >= 0)) break;
+                if ((polls & 15u) == 0u && wall_clock64() - t0 > g_cl.wait) {
+                    failed = true;
+                    break;
+                }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (failed && lane == 0) {
                 __hip_atomic_store(g_cl.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 g_cl.failed = 1;
