@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     extern __shared__ __align__(256) uint8_t lds_levels[];
     __shared__ Solve<T> S;
     __shared__ Adj A;
-    __shared__ double red[16];
+    __shared__ double red[32];
     int cid, member;
     cluster_of_block(lp.cluster, cid, member);
     if (cid >= lp.nsolves) return;

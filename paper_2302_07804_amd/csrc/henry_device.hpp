@@ -8,14 +8,16 @@
 //
 //   repeat
 //     R = R(p, c)                                   FP64, scaled max norms
-//     (A_pp) dp = -R^p    one V(2,2) cycle, red-black Gauss-Seidel   inner T
-//     p += dp                                                         FP64
-//     S = R^c(p, c) - c R^p(p, c)                                     FP64
+//     stop if both norms <= tol
+//     unless |R^p| <= tol:
+//       (A_pp) dp = -R^p  one V(2,2) cycle, red-black Gauss-Seidel   inner T
+//       p += dp                                                       FP64
+//     R = R(p, c), S = R^c - c R^p                                    FP64
+//     stop if both norms <= tol
 //     (A_cc) dc = -S      one V-cycle, zebra x-lines before the coarse
 //                         correction, x- (global levels) or y-lines
 //                         (LDS levels) after                      inner T
 //     c += dc                                                         FP64
-//   until both scaled residual norms <= tol
 //
 // Each step starts from an extrapolation through the last converged states
 // (interpolating polynomials up to cubic, then on long solves the
@@ -291,6 +293,18 @@ __device__ inline double block_max(double v, double* red) {
     for (int k = 1; k < nw; ++k) r = nanmax(r, red[k]);
     return r;
 }
+__device__ inline void block_max2(double& a, double& b, double* red) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    a = wave_max(a);
+    b = wave_max(b);
+    __syncthreads();
+    if (lane == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
+    __syncthreads();
+    double ra = red[0], rb = red[1];
+    for (int k = 1; k < nw; ++k) { ra = nanmax(ra, red[2 * k]); rb = nanmax(rb, red[2 * k + 1]); }
+    a = ra;
+    b = rb;
+}
 __device__ inline double block_sum(double v, double* red) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
     v = wave_sum(v);
@@ -470,7 +484,8 @@ __device__ inline void cluster_init(int K, int member, double* sp, uint64_t wait
 // Maxima of two per-thread values over the whole cluster, in a fixed order
 // (NaN propagates); every thread of every member gets the same pair.
 __device__ inline void cluster_max2(double a, double b, double* red, double& ra, double& rb) {
-    const double pa = block_max(a, red), pb = block_max(b, red);
+    double pa = a, pb = b;
+    block_max2(pa, pb, red);
     if (g_cl.K == 1) {
         ra = pa; rb = pb;
         return;
@@ -645,6 +660,7 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
         S.rout_p[idx] = Rp;
         S.rout_c[idx] = Rc;
     } else {
+        mp = nanmax(mp, fabs(Rp * a.sc));
         L0.mx[idx] = (T)(q.he ? fe.M : 0.0);
         L0.dx[idx] = (T)(q.he ? fe.dif : 0.0);
         L0.my[idx] = (T)(q.hn ? fn.M : 0.0);
@@ -723,13 +739,8 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
         }
     }
     if (pcx) pcx->tick(mode == 0 ? 23 : 21);
-    if (mode == 0) {
-        cluster_max2(mp, mc, red, np_out, nc_out);
-        __syncthreads();
-    } else {
-        np_out = nc_out = 0.0;
-        ClusterTeam::sync();
-    }
+    cluster_max2(mp, mc, red, np_out, nc_out);
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ coefficient coarsening
@@ -1446,6 +1457,55 @@ __device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr, bool coarse_coeffs
     }
 }
 
+// Batched per-cell loops of the step: every thread first loads its kB cells
+// (kB round trips in flight at once), then stores; one cell per loop trip
+// would wait out a full memory latency per cell.
+template <int kB>
+__device__ inline void extrapolate_field(double* u0, double* u1, double* u2, double* u3, double* u4, int order, int n,
+                                         int rk, int ts) {
+    for (int base = rk; base < n; base += kB * ts) {
+        double a0[kB], a1[kB], a2[kB], a3[kB], a4[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int idx = base + k * ts;
+            if (idx < n) {
+                a0[k] = u0[idx]; a1[k] = u1[idx]; a2[k] = u2[idx]; a3[k] = u3[idx];
+                a4[k] = order == 4 ? u4[idx] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int idx = base + k * ts;
+            if (idx < n) {
+                double e = a0[k];
+                if (order == 1) e = 2.0 * a0[k] - a1[k];
+                else if (order == 2) e = 3.0 * a0[k] - 3.0 * a1[k] + a2[k];
+                else if (order == 3) e = 4.0 * a0[k] - 6.0 * a1[k] + 4.0 * a2[k] - a3[k];
+                else if (order == 4) e = (16.0 * a0[k] - 14.0 * a1[k] - 4.0 * a2[k] + 11.0 * a3[k] - 4.0 * a4[k]) * 0.2;
+                u0[idx] = e; u4[idx] = a3[k]; u3[idx] = a2[k]; u2[idx] = a1[k]; u1[idx] = a0[k];
+            }
+        }
+    }
+}
+
+template <int kB, typename T, class XI>
+__device__ inline void add_correction(double* u, const T* x, int n, int rk, int ts, XI xi) {
+    for (int base = rk; base < n; base += kB * ts) {
+        double uv[kB];
+        T xv[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int idx = base + k * ts;
+            if (idx < n) { uv[k] = u[idx]; xv[k] = x[xi(idx)]; }
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int idx = base + k * ts;
+            if (idx < n) u[idx] = uv[k] + (double)xv[k];
+        }
+    }
+}
+
 // One implicit Euler step (Sec. 2.3) from the state u^n = (S.p, S.c):
 // saves u^n in S.cn / S.pp (c^n is the previous time level of the
 // residual), shifts the older states, and runs the defect correction until
@@ -1465,32 +1525,8 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
                              PhaseClock& pc, int order = 0) {
     const int n = S.n;
     const int rk = ClusterTeam::rank(), ts = ClusterTeam::size();
-    for (int idx = rk; idx < n; idx += ts) {
-        const double c0 = S.c[idx], p0 = S.p[idx];
-        const double c1 = S.cn[idx], p1 = S.pp[idx];
-        const double c2 = S.c2[idx], p2 = S.p2[idx];
-        if (order == 1) {
-            S.c[idx] = 2.0 * c0 - c1;
-            S.p[idx] = 2.0 * p0 - p1;
-        } else if (order == 2) {
-            S.c[idx] = 3.0 * c0 - 3.0 * c1 + c2;
-            S.p[idx] = 3.0 * p0 - 3.0 * p1 + p2;
-        } else if (order == 3) {
-            S.c[idx] = 4.0 * c0 - 6.0 * c1 + 4.0 * c2 - S.c3[idx];
-            S.p[idx] = 4.0 * p0 - 6.0 * p1 + 4.0 * p2 - S.p3[idx];
-        } else if (order == 4) {
-            S.c[idx] = (16.0 * c0 - 14.0 * c1 - 4.0 * c2 + 11.0 * S.c3[idx] - 4.0 * S.c4[idx]) * 0.2;
-            S.p[idx] = (16.0 * p0 - 14.0 * p1 - 4.0 * p2 + 11.0 * S.p3[idx] - 4.0 * S.p4[idx]) * 0.2;
-        }
-        S.c4[idx] = S.c3[idx];
-        S.p4[idx] = S.p3[idx];
-        S.c3[idx] = c2;
-        S.p3[idx] = p2;
-        S.c2[idx] = c1;
-        S.p2[idx] = p1;
-        S.cn[idx] = c0;
-        S.pp[idx] = p0;
-    }
+    extrapolate_field<4>(S.c, S.cn, S.c2, S.c3, S.c4, order, n, rk, ts);
+    extrapolate_field<4>(S.p, S.pp, S.p2, S.p3, S.p4, order, n, rk, ts);
     ClusterTeam::sync();
     pc.tick(7);
     for (int it = 0; it < max_outer; ++it) {
@@ -1501,23 +1537,30 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
         if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) return 2;
         if (np <= tol && nc <= tol) return 0;
         iters += 1.0;
-        coarsen_cluster<T, false>(S);
-        pc.tick(1);
-        vcycle<T, false>(S, &pc, true);
-        pc.tick(2);
-        for (int idx = rk; idx < n; idx += ts) {
-            const int j = idx >> log2i(S.nx);
-            S.p[idx] += (double)S.lv[0].x[pidx(idx - j * S.nx, j, S.nx)];
+        if (np > tol) {  // a pressure residual within the tolerance needs no correction
+            coarsen_cluster<T, false>(S);
+            pc.tick(1);
+            vcycle<T, false>(S, &pc, true);
+            pc.tick(2);
+            const int nx = S.nx, sx = log2i(S.nx);
+            add_correction<8>(S.p, S.lv[0].x, n, rk, ts, [=](int idx) {
+                const int j = idx >> sx;
+                return pidx(idx - j * nx, j, nx);
+            });
+            ClusterTeam::sync();
         }
-        ClusterTeam::sync();
         pc.tick(15);
+        // the salt system's pass evaluates both residuals at the updated
+        // state: the step may end here, before the salt cycle
         residual_pass(ph, S, 1, red, np, nc, &pc);
+        if (!(np == np) || !(nc == nc) || np > 1e300 || nc > 1e300) return 2;
+        if (np <= tol && nc <= tol) return 0;
         pc.tick(3);
         coarsen_cluster<T, true>(S);
         pc.tick(4);
         vcycle<T, true>(S, &pc, true);
         pc.tick(5);
-        for (int idx = rk; idx < n; idx += ts) S.c[idx] += (double)S.lv[0].x[idx];
+        add_correction<8>(S.c, S.lv[0].x, n, rk, ts, [](int idx) { return idx; });
         ClusterTeam::sync();
         pc.tick(6);
     }
@@ -1619,7 +1662,7 @@ template <typename T>
 __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kernel(Launch lp) {
     extern __shared__ __align__(256) uint8_t lds_levels[];
     __shared__ Solve<T> S;
-    __shared__ double red[16];
+    __shared__ double red[32];
     int cid, member;
     cluster_of_block(lp.cluster, cid, member);
     if (cid >= lp.nsolves) return;
@@ -1721,7 +1764,7 @@ __global__ void __launch_bounds__(1024) henry_residual_kernel(Launch lp, const d
                                                               const double* cn, double* rp, double* rc) {
     extern __shared__ __align__(256) uint8_t lds_levels[];  // launched with none: no level in LDS
     __shared__ Solve<float> S;
-    __shared__ double red[16];
+    __shared__ double red[32];
     const SolveDesc d = lp.descs[blockIdx.x];
     const Phys& ph = lp.ph;
     if (threadIdx.x == 0) {
