@@ -377,6 +377,9 @@ def main():
                     help="run only the 1024x512 KL workload (for counter runs) and print its record")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=None, metavar="JSON",
+                    help="autotuner choices: used as they are when the file holds every grid, else tuned and "
+                         "written there (counter runs reuse the bench's launch configuration this way)")
     ap.add_argument("--extras", action="store_true",
                     help="also run the method's other workloads (adjoint, adaptive MLMC, QMC reference, the "
                          "paper's set-up); their records go to stderr and --extras-out, not to stdout")
@@ -464,7 +467,7 @@ def main():
     tuned = {}
     if not args.no_tune:
         t = time.time()
-        res = hm.autotune(ctx, grids, xi, opts)
+        res = hm.autotune(ctx, grids, xi, opts, cache_path=args.tune_cache)
         tuned = {f"{nx}x{nx // 2}": v[0] for (nx, _), v in res.items()}
         log(f"autotune ({time.time() - t:.1f} s): {tuned}")
     for w in range(args.warmup):
