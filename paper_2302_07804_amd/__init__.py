@@ -789,7 +789,7 @@ def _short_batch(solves, target=TUNE_FRAC_TARGET, min_steps=8):
 
 def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int = 8, max_solves: int = 1024,
              candidates=(64, 128, 256, 512, 1024), cache_path: str | None = None, clusters=(1, 2, 4, 8),
-             plans=STREAM_PLANS, model=None, reps: int = 2):
+             plans=STREAM_PLANS, model=None, reps: int = 2, trial_frac: int = 1):
     """Fill the context's tuning cache for the grids of `solves` by timing
     the candidates on short runs of the caller's own batch:
       1. threads per solve-workgroup, per grid: the first `tune_steps` steps
@@ -799,8 +799,13 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
          grid after another in cost order (eq:workpl: n_l r_l), with at
          most 256 workgroups per group; then the stream plan of the
          one-workgroup groups (STREAM_PLANS).  Each candidate times the
-         whole batch shortened by a common factor that keeps every time
-         step (_short_batch), between events on the caller's stream.
+         whole batch, between events on the caller's stream, or with
+         trial_frac > 1 the batch shortened by about that factor keeping
+         every time step (_short_batch).  The whole batch is the default:
+         the cluster sizes of the largest grid trade its critical path
+         against the CUs left to the other groups, a balance of a few
+         percent that the early steps alone misjudge (L = 4 MLMC batch:
+         4 against 8 workgroups per 256x128 solve, 411 and 400 ms).
     Each candidate runs `reps` times and its fastest run counts.  The
     choices change no result (bitwise).  With cache_path, choices found
     there are used as they are and new ones are written back.  Returns
@@ -848,7 +853,7 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
             times[t] = best
         threads[nx] = (min(times, key=times.get), times)
     # ---- 2. clusters and stream plan on the shortened whole batch
-    f, short = _short_batch(solves)
+    f, short = _short_batch(solves, target=trial_frac)
     ph = dict(ctx.phys)
     ph["T"] = ph["T"] / f
     tctx = Context(ph, ctx.device)
