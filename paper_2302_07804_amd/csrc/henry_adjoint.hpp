@@ -473,6 +473,9 @@ __global__ void __launch_bounds__(512) henry_adjoint_kernel(Launch lp, AdjLaunch
     __syncthreads();
     if (lp.cluster > 1) cluster_init(lp.cluster, member, S.scratch, lp.cluster_wait);
     else cluster_init_single();
+    // no line staging here: the transposed cycles reuse the LDS levels'
+    // coefficients from one cycle to the next, so nothing may overlay them
+    if (threadIdx.x == 0) cluster_stage(lds_levels, 0, line_stage_bytes_per_wave<T>());
     const int n = S.n, N = d.nsteps, k = A.k;
     PhaseClock pc;
     pc.init();

@@ -55,6 +55,23 @@ size_t lds_bytes(int nx, int ny, int prec) {
                         : henry::lds_level_bytes<double>(nx, ny, kLdsCells, lds_block_cells(prec)));
 }
 
+// Dynamic LDS of a solve or adjoint launch: the LDS levels, or, for grids
+// of 512 or 1024 cells per row shared by clusters, the line staging buffers
+// of every wavefront if they take more (they overlay the levels; see
+// henry::line_sweep_x_staged), as long as the workgroup's LDS holds them
+// beside the kernel's static LDS (a few KB).
+constexpr size_t kLdsStageCap = 150 * 1024;
+size_t launch_lds_bytes(int nx, int ny, int prec, int threads, int cluster) {
+    size_t b = lds_bytes(nx, ny, prec);
+    if (cluster > 1 && nx >= 512) {
+        const size_t per_wave = (size_t)(prec == HENRY_PREC_MIXED ? henry::line_stage_bytes_per_wave<float>()
+                                                                  : henry::line_stage_bytes_per_wave<double>());
+        const size_t st = (size_t)(threads / 64) * per_wave;
+        if (st <= kLdsStageCap) b = std::max(b, st);
+    }
+    return b;
+}
+
 // Device memory of the allocation-free entry point (henry_solve_batch_static):
 // every GPU the library runs on holds one copy of this array until the
 // process ends.  Host code never uses the array's name as an address: each
@@ -287,7 +304,8 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
         // global step s * rmax / r; one chunk when steps_per_launch == 0
         l.lds_cells = kLdsCells;
         l.lds_block_cells = lds_block_cells(prec);
-        const size_t lds = lds_bytes(G.nx, G.ny, prec);
+        const size_t lds = launch_lds_bytes(G.nx, G.ny, prec, G.threads, K);
+        l.lds_bytes = (int32_t)lds;
         const int chunk = spl > 0 ? spl : rmax;
         if (profile) {
             henry_group_time_t& pt = ctx->prof[gi];
@@ -1064,7 +1082,8 @@ int henry_adjoint_batch(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsol
         hipLaunchKernelGGL(henry::henry_fields_kernel, dim3(nb), dim3(256), 0, st, l);
         l.lds_cells = kLdsCells;
         l.lds_block_cells = lds_block_cells(prec);
-        const size_t lds = lds_bytes(G.nx, G.ny, prec);
+        const size_t lds = lds_bytes(G.nx, G.ny, prec);  // no line staging in the adjoint kernel
+        l.lds_bytes = (int32_t)lds;
         if (prec == HENRY_PREC_MIXED)
             hipLaunchKernelGGL(henry::henry_adjoint_kernel<float>, dim3(nblk), dim3(G.threads), lds, st, l, al);
         else

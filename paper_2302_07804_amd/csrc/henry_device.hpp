@@ -85,6 +85,7 @@ struct Launch {
     int32_t g_total;         // global steps of the whole batch (max nsteps)
     int32_t lds_cells;       // multigrid levels with at most this many cells live in LDS (wavefront 0)
     int32_t lds_block_cells; // levels 1.. with at most this many cells also live in LDS (whole workgroup)
+    int32_t lds_bytes;       // dynamic LDS of the launch (the LDS levels, or the line staging if larger)
     int32_t xi_dim;          // coefficients per solve in xi (3 closed form, 41 KL)
     const double* kl_modes;  // KL: sqrt(lam_k) e_k at the cells of this group's grid, [20][n]
     double kl_sigma_phi, kl_sigma_logk;
@@ -383,6 +384,8 @@ struct ClusterState {
     int local;       // all members on one XCD
     int failed;
     uint64_t wait;   // bound of one wait (wall-clock ticks)
+    uint8_t* stage;  // the dynamic LDS, as line staging buffers on the cluster levels
+    int stage_waves; // wavefronts whose staging buffer fits in it
 };
 __shared__ ClusterState g_cl;
 
@@ -444,6 +447,13 @@ struct ClusterTeam {
         else cluster_barrier();
     }
 };
+
+// The launch's dynamic LDS as line staging buffers (thread 0; read after the
+// next workgroup barrier).
+__device__ inline void cluster_stage(uint8_t* lds, int lds_bytes, int64_t per_wave) {
+    g_cl.stage = lds;
+    g_cl.stage_waves = (int)(lds_bytes / per_wave);
+}
 
 // Cluster of one workgroup (the adjoint kernel, small grids).
 __device__ inline void cluster_init_single() {
@@ -1286,9 +1296,160 @@ __device__ __attribute__((noinline)) void line_sweep_m(Level<T>& v0, int col) {
 // touches half as many (or fewer) cache lines as with one column of strided
 // rows.  The wavefront-team levels (at most 512 cells) have lines of at most
 // 32 cells: two rows per lane.
+// x-lines of 512 and 1024 cells on the cluster levels (one wavefront per
+// line, MS = 8 or 16 rows per lane).  line_sweep_m gathers a lane's MS
+// consecutive cells, so each of its load instructions touches 32 cache lines
+// at 8 bytes each, and the lines are gone from L1 and L2 before the lane
+// comes back for the rest of them.  Here the wavefront forms each row's
+// coefficients (the same stencil arithmetic) from coalesced loads, 64
+// consecutive cells per instruction, into its own LDS buffer, and each lane
+// reads its segment back from there for the same elimination (results are
+// bitwise those of line_sweep_m).  A 1024-cell row is staged in two halves
+// of 512 (lanes 0-31 eliminate the first, 32-63 the second).  The buffers
+// overlay the LDS levels, which are dead while the cluster runs its levels
+// in the forward solve: every cycle's leader rebuilds them (coarse_coeffs)
+// after the cluster's downward leg and is done with them before its upward
+// leg.  The adjoint's transposed cycles keep them from cycle to cycle, so
+// its kernel turns the staging off (g_cl.stage_waves = 0).  Padding of one
+// element per segment keeps the segment reads free of bank conflicts (lane
+// stride MS + 1).
+constexpr int kStageCells = 512;
+constexpr int kStageElems = kStageCells + kStageCells / 8;  // one pad per segment of >= 8 cells
+template <typename T>
+__host__ __device__ constexpr int64_t line_stage_bytes_per_wave() { return 4 * (int64_t)kStageElems * (int64_t)sizeof(T); }
+
+template <typename T, bool kTrans, int MS>
+__device__ __attribute__((noinline)) void line_sweep_x_staged(Level<T>& v0, int col) {
+    static_assert(MS == 8 || MS == 16, "staged x-lines are 512 or 1024 cells");
+    constexpr int NH = kWave * MS / kStageCells;  // halves of a row
+    const LV<T, 1> v(v0);
+    const int nlines = (v.ny - col + 1) >> 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    T* buf = reinterpret_cast<T*>(g_cl.stage) + (int64_t)(threadIdx.x / kWave) * 4 * kStageElems;
+    auto As = as_ptr<3>(buf);
+    auto Cs = as_ptr<3>(buf + kStageElems);
+    auto Ds = as_ptr<3>(buf + 2 * kStageElems);
+    auto Rs = as_ptr<3>(buf + 3 * kStageElems);
+    const int waves = ClusterTeam::size() / kWave, wrank = ClusterTeam::rank() / kWave;
+    const int t = lane;
+    for (int l0 = 0; l0 < nlines; l0 += waves) {  // the same trip count in every lane
+        const int li = l0 + wrank;
+        const bool active = li < nlines;
+        const int j = col + 2 * (active ? li : 0);
+        T cp[MS], y[MS], u[MS];
+        T wlast = (T)0;
+        T ar = (T)0, br = (T)1, cr = (T)0, dr = (T)0;
+        for (int hh = 0; hh < NH; ++hh) {
+            // coefficients of cells hh * 512 + r * 64 + lane, coalesced
+#pragma unroll 2
+            for (int r = 0; r < kStageCells / kWave; ++r) {
+                const int kl = r * kWave + lane;
+                const Nb nb(hh * kStageCells + kl, j, v.nx, v.ny);
+                const Stencil<T> st = stencil<T, true, kTrans>(v, nb, j);
+                T rhs = v.b[nb.idx];
+                const T xS = v.x[nb.s], xN = v.x[nb.n];
+                rhs += st.s * xS;
+                rhs += st.n * xN;
+                const int si = kl + kl / MS;
+                As[si] = -st.w;
+                Cs[si] = -st.e;
+                Ds[si] = st.d;
+                Rs[si] = rhs;
+            }
+            WaveTeam::sync();
+            // forward elimination of the lanes whose segment lies in this half
+            if (t * MS / kStageCells == hh) {
+                const int s0 = (t * MS - hh * kStageCells) / MS * (MS + 1);
+#pragma unroll
+                for (int q = 0; q < MS; ++q) {
+                    const T a = As[s0 + q], c = Cs[s0 + q], d = Ds[s0 + q], rhs = Rs[s0 + q];
+                    if (q < MS - 1) {
+                        const T den = (q > 0) ? d - a * cp[q > 0 ? q - 1 : 0] : d;
+                        const T inv = qdiv((T)1, den);
+                        const T yprev = (q > 0) ? y[q > 0 ? q - 1 : 0] : (T)0;
+                        const T uprev = (q > 0) ? u[q > 0 ? q - 1 : 0] : (T)0;
+                        cp[q] = c * inv;
+                        y[q] = (rhs - a * yprev) * inv;
+                        u[q] = ((q == 0 ? -a : (T)0) - a * uprev) * inv;
+                        if (q == MS - 2) wlast = (-c - a * (T)0) * inv;
+                    } else {
+                        ar = a; br = d; cr = c; dr = rhs;
+                    }
+                }
+            }
+            WaveTeam::sync();  // the buffer is refilled by the next half or line
+        }
+        // back substitution of the interior rows (coupling to iota_t: the
+        // running product wrun, w[q] = 0 - cp[q] w[q + 1])
+        T wrun = wlast;
+#pragma unroll
+        for (int q = MS - 2; q >= 0; --q) {
+            if (q < MS - 2) {
+                y[q] -= cp[q] * y[q + 1];
+                u[q] -= cp[q] * u[q + 1];
+                wrun = (T)0 - cp[q] * wrun;
+            }
+        }
+        const T yL = y[MS - 2], uL = u[MS - 2], wL = wlast;
+        const T yF = y[0], uF = u[0], wF = wrun;
+        // first row of the next lane of the same line
+        const bool last = (t == kWave - 1);
+        const int src = last ? lane : lane + 1;
+        T yN = __shfl(yF, src, kWave), uN = __shfl(uF, src, kWave), wN = __shfl(wF, src, kWave);
+        if (last) { yN = (T)0; uN = (T)0; wN = (T)0; cr = (T)0; }
+        T A = ar * uL;
+        T B = br + ar * wL + cr * uN;
+        T C = cr * wN;
+        T D = dr - ar * yL - cr * yN;
+        // parallel cyclic reduction over the 64 interface equations
+        for (int sft = 1; sft < kWave; sft <<= 1) {
+            const bool hasL = t >= sft, hasR = t + sft < kWave;
+            const int l = hasL ? lane - sft : lane, r = hasR ? lane + sft : lane;
+            const T Al = __shfl(A, l, kWave), Bl = __shfl(B, l, kWave), Cl = __shfl(C, l, kWave),
+                    Dl = __shfl(D, l, kWave);
+            const T Ar = __shfl(A, r, kWave), Br = __shfl(B, r, kWave), Cr = __shfl(C, r, kWave),
+                    Dr = __shfl(D, r, kWave);
+            T nA = (T)0, nB = B, nC = (T)0, nD = D;
+            if (hasL) {
+                const T k1 = qdiv(A, Bl);
+                nA = -Al * k1;
+                nB -= Cl * k1;
+                nD -= Dl * k1;
+            }
+            if (hasR) {
+                const T k2 = qdiv(C, Br);
+                nC = -Cr * k2;
+                nB -= Ar * k2;
+                nD -= Dr * k2;
+            }
+            A = nA; B = nB; C = nC; D = nD;
+        }
+        const T iota = qdiv(D, B);
+        const T left0 = __shfl(iota, t > 0 ? lane - 1 : lane, kWave);
+        const T left = t > 0 ? left0 : (T)0;
+        if (active) {
+            // rows from the bottom up, rebuilding w[q] as in the back substitution
+            T wq = wlast;
+#pragma unroll
+            for (int q = MS - 1; q >= 0; --q) {
+                if (q < MS - 2) wq = (T)0 - cp[q] * wq;
+                v.x[j * v.nx + t * MS + q] = (q < MS - 1) ? y[q] + u[q] * left + wq * iota : iota;
+            }
+        }
+    }
+    ClusterTeam::sync();
+}
+
 template <typename T, bool kXLine, bool kTrans = false, class Team = BlockTeam, int AS = 0>
 __device__ void line_sweep(Level<T>& v, int col) {
     const int len = kXLine ? v.nx : v.ny;  // 2 .. 1024, a power of two
+    if constexpr (kXLine && AS == 1 && std::is_same<Team, ClusterTeam>::value) {
+        if (len >= 512 && g_cl.K > 1 && (int)(blockDim.x / kWave) <= g_cl.stage_waves) {
+            if (len == 512) line_sweep_x_staged<T, kTrans, 8>(v, col);
+            else line_sweep_x_staged<T, kTrans, 16>(v, col);
+            return;
+        }
+    }
     if constexpr (std::is_same<Team, WaveTeam>::value) {
         line_sweep_m<T, kXLine, kTrans, 2, Team, AS>(v, col);
     } else if constexpr (kXLine) {
@@ -1683,6 +1844,7 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
     double* sp = S.scratch;
     if (lp.cluster > 1) cluster_init(lp.cluster, member, sp, lp.cluster_wait);
     else cluster_init_single();
+    if (threadIdx.x == 0) cluster_stage(lds_levels, lp.lds_bytes, line_stage_bytes_per_wave<T>());
     const int n = S.n;
     // scratch: [0] = q, [1] = status, [2] = iterations, [3] = converged
     // states in a row (the initial state counts as one); written by the
