@@ -133,8 +133,9 @@ __host__ __device__ inline int64_t level_bytes(int nx, int ny) {
 //           seawater face; 0 above the top row),
 //   isc     residual scale tau / (h^2 phi_P rho0),
 // then the older states c2, p2 (u^{n-2}), c3, p3 (u^{n-3}) and c4, p4
-// (u^{n-4}) of the extrapolated initial guess, then kScratch doubles of scratch: [0] recharge, [1] status, [2] outer
-// iterations, [3] converged states in a row, [8..31] phase timers of builds with
+// (u^{n-4}) of the extrapolated initial guess (their roles rotate: bind_history), then kScratch doubles of
+// scratch: [0] recharge, [1] status, [2] outer iterations, [3] converged states in a row, [4] the history's
+// rotation at the end of a launch, [8..31] phase timers of builds with
 // HENRY_PHASE_TIMERS, [32..63] the state of a cluster of workgroups sharing the solve (the members'
 // 32-bit arrival counts in [32..35], the error flag in [36], barriers passed [37], the members' XCD
 // ids [40..47], their partial residual norms [48..63]).
@@ -195,6 +196,7 @@ struct Solve {
     int lb;        // first level whose arrays live in LDS (lb <= lds_from)
     int lc;        // levels 0 .. lc-1 are run by the whole cluster (0 with one workgroup)
     int hand;      // level lc is in LDS and fed by the cluster through its global copy hg
+    int hist;      // rotation of the state history (see bind_history)
     double h, tau;
     double q;  // recharge (m/s)
     double *p, *c, *cn, *phi, *K, *pp, *tx, *ty, *wx, *wy, *isc, *c2, *p2, *c3, *p3, *c4, *p4, *scratch;
@@ -224,6 +226,26 @@ __host__ __device__ inline int64_t lds_level_bytes(int nx, int ny, int lds_cells
     return b;
 }
 
+// The state history: five arrays per field hold the iterate and the four
+// converged states before it, u^n .. u^{n-3} (the roles c / cn / c2 / c3 /
+// c4 and p / pp / p2 / p3 / p4).  A step's extrapolated start overwrites the
+// oldest state in place (each cell reads only its own history) and the roles
+// then rotate by one: role k is array (k + hist) mod 5 of the field, and a
+// step takes hist to hist + 4 mod 5.  One write per cell and field instead of
+// five (the older states are never copied).
+template <typename T>
+__device__ inline void bind_history(Solve<T>& S, uint8_t* base) {
+    double* f = reinterpret_cast<double*>(base);
+    const int64_t n = (int64_t)S.nx * S.ny;
+    const int cs[5] = {kC, kCn, kC2, kC3, kC4}, ps[5] = {kP, kPp, kP2, kP3, kP4};
+    double** cr[5] = {&S.c, &S.cn, &S.c2, &S.c3, &S.c4};
+    double** pr[5] = {&S.p, &S.pp, &S.p2, &S.p3, &S.p4};
+    for (int k = 0; k < 5; ++k) {
+        *cr[k] = f + (int64_t)cs[(k + S.hist) % 5] * n;
+        *pr[k] = f + (int64_t)ps[(k + S.hist) % 5] * n;
+    }
+}
+
 // Binds the solve's arrays.  The LDS levels (level_in_lds) get their inner
 // arrays in the workgroup's LDS (`lds`): they are rebuilt every iteration,
 // so nothing there has to survive a launch.  Every level keeps its region
@@ -237,10 +259,11 @@ __device__ inline void bind_solve(Solve<T>& S, uint8_t* base, int nx, int ny, ui
     double* f = reinterpret_cast<double*>(base);
     const int n = nx * ny;
     auto arr = [&](int k) { return f + (int64_t)k * n; };
-    S.p = arr(kP); S.c = arr(kC); S.cn = arr(kCn); S.phi = arr(kPhi); S.K = arr(kK); S.pp = arr(kPp);
+    S.phi = arr(kPhi); S.K = arr(kK);
     S.tx = arr(kTx); S.ty = arr(kTy); S.wx = arr(kWx); S.wy = arr(kWy); S.isc = arr(kIsc);
-    S.c2 = arr(kC2); S.p2 = arr(kP2); S.c3 = arr(kC3); S.p3 = arr(kP3); S.c4 = arr(kC4); S.p4 = arr(kP4);
     S.scratch = arr(kF64Arrays);
+    S.hist = 0;
+    bind_history(S, base);
     uint8_t* q = base + align256((int64_t)kF64Arrays * n * 8 + kScratch * 8);
     uint8_t* ql = lds;
     int lx = nx, ly = ny;
@@ -1622,8 +1645,8 @@ __device__ void vcycle(Solve<T>& S, PhaseClock* pc = nullptr, bool coarse_coeffs
 // (kB round trips in flight at once), then stores; one cell per loop trip
 // would wait out a full memory latency per cell.
 template <int kB>
-__device__ inline void extrapolate_field(double* u0, double* u1, double* u2, double* u3, double* u4, int order, int n,
-                                         int rk, int ts) {
+__device__ inline void extrapolate_field(const double* u0, const double* u1, const double* u2, const double* u3,
+                                         double* u4, int order, int n, int rk, int ts) {
     for (int base = rk; base < n; base += kB * ts) {
         double a0[kB], a1[kB], a2[kB], a3[kB], a4[kB];
 #pragma unroll
@@ -1643,7 +1666,7 @@ __device__ inline void extrapolate_field(double* u0, double* u1, double* u2, dou
                 else if (order == 2) e = 3.0 * a0[k] - 3.0 * a1[k] + a2[k];
                 else if (order == 3) e = 4.0 * a0[k] - 6.0 * a1[k] + 4.0 * a2[k] - a3[k];
                 else if (order == 4) e = (16.0 * a0[k] - 14.0 * a1[k] - 4.0 * a2[k] + 11.0 * a3[k] - 4.0 * a4[k]) * 0.2;
-                u0[idx] = e; u4[idx] = a3[k]; u3[idx] = a2[k]; u2[idx] = a1[k]; u1[idx] = a0[k];
+                u4[idx] = e;  // the oldest state's array becomes the iterate
             }
         }
     }
@@ -1668,8 +1691,9 @@ __device__ inline void add_correction(double* u, const T* x, int n, int rk, int 
 }
 
 // One implicit Euler step (Sec. 2.3) from the state u^n = (S.p, S.c):
-// saves u^n in S.cn / S.pp (c^n is the previous time level of the
-// residual), shifts the older states, and runs the defect correction until
+// u^n becomes S.cn / S.pp (c^n is the previous time level of the
+// residual) and the older states move down one role (bind_history), and the
+// defect correction runs until
 // both scaled residual max norms are <= tol.  The iteration starts from an
 // extrapolation through the last states, by `order`: 0..3 the polynomial
 // through the last order + 1 states (u^n; 2u^n - u^{n-1};
@@ -1689,6 +1713,11 @@ __device__ int implicit_step(const Phys& ph, Solve<T>& S, double* red, int max_o
     extrapolate_field<4>(S.c, S.cn, S.c2, S.c3, S.c4, order, n, rk, ts);
     extrapolate_field<4>(S.p, S.pp, S.p2, S.p3, S.p4, order, n, rk, ts);
     ClusterTeam::sync();
+    if (threadIdx.x == 0) {
+        S.hist = (S.hist + 4) % 5;
+        bind_history(S, reinterpret_cast<uint8_t*>(S.scratch - (int64_t)kF64Arrays * n));
+    }
+    __syncthreads();
     pc.tick(7);
     for (int it = 0; it < max_outer; ++it) {
         double np, nc;
@@ -1847,8 +1876,9 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
     if (threadIdx.x == 0) cluster_stage(lds_levels, lp.lds_bytes, line_stage_bytes_per_wave<T>());
     const int n = S.n;
     // scratch: [0] = q, [1] = status, [2] = iterations, [3] = converged
-    // states in a row (the initial state counts as one); written by the
-    // leader at the end of a launch, read by every member at the next
+    // states in a row (the initial state counts as one), [4] = the history's
+    // rotation; written by the leader at the end of a launch, read by every
+    // member at the next
     int status = 0, good = 1;
     double iters = 0.0;
     if (s_begin == 0) {
@@ -1858,7 +1888,13 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
         iters = sp[2];
         good = (int)sp[3];
     }
-    if (threadIdx.x == 0) S.q = sp[0];
+    if (threadIdx.x == 0) {
+        S.q = sp[0];
+        if (s_begin > 0) {
+            S.hist = (int)sp[4];
+            bind_history(S, lp.ws + d.ws_off);
+        }
+    }
     ClusterTeam::sync();
     PhaseClock pc;
     pc.init();
@@ -1898,6 +1934,7 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kerne
         sp[3] = (double)good;
         sp[1] = (double)status;
         sp[2] = iters;
+        sp[4] = (double)S.hist;
         sp[kClusterGen] = (double)g_cl.gen;
 #ifdef HENRY_PHASE_TIMERS
         for (int k = 0; k < 24; ++k) sp[8 + k] = (double)pc.acc[k];
