@@ -798,7 +798,9 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
       2. workgroups per solve (cluster) for the grids above 2048 cells, one
          grid after another in cost order (eq:workpl: n_l r_l), with at
          most 256 workgroups per group; then the stream plan of the
-         one-workgroup groups (STREAM_PLANS).  Each candidate times the
+         one-workgroup groups (STREAM_PLANS); then again the workgroup size
+         of each one-workgroup grid (half, the same, twice), now that the
+         cluster groups hold their CUs beside it.  Each candidate times the
          whole batch, between events on the caller's stream, or with
          trial_frac > 1 the batch shortened by about that factor keeping
          every time step (_short_batch).  The whole batch is the default:
@@ -831,6 +833,7 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
         return result
     field = _field_of(xi, model)
     # ---- 1. threads per grid, each grid alone
+    tmax = 1024 if prec == PREC_MIXED else 512
     threads = {}
     for nx, ks in sorted(by_grid.items()):
         ks = ks[:max_solves]
@@ -838,7 +841,6 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
         xs = xi[ks].contiguous()
         cells = nx * (nx // 2)
         times = {}
-        tmax = 1024 if prec == PREC_MIXED else 512
         for t in candidates:
             if (t > 64 and t > 2 * cells) or t > tmax:
                 continue
@@ -900,6 +902,19 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
             best_plan = min(plan_times, key=plan_times.get)
             for nx, st in _plan_streams(best_plan, single).items():
                 choice[nx][2] = st
+            # 3. the one-workgroup grids' sizes again, now beside the cluster
+            # groups on the CUs these leave them: half, the same, twice
+            for nx in sorted(single, key=lambda g: -costs[g]):
+                cells = nx * (nx // 2)
+                t0 = choice[nx][0]
+                rtimes = {}
+                for t in (t0 // 2, t0, 2 * t0):
+                    if t < 64 or t > tmax or (t > 64 and t > 2 * cells):
+                        continue
+                    choice[nx][0] = t
+                    rtimes[t] = trial()
+                choice[nx][0] = min(rtimes, key=rtimes.get)
+                threads[nx][1].update({f"in batch {t}": v for t, v in rtimes.items()})
     finally:
         tctx.close()
     for nx in by_grid:

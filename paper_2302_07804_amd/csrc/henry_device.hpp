@@ -1822,15 +1822,18 @@ __device__ void record_trace(const Launch& lp, Solve<T>& S, int index, int k, do
 
 // ------------------------------------------------------------------ the solve kernel
 // Cluster levels of a solve shared by K workgroups: level 0, then every
-// level of >= 2048 K cells (>= 2048 per member) whose coarser neighbour is
+// level of >= 1024 K cells (>= 1024 per member) whose coarser neighbour is
 // not run by wavefront 0; the level after them is handed to the leader's
-// LDS when it lives there (cluster levels, >= 4096 cells, never do).
+// LDS when it lives there (cluster levels, of 8192 cells or more, never
+// do).  At K = 8 the 128x64 level of a 256x128 solve is split (1024 cells
+// per member): 383 -> 367 ms for the 16 such solves of the L = 4 batch,
+// against its leader running it alone.
 template <typename T>
 __device__ inline void set_cluster_levels(Solve<T>& S, int K) {
     int lc = 0;
     if (K > 1) {
         lc = 1;
-        while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 2048 * K) ++lc;
+        while (lc + 1 < S.lds_from && (S.lv[lc].nx * S.lv[lc].ny) >= 1024 * K) ++lc;
     }
     S.lc = lc;
     S.hand = lc > 0 && lc == S.lb;
