@@ -98,7 +98,7 @@ TRAFFIC_PATHS = {
     "kl_1024x512": os.path.join(ROOT, "profiles", "henry_solve_kernel_traffic_kl_1024x512.json"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_07804_amd", "csrc", f)
-                  for f in ("henry_device.hpp", "henry_api.hip")]
+                  for f in ("henry_device.hpp", "henry_api.hip", "henry_solve512.hip")]
 
 
 def kernel_hash() -> str:

@@ -375,7 +375,9 @@ int henry_level_smooth(henry_ctx* ctx, int32_t nx, int32_t ny, int32_t kind, int
  * onto workgroups and streams, priced by their cost n_l r_l, eq:workpl):
  *   threads  workgroup size when opts->threads == 0; 0 = built-in (128
  *            threads up to 128 cells, 256 up to 512, 512 up to 2048, above
- *            that 1024 with PREC_MIXED and 512 with PREC_FP64);
+ *            that 1024 with PREC_MIXED and 512 with PREC_FP64; 512 for a
+ *            PREC_MIXED group whose solves are shared by clusters, which then
+ *            runs the kernel's 512-thread build);
  *            <= 1024 for PREC_MIXED and <= 512 for PREC_FP64
  *   cluster  workgroups per solve (1, 2, 4 or 8) when opts->cluster == 0;
  *            0 = built-in (see henry_opts_t.cluster); grids of 2048 cells
@@ -387,8 +389,9 @@ int henry_level_smooth(henry_ctx* ctx, int32_t nx, int32_t ny, int32_t kind, int
  * choices changes a result (bitwise).  The measuring driver that fills it
  * times candidates on short runs of the caller's own batch (Python
  * binding: paper_2302_07804_amd.autotune).  henry_tune_get returns the
- * effective workgroup size and the stored cluster and stream (0 / -1 =
- * built-in); cluster and stream may be NULL. */
+ * effective workgroup size of a group of one workgroup per solve and the
+ * stored cluster and stream (0 / -1 = built-in); cluster and stream may be
+ * NULL. */
 int henry_tune_set(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t threads, int32_t cluster, int32_t stream);
 int henry_tune_get(henry_ctx* ctx, int32_t nx, int32_t prec, int32_t* threads, int32_t* cluster, int32_t* stream);
 

@@ -14,7 +14,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libhenry.so")
-_SOURCES = [os.path.join(_HERE, "csrc", "henry_api.hip"), os.path.join(_HERE, "csrc", "henry_mlmc_plan.cpp")]
+_SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("henry_api.hip", "henry_solve512.hip", "henry_mlmc_plan.cpp")]
 _DEPS = [os.path.join(_HERE, "csrc", f) for f in ("henry_device.hpp", "henry_mlmc.hpp", "henry_adjoint.hpp")] + \
     [os.path.join(_ROOT, "include", "henry.h")]
 
@@ -798,9 +798,10 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
       2. workgroups per solve (cluster) for the grids above 2048 cells, one
          grid after another in cost order (eq:workpl: n_l r_l), with at
          most 256 workgroups per group; then the stream plan of the
-         one-workgroup groups (STREAM_PLANS); then again the workgroup size
-         of each one-workgroup grid (half, the same, twice), now that the
-         cluster groups hold their CUs beside it.  Each candidate times the
+         one-workgroup groups (STREAM_PLANS); then again every grid's
+         workgroup size (half, the same, twice) at its chosen cluster size
+         and beside the other groups (a cluster group may run the 512-thread
+         build best while 1024 threads won at the built-in cluster size).  Each candidate times the
          whole batch, between events on the caller's stream, or with
          trial_frac > 1 the batch shortened by about that factor keeping
          every time step (_short_batch).  The whole batch is the default:
@@ -902,19 +903,20 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
             best_plan = min(plan_times, key=plan_times.get)
             for nx, st in _plan_streams(best_plan, single).items():
                 choice[nx][2] = st
-            # 3. the one-workgroup grids' sizes again, now beside the cluster
-            # groups on the CUs these leave them: half, the same, twice
-            for nx in sorted(single, key=lambda g: -costs[g]):
-                cells = nx * (nx // 2)
-                t0 = choice[nx][0]
-                rtimes = {}
-                for t in (t0 // 2, t0, 2 * t0):
-                    if t < 64 or t > tmax or (t > 64 and t > 2 * cells):
-                        continue
-                    choice[nx][0] = t
-                    rtimes[t] = trial()
-                choice[nx][0] = min(rtimes, key=rtimes.get)
-                threads[nx][1].update({f"in batch {t}": v for t, v in rtimes.items()})
+        # 3. every grid's workgroup size again (half, the same, twice), in
+        # cost order, now with its cluster size and beside the other groups:
+        # the sizes of step 1 were timed alone and at the built-in clusters
+        for nx in sorted(by_grid, key=lambda g: -costs[g]):
+            cells = nx * (nx // 2)
+            t0 = choice[nx][0]
+            rtimes = {}
+            for t in (t0 // 2, t0, 2 * t0):
+                if t < 64 or t > tmax or (t > 64 and t > 2 * cells):
+                    continue
+                choice[nx][0] = t
+                rtimes[t] = trial()
+            choice[nx][0] = min(rtimes, key=rtimes.get)
+            threads[nx][1].update({f"in batch {t}": v for t, v in rtimes.items()})
     finally:
         tctx.close()
     for nx in by_grid:

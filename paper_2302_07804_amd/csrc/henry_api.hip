@@ -26,6 +26,10 @@
 #include "henry_kl.hpp"
 #include "henry_mlmc.hpp"
 
+// The 512-thread FP32 build (henry_solve512.hip).
+size_t henry512_launch_bytes();
+hipError_t henry512_launch_solve(dim3 grid, dim3 block, size_t lds, hipStream_t stream, const void* launch);
+
 namespace {
 
 constexpr int kStreams = 4;
@@ -182,9 +186,19 @@ struct DeviceGuard {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Largest workgroup of the solve kernel: the FP32-inner instantiation is
-// built for 1024 threads (<= 128 VGPRs), the FP64 one for 512.
+// Largest workgroup of the solve kernel: the FP32-inner kernel has a build
+// for 1024 threads (<= 128 VGPRs) and one for 512 (henry_solve512.hip, no
+// register spills); the FP64 kernel is built for 512.
 int max_threads(int prec) { return prec == HENRY_PREC_MIXED ? 1024 : 512; }
+
+// Groups whose solves are shared by clusters run the 512-thread FP32 build
+// when their workgroups allow it (their phases stream whole levels, and the
+// spills of the 1024-thread build cost them: 1024x512 KL batch 4 % faster);
+// the groups of one workgroup per solve keep the 1024-thread build, of which
+// two 512-thread workgroups fit on one CU.  Results are the same bits.
+bool use_build512(int prec, int threads, int cluster) {
+    return prec == HENRY_PREC_MIXED && cluster > 1 && threads <= 512;
+}
 constexpr int kAdjMaxThreads = 512;
 
 int check_grid(const henry_grid_t& g) {
@@ -319,10 +333,14 @@ int enqueue_groups(henry_ctx* ctx, const std::vector<Group>& order, const std::v
             l.g_begin = g0;
             l.g_end = std::min(rmax, g0 + chunk);
             l.g_total = rmax;
-            if (prec == HENRY_PREC_MIXED)
+            if (use_build512(prec, G.threads, K)) {
+                if (henry512_launch_bytes() != sizeof(l)) return HENRY_EHIP;  // one header, one layout
+                if (henry512_launch_solve(dim3(nblk), dim3(G.threads), lds, st, &l) != hipSuccess) return HENRY_EHIP;
+            } else if (prec == HENRY_PREC_MIXED) {
                 hipLaunchKernelGGL(henry::henry_solve_kernel<float>, dim3(nblk), dim3(G.threads), lds, st, l);
-            else
+            } else {
                 hipLaunchKernelGGL(henry::henry_solve_kernel<double>, dim3(nblk), dim3(G.threads), lds, st, l);
+            }
         }
         if (hipGetLastError() != hipSuccess) return HENRY_EHIP;
         if (profile && hipEventRecord(ctx->prof_ev[2 * gi + 1], st) != hipSuccess) return HENRY_EHIP;
@@ -668,9 +686,10 @@ int solve_batch_impl(henry_ctx* ctx, const henry_grid_t* solves, int32_t nsolves
         const auto it = ctx->tuned.find((long)G.nx * 4 + prec);
         const Tuned tu = it != ctx->tuned.end() ? it->second : Tuned{};
         int t = o->threads;
-        if (t == 0) t = tu.threads > 0 ? tu.threads : default_threads(G.nx, G.ny, prec);
-        G.threads = t;
         G.cluster = cluster_size(G.nx, G.ny, (int)G.members.size(), o->cluster > 0 ? o->cluster : tu.cluster);
+        if (t == 0 && tu.threads > 0) t = tu.threads;
+        if (t == 0) t = (prec == HENRY_PREC_MIXED && G.cluster > 1) ? 512 : default_threads(G.nx, G.ny, prec);
+        G.threads = t;
         G.stream = tu.stream;
     }
 

@@ -43,7 +43,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace henry {
+// The namespace and the FP32 kernel's workgroup bound of this build: the
+// library compiles this header twice, as henry with 1024-thread bounds
+// (henry_api.hip) and as henry512 with 512-thread bounds (henry_solve512.hip),
+// so that each build's device functions get their own register budget.
+#ifndef HENRY_NS
+#define HENRY_NS henry
+#endif
+#ifndef HENRY_FP32_THREADS
+#define HENRY_FP32_THREADS 1024
+#endif
+
+namespace HENRY_NS {
 
 constexpr int kMaxLevels = 12;  // ny <= 512 -> at most 10 multigrid levels
 constexpr int kWave = 64;
@@ -484,6 +495,7 @@ __device__ inline void cluster_init_single() {
         g_cl.K = 1; g_cl.member = 0; g_cl.base = 0; g_cl.size = (int)blockDim.x;
         g_cl.flags = nullptr; g_cl.err = nullptr; g_cl.slots = nullptr;
         g_cl.gen = 0u; g_cl.local = 1; g_cl.failed = 0; g_cl.wait = 0;
+        g_cl.stage = nullptr; g_cl.stage_waves = 0;  // no line staging unless cluster_stage says so
     }
     __syncthreads();
 }
@@ -500,6 +512,7 @@ __device__ inline void cluster_init(int K, int member, double* sp, uint64_t wait
         g_cl.gen = (unsigned)sp[kClusterGen];
         g_cl.local = 0;  // the placement check itself uses the agent-scope protocol
         g_cl.failed = 0;
+        g_cl.stage = nullptr; g_cl.stage_waves = 0;  // no line staging unless cluster_stage says so
         sp[kClusterXcc + member] = (double)xcc_id();
     }
     cluster_barrier();
@@ -1769,13 +1782,24 @@ __device__ void initial_state(const Phys& ph, Solve<T>& S, const double* c0) {
     }
 }
 
-// Q = h^2 sum_{x<1} phi rho(c) c (FP64, fixed-order block reduction).
+// Q = h^2 sum_{x<1} phi rho(c) c (FP64) in an order fixed by the grid
+// alone: wavefront 0 keeps 64 partial sums (lane l adds the cells of index
+// l mod 64 in increasing order), then a fixed butterfly over the lanes, so
+// every workgroup size, cluster size and build gives the same bits.  Once
+// per solve; the other wavefronts wait.
 template <typename T>
 __device__ double qoi_of(const Phys& ph, Solve<T>& S, double* red) {
-    double part = 0.0;
-    for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x)
-        if ((idx % S.nx) < S.nx / 2) part += S.phi[idx] * rho_of(ph, S.c[idx]) * S.c[idx];
-    return block_sum(part, red) * S.h * S.h;
+    if (threadIdx.x < kWave) {
+        double part = 0.0;
+        for (int idx = threadIdx.x; idx < S.n; idx += kWave)
+            if ((idx % S.nx) < S.nx / 2) part += S.phi[idx] * rho_of(ph, S.c[idx]) * S.c[idx];
+        part = wave_sum(part);
+        if (threadIdx.x == 0) red[0] = part;
+    }
+    __syncthreads();
+    const double q = red[0] * S.h * S.h;
+    __syncthreads();  // red is reused
+    return q;
 }
 
 // Start of a step after `good` converged states in a row (the initial state
@@ -1852,7 +1876,7 @@ __device__ inline void cluster_of_block(int K, int& cid, int& member) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) henry_solve_kernel(Launch lp) {
+__global__ void __launch_bounds__(sizeof(T) == 4 ? HENRY_FP32_THREADS : 512) henry_solve_kernel(Launch lp) {
     extern __shared__ __align__(256) uint8_t lds_levels[];
     __shared__ Solve<T> S;
     __shared__ double red[32];
@@ -2085,4 +2109,4 @@ __global__ void henry_fields_kernel(Launch lp) {
     }
 }
 
-}  // namespace henry
+}  // namespace HENRY_NS

@@ -45,6 +45,7 @@ def test_abi_host_code_under_address_and_ub_sanitizers(tmp_path):
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2302_07804_amd", "csrc"),
            "-o", str(exe), os.path.join(ROOT, "tests", "sanitize_abi_driver.cpp"),
            os.path.join(ROOT, "paper_2302_07804_amd", "csrc", "henry_api.hip"),
+           os.path.join(ROOT, "paper_2302_07804_amd", "csrc", "henry_solve512.hip"),
            os.path.join(ROOT, "paper_2302_07804_amd", "csrc", "henry_mlmc_plan.cpp")]
     subprocess.run(cmd, check=True, capture_output=True, text=True, timeout=600)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1")
