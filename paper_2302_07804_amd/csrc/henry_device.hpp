@@ -1982,6 +1982,10 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? HENRY_FP32_THREADS : 512) hen
     }
 }
 
+// The kernels below run from the main build only (a build of the solve
+// kernel alone defines HENRY_SOLVE_KERNEL_ONLY).
+#ifndef HENRY_SOLVE_KERNEL_ONLY
+
 // The FP64 residual of one solve's discrete equations at a given state
 // (p, c; previous time level cn): the same residual pass as the solver's,
 // writing R^p and R^c instead of the inner-solve arrays.  One workgroup per
@@ -2108,5 +2112,7 @@ __global__ void henry_fields_kernel(Launch lp) {
         isc[idx] = tau / (h * h * fP * ph.rho0);
     }
 }
+
+#endif  // HENRY_SOLVE_KERNEL_ONLY
 
 }  // namespace HENRY_NS

@@ -13,6 +13,7 @@
 
 #define HENRY_NS henry512
 #define HENRY_FP32_THREADS 512
+#define HENRY_SOLVE_KERNEL_ONLY
 #include "henry_device.hpp"
 
 // Size of this build's launch record (the same struct as henry::Launch,
