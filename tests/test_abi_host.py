@@ -177,3 +177,33 @@ def test_time_series_entry_points_reject_bad_arguments(L):
         assert L.henry_first_passage(handle, *args, x, 0.5, 1, x, x, None) == hm.HENRY_EINVAL, args
     assert L.henry_first_passage(handle, 10, 5, 3, 1, x, float("inf"), 1, x, x, None) == hm.HENRY_EINVAL
     assert L.henry_first_passage(handle, 0, 5, 3, 1, x, 0.5, 1, x, None, None) == hm.HENRY_OK  # nothing to do
+
+
+def test_tuner_trial_batch_keeps_every_time_step():
+    """The tuner's shortened trial batch (trial_frac > 1) divides every
+    solve's step count by one common factor f (so each keeps its time step
+    tau = T / r with horizon T / f), nearest the requested factor among the
+    divisors of the steps' gcd that leave at least min_steps steps; factor 1
+    (the default) is the caller's batch itself."""
+    solves = [(16, 8, 50), (32, 16, 100), (64, 32, 200), (128, 64, 400), (256, 128, 800)]
+    f, short = hm._short_batch(solves, target=5)
+    assert f == 5 and short == [(s[0], s[1], s[2] // 5) for s in solves]
+    f, short = hm._short_batch(solves, target=1)
+    assert f == 1 and short == [tuple(s) for s in solves]
+    # 50 / 25 = 2 steps is below min_steps = 8: the largest factor allowed is 5 (50 / 5 = 10 steps)
+    f, _ = hm._short_batch(solves, target=25)
+    assert f == 5
+    f, short = hm._short_batch([(16, 8, 7), (32, 16, 21)], target=5)
+    assert f == 1 and short == [(16, 8, 7), (32, 16, 21)]
+
+
+def test_tuner_stream_plans():
+    """Stream of each one-workgroup grid under the tuner's plans: the
+    built-in plan (-1), one lane beside the cluster groups (stream 1),
+    spread over streams 1..3 in cost order, or everything on stream 0."""
+    costs = {128: 4.0, 64: 2.0, 32: 3.0, 16: 1.0}
+    assert hm._plan_streams("built-in", costs) == {nx: -1 for nx in costs}
+    assert hm._plan_streams("one lane", costs) == {nx: 1 for nx in costs}
+    assert hm._plan_streams("spread", costs) == {128: 1, 32: 2, 64: 3, 16: 1}
+    assert hm._plan_streams("serial", costs) == {nx: 0 for nx in costs}
+    assert set(hm.STREAM_PLANS) == {"built-in", "one lane", "spread", "serial"}
