@@ -753,20 +753,24 @@ def henry_tune_get(ctx: Context, nx: int, prec: int):
     return t.value, k.value, st.value
 
 
-STREAM_PLANS = ("built-in", "one lane", "spread", "serial")
+STREAM_PLANS = ("built-in", "one lane", "halves", "spread", "serial")
 TUNE_FRAC_TARGET = 5
 
 
 def _plan_streams(plan, grid_costs):
     """Stream of each one-workgroup grid under a named plan: 'built-in'
     leaves the library's plan (-1), 'one lane' puts every such group on
-    stream 1 beside the cluster groups, 'spread' deals them over streams
-    1..3 in cost order, 'serial' runs everything on stream 0."""
+    stream 1 beside the cluster groups, 'halves' the costlier half of them
+    (in cost order) on stream 1 and the cheaper half on stream 2, 'spread'
+    deals them over streams 1..3 in cost order, 'serial' runs everything on
+    stream 0."""
     order = sorted(grid_costs, key=lambda nx: -grid_costs[nx])
     if plan == "built-in":
         return {nx: -1 for nx in order}
     if plan == "one lane":
         return {nx: 1 for nx in order}
+    if plan == "halves":
+        return {nx: 1 if k < (len(order) + 1) // 2 else 2 for k, nx in enumerate(order)}
     if plan == "spread":
         return {nx: 1 + k % 3 for k, nx in enumerate(order)}
     return {nx: 0 for nx in order}
@@ -801,7 +805,8 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
          one-workgroup groups (STREAM_PLANS); then again every grid's
          workgroup size (half, the same, twice) at its chosen cluster size
          and beside the other groups (a cluster group may run the 512-thread
-         build best while 1024 threads won at the built-in cluster size).  Each candidate times the
+         build best while 1024 threads won at the built-in cluster size),
+         and the stream plan once more at those sizes.  Each candidate times the
          whole batch, between events on the caller's stream, or with
          trial_frac > 1 the batch shortened by about that factor keeping
          every time step (_short_batch).  The whole batch is the default:
@@ -917,6 +922,16 @@ def autotune(ctx: Context, solves, xi, opts: Opts | None = None, tune_steps: int
                 rtimes[t] = trial()
             choice[nx][0] = min(rtimes, key=rtimes.get)
             threads[nx][1].update({f"in batch {t}": v for t, v in rtimes.items()})
+        # 4. the stream plan again, at these sizes
+        if single:
+            plan_times = {}
+            for plan in plans:
+                for nx, st in _plan_streams(plan, single).items():
+                    choice[nx][2] = st
+                plan_times[plan] = trial()
+            best_plan = min(plan_times, key=plan_times.get)
+            for nx, st in _plan_streams(best_plan, single).items():
+                choice[nx][2] = st
     finally:
         tctx.close()
     for nx in by_grid:

@@ -199,11 +199,14 @@ def test_tuner_trial_batch_keeps_every_time_step():
 
 def test_tuner_stream_plans():
     """Stream of each one-workgroup grid under the tuner's plans: the
-    built-in plan (-1), one lane beside the cluster groups (stream 1),
-    spread over streams 1..3 in cost order, or everything on stream 0."""
+    built-in plan (-1), one lane beside the cluster groups (stream 1), the
+    costlier half on stream 1 and the cheaper on stream 2, spread over
+    streams 1..3 in cost order, or everything on stream 0."""
     costs = {128: 4.0, 64: 2.0, 32: 3.0, 16: 1.0}
     assert hm._plan_streams("built-in", costs) == {nx: -1 for nx in costs}
     assert hm._plan_streams("one lane", costs) == {nx: 1 for nx in costs}
+    assert hm._plan_streams("halves", costs) == {128: 1, 32: 1, 64: 2, 16: 2}
+    assert hm._plan_streams("halves", {128: 3.0, 64: 2.0, 16: 1.0}) == {128: 1, 64: 1, 16: 2}
     assert hm._plan_streams("spread", costs) == {128: 1, 32: 2, 64: 3, 16: 1}
     assert hm._plan_streams("serial", costs) == {nx: 0 for nx in costs}
-    assert set(hm.STREAM_PLANS) == {"built-in", "one lane", "spread", "serial"}
+    assert set(hm.STREAM_PLANS) == {"built-in", "one lane", "halves", "spread", "serial"}
