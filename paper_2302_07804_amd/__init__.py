@@ -753,7 +753,12 @@ def henry_tune_get(ctx: Context, nx: int, prec: int):
     return t.value, k.value, st.value
 
 
-STREAM_PLANS = ("built-in", "one lane", "halves", "spread", "serial")
+# The tuner's default candidates.  "halves" (see _plan_streams) is left out:
+# on the L = 4 batch it gains 0-2 % on some boxes and loses 1 % on others,
+# and its cheap groups' launches stretch to several times their length while
+# they wait for CUs (16x8: 26 -> 149 ms), which blurs the per-group timings;
+# pass plans=STREAM_PLANS + ("halves",) to include it.
+STREAM_PLANS = ("built-in", "one lane", "spread", "serial")
 TUNE_FRAC_TARGET = 5
 
 

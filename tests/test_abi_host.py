@@ -209,4 +209,4 @@ def test_tuner_stream_plans():
     assert hm._plan_streams("halves", {128: 3.0, 64: 2.0, 16: 1.0}) == {128: 1, 64: 1, 16: 2}
     assert hm._plan_streams("spread", costs) == {128: 1, 32: 2, 64: 3, 16: 1}
     assert hm._plan_streams("serial", costs) == {nx: 0 for nx in costs}
-    assert set(hm.STREAM_PLANS) == {"built-in", "one lane", "halves", "spread", "serial"}
+    assert set(hm.STREAM_PLANS) == {"built-in", "one lane", "spread", "serial"}
