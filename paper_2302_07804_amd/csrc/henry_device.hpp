@@ -53,8 +53,26 @@
 #ifndef HENRY_FP32_THREADS
 #define HENRY_FP32_THREADS 1024
 #endif
+// Grids of at least HENRY_RES_FIELDS_NX columns (0: none): the residual
+// pass forms the face coefficients and the norm scale from K and phi (5 FP64
+// loads per cell instead of 9, and seven FP64 divisions); smaller ones load
+// the stored ones.  Both give the same bits.
+#ifndef HENRY_RES_FIELDS_NX
+#define HENRY_RES_FIELDS_NX 0
+#endif
+// Cells per thread gathered by the grid transfers of the builds with at most
+// 512 threads (the 1024-thread build takes one).
+#ifndef HENRY_TRANSFER_BATCH
+#define HENRY_TRANSFER_BATCH 1
+#endif
 
 namespace HENRY_NS {
+
+// Cells per thread whose operands a transfer between levels (restriction,
+// prolongation, coefficient coarsening) from a finer level in global memory
+// gathers before it writes any, so that their loads are in flight together;
+// the 1024-thread build has no registers to spare for more than one.
+constexpr int kTBatch = HENRY_FP32_THREADS <= 512 ? HENRY_TRANSFER_BATCH : 1;
 
 constexpr int kMaxLevels = 12;  // ny <= 512 -> at most 10 multigrid levels
 constexpr int kWave = 64;
@@ -658,6 +676,16 @@ struct PhaseClock {
 };
 
 // ------------------------------------------------------------------ FP64 residual
+// Face coefficients between cells a and b (harmonic means of K and of phi)
+// and at the right boundary, and the scale of a cell's residual in the
+// norms; the fields kernel stores them, the residual pass may form them
+// again from K and phi with the same operations.
+__device__ inline double face_perm(const Phys& ph, double Ka, double Kb) { return 2.0 * Ka * Kb / (Ka + Kb) / ph.mu; }
+__device__ inline double face_disp(const Phys& ph, double fa, double fb) { return 2.0 * fa * fb / (fa + fb) * ph.D; }
+__device__ inline double face_perm_edge(const Phys& ph, double K) { return 2.0 * K / ph.mu; }
+__device__ inline double face_disp_edge(const Phys& ph, double f) { return 2.0 * f * ph.D; }
+__device__ inline double res_scale(const Phys& ph, double tau, double h, double f) { return tau / (h * h * f * ph.rho0); }
+
 // Operands of one cell's residual, loaded from clamped indices before any
 // arithmetic (no loads under boundary branches).
 struct ResIn {
@@ -720,22 +748,12 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
     mc = nanmax(mc, fabs(Rc * a.sc));
 }
 
-// mode 0: R^p and R^c, pressure coefficients te/tn at level 0, and the
-//         scaled max norms (block max).
-// mode 1: the salt defect S = R^c - c R^p with the transport coefficients
-//         at level 0.
-// mode 2: R^p and R^c into S.rout_p, S.rout_c (the residual entry point).
-// Thread layout: lanes along x (cw = min(nx, blockDim) columns), the
-// blockDim / cw row groups each march up their own band of rows.  A cell
-// takes p and c of the rows below and above from the registers of the
-// previous row and a load of the next one, and its east and west
-// neighbours' values from the adjacent lanes (one-lane loads only at the
-// ends of a wavefront): 9 full loads per cell instead of 21.
-// The row bands are spread over all threads of the cluster; mode 0 ends
-// with the cluster-wide norms, mode 1 with a cluster barrier only.
-template <typename T>
-__device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out,
-                              PhaseClock* pcx = nullptr) {
+// The rows of one residual pass (see residual_pass).  kFields: the face
+// coefficients and the norm scale formed from K and phi (5 FP64 loads per
+// cell instead of 9, and seven FP64 divisions), with the same operations as
+// the fields kernel's stored ones, so both variants give the same bits.
+template <bool kFields, typename T>
+__device__ inline void residual_rows(const Phys& ph, Solve<T>& S, int mode, double& mp, double& mc) {
     const int nx = S.nx, ny = S.ny;
     const int bs = ClusterTeam::size(), rk = ClusterTeam::rank();
     const int cw = nx < bs ? nx : bs;  // both powers of two
@@ -744,15 +762,26 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
     const int lane = threadIdx.x & (kWave - 1);
     const int g = rk / cw, ci = rk - g * cw;
     const int j0 = g * band;
-    double mp = 0.0, mc = 0.0;
     for (int cx = 0; cx < nx; cx += cw) {
         const int i = cx + ci;
         // rows below and at the start of the band (clamped into the grid)
         const int jb = j0 < ny ? j0 : ny - 1;
         const int js = jb > 0 ? jb - 1 : jb;
         double pS = S.p[js * nx + i], cS = S.c[js * nx + i];
-        double tyS = S.ty[js * nx + i], wyS = S.wy[js * nx + i];
         double pP = S.p[jb * nx + i], cP = S.c[jb * nx + i];
+        double KP = 0.0, fP = 0.0, tyS = 0.0, wyS = 0.0;
+        if constexpr (kFields) {
+            KP = S.K[jb * nx + i];
+            fP = S.phi[jb * nx + i];
+            if (jb > 0) {  // the first row's south face (none at j = 0)
+                const double Ks = S.K[js * nx + i], fs = S.phi[js * nx + i];
+                tyS = face_perm(ph, Ks, KP);
+                wyS = face_disp(ph, fs, fP);
+            }
+        } else {
+            tyS = S.ty[js * nx + i];
+            wyS = S.wy[js * nx + i];
+        }
         for (int t = 0; t < band; ++t) {  // the same trip count in every lane (shuffles)
             const int j = j0 + t;
             const bool active = j < ny;
@@ -762,13 +791,32 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
             ResIn a;
             a.pP = pP; a.cP = cP; a.pS = pS; a.cS = cS; a.tyS = tyS; a.wyS = wyS;
             a.pN = S.p[q.n]; a.cN = S.c[q.n];
-            a.cnP = S.cn[idx]; a.phiP = S.phi[idx];
-            a.txP = S.tx[idx]; a.wxP = S.wx[idx]; a.tyP = S.ty[idx]; a.wyP = S.wy[idx];
-            a.sc = S.isc[idx];
+            a.cnP = S.cn[idx];
             // neighbours in x: adjacent lanes, or memory at the wavefront's ends
             double pEm = 0.0, cEm = 0.0, pWm = 0.0, cWm = 0.0, txWm = 0.0, wxWm = 0.0;
-            if (lane == kWave - 1) { pEm = S.p[q.e]; cEm = S.c[q.e]; }
-            if (lane == 0) { pWm = S.p[q.w]; cWm = S.c[q.w]; txWm = S.tx[q.w]; wxWm = S.wx[q.w]; }
+            double KN = 0.0, fN = 0.0;
+            if constexpr (kFields) {
+                KN = S.K[q.n];
+                fN = S.phi[q.n];
+                double KEm = 0.0, fEm = 0.0, KWm = 0.0, fWm = 0.0;
+                if (lane == kWave - 1) { pEm = S.p[q.e]; cEm = S.c[q.e]; KEm = S.K[q.e]; fEm = S.phi[q.e]; }
+                if (lane == 0) { pWm = S.p[q.w]; cWm = S.c[q.w]; KWm = S.K[q.w]; fWm = S.phi[q.w]; }
+                const double KEs = __shfl_down(KP, 1, kWave), fEs = __shfl_down(fP, 1, kWave);
+                const double KE = lane == kWave - 1 ? KEm : KEs, fE = lane == kWave - 1 ? fEm : fEs;
+                a.phiP = fP;
+                a.txP = q.he ? face_perm(ph, KP, KE) : face_perm_edge(ph, KP);
+                a.wxP = q.he ? face_disp(ph, fP, fE) : face_disp_edge(ph, fP);
+                a.tyP = q.hn ? face_perm(ph, KP, KN) : 0.0;
+                a.wyP = q.hn ? face_disp(ph, fP, fN) : 0.0;
+                a.sc = res_scale(ph, S.tau, S.h, fP);
+                if (lane == 0) { txWm = face_perm(ph, KWm, KP); wxWm = face_disp(ph, fWm, fP); }
+            } else {
+                a.phiP = S.phi[idx];
+                a.txP = S.tx[idx]; a.wxP = S.wx[idx]; a.tyP = S.ty[idx]; a.wyP = S.wy[idx];
+                a.sc = S.isc[idx];
+                if (lane == kWave - 1) { pEm = S.p[q.e]; cEm = S.c[q.e]; }
+                if (lane == 0) { pWm = S.p[q.w]; cWm = S.c[q.w]; txWm = S.tx[q.w]; wxWm = S.wx[q.w]; }
+            }
             const double pEs = __shfl_down(pP, 1, kWave), cEs = __shfl_down(cP, 1, kWave);
             const double pWs = __shfl_up(pP, 1, kWave), cWs = __shfl_up(cP, 1, kWave);
             const double txWs = __shfl_up(a.txP, 1, kWave), wxWs = __shfl_up(a.wxP, 1, kWave);
@@ -782,8 +830,33 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
             // carry up one row
             pS = pP; cS = cP; tyS = a.tyP; wyS = a.wyP;
             pP = a.pN; cP = a.cN;
+            KP = KN; fP = fN;
         }
     }
+}
+
+// mode 0: R^p and R^c, pressure coefficients te/tn at level 0, and the
+//         scaled max norms (block max).
+// mode 1: the salt defect S = R^c - c R^p with the transport coefficients
+//         at level 0.
+// mode 2: R^p and R^c into S.rout_p, S.rout_c (the residual entry point).
+// Thread layout: lanes along x (cw = min(nx, blockDim) columns), the
+// blockDim / cw row groups each march up their own band of rows.  A cell
+// takes p and c of the rows below and above from the registers of the
+// previous row and a load of the next one, and its east and west
+// neighbours' values from the adjacent lanes (one-lane loads only at the
+// ends of a wavefront): 9 full loads per cell instead of 21.  Grids of at
+// least HENRY_RES_FIELDS_NX columns form the face coefficients from K and
+// phi instead (their passes are bound by bandwidth); on smaller ones, whose
+// passes wait on load latency, the divisions would lengthen the wait.
+// The row bands are spread over all threads of the cluster; mode 0 ends
+// with the cluster-wide norms, mode 1 with a cluster barrier only.
+template <typename T>
+__device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red, double& np_out, double& nc_out,
+                              PhaseClock* pcx = nullptr) {
+    double mp = 0.0, mc = 0.0;
+    if (HENRY_RES_FIELDS_NX > 0 && S.nx >= HENRY_RES_FIELDS_NX) residual_rows<true>(ph, S, mode, mp, mc);
+    else residual_rows<false>(ph, S, mode, mp, mc);
     if (pcx) pcx->tick(mode == 0 ? 23 : 21);
     cluster_max2(mp, mc, red, np_out, nc_out);
     __syncthreads();
@@ -792,17 +865,82 @@ __device__ void residual_pass(const Phys& ph, Solve<T>& S, int mode, double* red
 // ------------------------------------------------------------------ coefficient coarsening
 // One level of each hierarchy from the level below it (Team loops; the
 // caller synchronises the team before the level is read).
+template <typename T, class Team, int ASF, int ASC, int KB>
+__device__ inline void coarsen_pressure_level_kb(const LV<T, ASF>& F, const LV<T, ASC>& C) {
+    const int nc = C.nx * C.ny;
+    const int sx = log2i(C.nx);
+    const int ts = Team::size();
+    for (int k0 = Team::rank(); k0 < nc; k0 += KB * ts) {
+        T e0[KB], e1[KB], n0[KB], n1[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int k = k0 + u * ts;
+            const int idx = k < nc ? k : 0;
+            int I, J;  // colour-split layout on both levels
+            pcell(idx, C.nx, sx, I, J);
+            e0[u] = F.te[pidx(2 * I + 1, 2 * J, F.nx)];
+            e1[u] = F.te[pidx(2 * I + 1, 2 * J + 1, F.nx)];
+            n0[u] = F.tn[pidx(2 * I, 2 * J + 1, F.nx)];
+            n1[u] = F.tn[pidx(2 * I + 1, 2 * J + 1, F.nx)];
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int k = k0 + u * ts;
+            if (k < nc) {
+                C.te[k] = (T)0.5 * (e0[u] + e1[u]);
+                C.tn[k] = (T)0.5 * (n0[u] + n1[u]);
+            }
+        }
+    }
+}
+
 template <typename T, class Team, int ASF, int ASC>
 __device__ void coarsen_pressure_level(const Level<T>& F0, Level<T>& C0) {
     const LV<T, ASF> F(F0);
     const LV<T, ASC> C(C0);
+    if (kTBatch > 1 && ASF == 1 && C.nx * C.ny > Team::size())
+        coarsen_pressure_level_kb<T, Team, ASF, ASC, kTBatch>(F, C);
+    else coarsen_pressure_level_kb<T, Team, ASF, ASC, 1>(F, C);
+}
+
+template <typename T, class Team, int ASF, int ASC, int KB>
+__device__ inline void coarsen_transport_level_kb(const LV<T, ASF>& F, const LV<T, ASC>& C) {
     const int nc = C.nx * C.ny;
     const int sx = log2i(C.nx);
-    for (int idx = Team::rank(); idx < nc; idx += Team::size()) {
-        int I, J;  // colour-split layout on both levels
-        pcell(idx, C.nx, sx, I, J);
-        C.te[idx] = (T)0.5 * (F.te[pidx(2 * I + 1, 2 * J, F.nx)] + F.te[pidx(2 * I + 1, 2 * J + 1, F.nx)]);
-        C.tn[idx] = (T)0.5 * (F.tn[pidx(2 * I, 2 * J + 1, F.nx)] + F.tn[pidx(2 * I + 1, 2 * J + 1, F.nx)]);
+    const int ts = Team::size();
+    for (int k0 = Team::rank(); k0 < nc; k0 += KB * ts) {
+        T a00[KB], a01[KB], a10[KB], a11[KB], mx0[KB], mx1[KB], dx0[KB], dx1[KB], my0[KB], my1[KB], dy0[KB],
+            dy1[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int k = k0 + u * ts;
+            const int idx = k < nc ? k : 0;
+            const int I = idx & (C.nx - 1), J = idx >> sx;
+            const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
+            a00[u] = F.acc[f0]; a01[u] = F.acc[f0 + 1]; a10[u] = F.acc[f1]; a11[u] = F.acc[f1 + 1];
+            mx0[u] = F.mx[f0 + 1]; mx1[u] = F.mx[f1 + 1]; dx0[u] = F.dx[f0 + 1]; dx1[u] = F.dx[f1 + 1];
+            my0[u] = F.my[f1]; my1[u] = F.my[f1 + 1]; dy0[u] = F.dy[f1]; dy1[u] = F.dy[f1 + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int k = k0 + u * ts;
+            if (k < nc) {
+                const int I = k & (C.nx - 1), J = k >> sx;
+                C.acc[k] = (a00[u] + a01[u]) + (a10[u] + a11[u]);
+                // mass fluxes through the two fine faces add; diffusion
+                // transmissibilities (length/distance = 1 on every level) average
+                C.mx[k] = (I + 1 < C.nx) ? mx0[u] + mx1[u] : (T)0;
+                C.dx[k] = (I + 1 < C.nx) ? (T)0.5 * (dx0[u] + dx1[u]) : (T)0;
+                C.my[k] = (J + 1 < C.ny) ? my0[u] + my1[u] : (T)0;
+                C.dy[k] = (J + 1 < C.ny) ? (T)0.5 * (dy0[u] + dy1[u]) : (T)0;
+            }
+        }
+    }
+    for (int J = Team::rank(); J < C.ny; J += ts) {
+        C.dl[J] = (T)0.5 * (F.dl[2 * J] + F.dl[2 * J + 1]);
+        C.dr[J] = (T)0.5 * (F.dr[2 * J] + F.dr[2 * J + 1]);
+        C.mr[J] = F.mr[2 * J] + F.mr[2 * J + 1];
+        C.ml[J] = F.ml[2 * J] + F.ml[2 * J + 1];
     }
 }
 
@@ -810,25 +948,9 @@ template <typename T, class Team, int ASF, int ASC>
 __device__ void coarsen_transport_level(const Level<T>& F0, Level<T>& C0) {
     const LV<T, ASF> F(F0);
     const LV<T, ASC> C(C0);
-    const int nc = C.nx * C.ny;
-    const int sx = log2i(C.nx);
-    for (int idx = Team::rank(); idx < nc; idx += Team::size()) {
-        const int I = idx & (C.nx - 1), J = idx >> sx;
-        const int f0 = (2 * J) * F.nx + 2 * I, f1 = f0 + F.nx;
-        C.acc[idx] = (F.acc[f0] + F.acc[f0 + 1]) + (F.acc[f1] + F.acc[f1 + 1]);
-        // mass fluxes through the two fine faces add; diffusion
-        // transmissibilities (length/distance = 1 on every level) average
-        C.mx[idx] = (I + 1 < C.nx) ? F.mx[f0 + 1] + F.mx[f1 + 1] : (T)0;
-        C.dx[idx] = (I + 1 < C.nx) ? (T)0.5 * (F.dx[f0 + 1] + F.dx[f1 + 1]) : (T)0;
-        C.my[idx] = (J + 1 < C.ny) ? F.my[f1] + F.my[f1 + 1] : (T)0;
-        C.dy[idx] = (J + 1 < C.ny) ? (T)0.5 * (F.dy[f1] + F.dy[f1 + 1]) : (T)0;
-    }
-    for (int J = Team::rank(); J < C.ny; J += Team::size()) {
-        C.dl[J] = (T)0.5 * (F.dl[2 * J] + F.dl[2 * J + 1]);
-        C.dr[J] = (T)0.5 * (F.dr[2 * J] + F.dr[2 * J + 1]);
-        C.mr[J] = F.mr[2 * J] + F.mr[2 * J + 1];
-        C.ml[J] = F.ml[2 * J] + F.ml[2 * J + 1];
-    }
+    if (kTBatch > 1 && ASF == 1 && C.nx * C.ny > Team::size())
+        coarsen_transport_level_kb<T, Team, ASF, ASC, kTBatch>(F, C);
+    else coarsen_transport_level_kb<T, Team, ASF, ASC, 1>(F, C);
 }
 
 template <typename T, bool kTransport, class Team, int ASF, int ASC>
@@ -982,24 +1104,45 @@ __device__ inline Stencil<T> stencil(const V& v, const Q& q, int j) {
 // x_f += P x_c.  Restriction is its exact transpose (full weighting with
 // weights (1,3,3,1)/4 per direction, boundary weights folded in).
 // kSplit: both levels in the colour-split layout (pressure cycle).
+template <typename T, class Team, int ASC, int ASF, bool kSplit, int KB>
+__device__ inline void prolong_add_kb(const LV<T, ASC>& C, const LV<T, ASF>& F) {
+    const int n = F.nx * F.ny;
+    const int sx = log2i(F.nx);
+    const int ts = Team::size();
+    auto cat = [&](int I, int J) { return kSplit ? pidx(I, J, C.nx) : J * C.nx + I; };
+    for (int k0 = Team::rank(); k0 < n; k0 += KB * ts) {
+        T v[KB], xf[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int k = k0 + u * ts;
+            const int idx = k < n ? k : 0;
+            int i, j;
+            if constexpr (kSplit) pcell(idx, F.nx, sx, i, j);
+            else { i = idx & (F.nx - 1); j = idx >> sx; }
+            const int I = i >> 1, J = j >> 1;
+            const int In = (i & 1) ? min(I + 1, C.nx - 1) : max(I - 1, 0);
+            const int Jn = (j & 1) ? min(J + 1, C.ny - 1) : max(J - 1, 0);
+            v[u] = (T)0.5625 * C.x[cat(I, J)] + (T)0.1875 * (C.x[cat(In, J)] + C.x[cat(I, Jn)]) +
+                   (T)0.0625 * C.x[cat(In, Jn)];
+            xf[u] = F.x[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (k0 + u * ts < n) F.x[k0 + u * ts] = xf[u] + v[u];
+    }
+}
+
+// Prolongation: bilinear with constant extrapolation at the boundary,
+// x_f += P x_c.  Restriction is its exact transpose (full weighting with
+// weights (1,3,3,1)/4 per direction, boundary weights folded in).
+// kSplit: both levels in the colour-split layout (pressure cycle).
 template <typename T, class Team = BlockTeam, int ASC = 0, int ASF = 0, bool kSplit = false>
 __device__ void prolong_add(const Level<T>& C0, Level<T>& F0) {
     const LV<T, ASC> C(C0);
     const LV<T, ASF> F(F0);
-    const int n = F.nx * F.ny;
-    const int sx = log2i(F.nx);
-    auto cat = [&](int I, int J) { return kSplit ? pidx(I, J, C.nx) : J * C.nx + I; };
-    for (int idx = Team::rank(); idx < n; idx += Team::size()) {
-        int i, j;
-        if constexpr (kSplit) pcell(idx, F.nx, sx, i, j);
-        else { i = idx & (F.nx - 1); j = idx >> sx; }
-        const int I = i >> 1, J = j >> 1;
-        const int In = (i & 1) ? min(I + 1, C.nx - 1) : max(I - 1, 0);
-        const int Jn = (j & 1) ? min(J + 1, C.ny - 1) : max(J - 1, 0);
-        const T v = (T)0.5625 * C.x[cat(I, J)] + (T)0.1875 * (C.x[cat(In, J)] + C.x[cat(I, Jn)]) +
-                    (T)0.0625 * C.x[cat(In, Jn)];
-        F.x[idx] += v;
-    }
+    if (kTBatch > 1 && ASF == 1 && F.nx * F.ny > Team::size())
+        prolong_add_kb<T, Team, ASC, ASF, kSplit, kTBatch>(C, F);
+    else prolong_add_kb<T, Team, ASC, ASF, kSplit, 1>(C, F);
 }
 
 // 1D restriction weight of fine index I2 = 2I - 1 + a (a = 0..3) for coarse
@@ -1011,52 +1154,74 @@ __device__ inline float rweight(int I, int n, int a) {
     return w;
 }
 
+template <typename T, class Team, int ASF, int ASC, bool kSplit, int KB>
+__device__ inline void restrict_residual_kb(const LV<T, ASF>& F, const LV<T, ASC>& C) {
+    const int n = C.nx * C.ny;
+    const int sx = log2i(C.nx);
+    const int ts = Team::size();
+    // fine cells whose residual the level residual left out (zero): black
+    // cells (aq + bq odd) in the pressure cycle, odd rows (bq even) in the
+    // transport cycle
+    auto live = [](int aq, int bq) { return kSplit ? ((aq + bq) & 1) == 0 : (bq & 1) == 1; };
+    for (int k0 = Team::rank(); k0 < n; k0 += KB * ts) {
+        T rv[KB][4][4];
+        int cI[KB], cJ[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int k = k0 + u * ts;
+            const int idx = k < n ? k : 0;
+            int I, J;
+            if constexpr (kSplit) pcell(idx, C.nx, sx, I, J);
+            else { I = idx & (C.nx - 1); J = idx >> sx; }
+            cI[u] = I; cJ[u] = J;
+            // fine rows / columns outside the level get weight 0 (their load
+            // is clamped to a valid cell)
+#pragma unroll
+            for (int bq = 0; bq < 4; ++bq) {
+                const int jf = min(max(2 * J - 1 + bq, 0), F.ny - 1);
+#pragma unroll
+                for (int aq = 0; aq < 4; ++aq) {
+                    const int ifn = min(max(2 * I - 1 + aq, 0), F.nx - 1);
+                    rv[u][bq][aq] = live(aq, bq) ? F.r[kSplit ? pidx(ifn, jf, F.nx) : jf * F.nx + ifn] : (T)0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int I = cI[u], J = cJ[u];
+            // terms outside the level are selected away, not weighted by
+            // zero: their clamped load may land on a cell whose residual was
+            // never written
+            T s = (T)0;
+#pragma unroll
+            for (int bq = 0; bq < 4; ++bq) {
+                const int jf = 2 * J - 1 + bq;
+                const bool jin = jf >= 0 && jf < F.ny;
+                T row = (T)0;
+#pragma unroll
+                for (int aq = 0; aq < 4; ++aq) {
+                    const int ifn = 2 * I - 1 + aq;
+                    const bool iin = ifn >= 0 && ifn < F.nx;
+                    row += iin ? (T)rweight(I, C.nx, aq) * rv[u][bq][aq] : (T)0;
+                }
+                s += jin ? (T)rweight(J, C.ny, bq) * row : (T)0;
+            }
+            const int k = k0 + u * ts;
+            if (k < n) {
+                C.b[k] = s;
+                C.x[k] = (T)0;
+            }
+        }
+    }
+}
+
 template <typename T, class Team = BlockTeam, int ASF = 0, int ASC = 0, bool kSplit = false>
 __device__ void restrict_residual(const Level<T>& F0, Level<T>& C0) {
     const LV<T, ASF> F(F0);
     const LV<T, ASC> C(C0);
-    const int n = C.nx * C.ny;
-    const int sx = log2i(C.nx);
-    for (int idx = Team::rank(); idx < n; idx += Team::size()) {
-        int I, J;
-        if constexpr (kSplit) pcell(idx, C.nx, sx, I, J);
-        else { I = idx & (C.nx - 1); J = idx >> sx; }
-        // fine rows / columns outside the level get weight 0 (their load is
-        // clamped to a valid cell)
-        // fine cells whose residual the level residual left out (zero):
-        // black cells (aq + bq odd) in the pressure cycle, odd rows (bq even)
-        // in the transport cycle
-        auto live = [](int aq, int bq) { return kSplit ? ((aq + bq) & 1) == 0 : (bq & 1) == 1; };
-        T rv[4][4];
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) {
-            const int jf = min(max(2 * J - 1 + bq, 0), F.ny - 1);
-#pragma unroll
-            for (int aq = 0; aq < 4; ++aq) {
-                const int ifn = min(max(2 * I - 1 + aq, 0), F.nx - 1);
-                rv[bq][aq] = live(aq, bq) ? F.r[kSplit ? pidx(ifn, jf, F.nx) : jf * F.nx + ifn] : (T)0;
-            }
-        }
-        // terms outside the level are selected away, not weighted by zero:
-        // their clamped load may land on a cell whose residual was never
-        // written
-        T s = (T)0;
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) {
-            const int jf = 2 * J - 1 + bq;
-            const bool jin = jf >= 0 && jf < F.ny;
-            T row = (T)0;
-#pragma unroll
-            for (int aq = 0; aq < 4; ++aq) {
-                const int ifn = 2 * I - 1 + aq;
-                const bool iin = ifn >= 0 && ifn < F.nx;
-                row += iin ? (T)rweight(I, C.nx, aq) * rv[bq][aq] : (T)0;
-            }
-            s += jin ? (T)rweight(J, C.ny, bq) * row : (T)0;
-        }
-        C.b[idx] = s;
-        C.x[idx] = (T)0;
-    }
+    if (kTBatch > 1 && ASF == 1 && C.nx * C.ny > Team::size())
+        restrict_residual_kb<T, Team, ASF, ASC, kSplit, kTBatch>(F, C);
+    else restrict_residual_kb<T, Team, ASF, ASC, kSplit, 1>(F, C);
 }
 
 // r = b - A x on one level after the pre-smoothing (operands of kRBatch
@@ -2095,21 +2260,21 @@ __global__ void henry_fields_kernel(Launch lp) {
         const double KP = K[idx], fP = phi[idx];
         if (i + 1 < nx) {
             const double KE = K[idx + 1], fE = phi[idx + 1];
-            tx[idx] = 2.0 * KP * KE / (KP + KE) / ph.mu;
-            wx[idx] = 2.0 * fP * fE / (fP + fE) * ph.D;
+            tx[idx] = face_perm(ph, KP, KE);
+            wx[idx] = face_disp(ph, fP, fE);
         } else {
-            tx[idx] = 2.0 * KP / ph.mu;
-            wx[idx] = 2.0 * fP * ph.D;
+            tx[idx] = face_perm_edge(ph, KP);
+            wx[idx] = face_disp_edge(ph, fP);
         }
         if (j + 1 < ny) {
             const double KN = K[idx + nx], fN = phi[idx + nx];
-            ty[idx] = 2.0 * KP * KN / (KP + KN) / ph.mu;
-            wy[idx] = 2.0 * fP * fN / (fP + fN) * ph.D;
+            ty[idx] = face_perm(ph, KP, KN);
+            wy[idx] = face_disp(ph, fP, fN);
         } else {
             ty[idx] = 0.0;
             wy[idx] = 0.0;
         }
-        isc[idx] = tau / (h * h * fP * ph.rho0);
+        isc[idx] = res_scale(ph, tau, h, fP);
     }
 }
 
