@@ -615,15 +615,16 @@ __device__ inline double rho_of(const Phys& ph, double c) { return ph.rho0 + (ph
 // wx = phi_f D), arithmetic rho; donor cell.
 struct FaceFlux { double M, F, lam, dif; };
 
-// Interior face a|b (b east or north of a); `buoy` = 1 on a north face,
-// where Darcy's law with gravity (0,-g) adds rho_f g h, 0 on an east face.
+// Interior face a|b (b east or north of a); on a north face Darcy's law
+// with gravity (0,-g) adds rho_f g h to the pressure difference.
+template <bool kNorth>
 __device__ inline FaceFlux flux_face(const Phys& ph, double h, double pa, double pb, double ca, double cb, double kf,
-                                     double wf, double buoy) {
+                                     double wf) {
     FaceFlux f;
     const double rf = 0.5 * (rho_of(ph, ca) + rho_of(ph, cb));
     f.lam = rf * kf;
     f.dif = rf * wf;
-    f.M = -f.lam * ((pb - pa) + buoy * (rf * ph.g * h));
+    f.M = kNorth ? -f.lam * ((pb - pa) + rf * ph.g * h) : -f.lam * (pb - pa);
     f.F = f.M * (f.M >= 0.0 ? ca : cb) - f.dif * (cb - ca);
     return f;
 }
@@ -676,51 +677,58 @@ struct PhaseClock {
 };
 
 // ------------------------------------------------------------------ FP64 residual
-// Face coefficients between cells a and b (harmonic means of K and of phi)
-// and at the right boundary, and the scale of a cell's residual in the
-// norms; the fields kernel stores them, the residual pass may form them
-// again from K and phi with the same operations.
-__device__ inline double face_perm(const Phys& ph, double Ka, double Kb) { return 2.0 * Ka * Kb / (Ka + Kb) / ph.mu; }
-__device__ inline double face_disp(const Phys& ph, double fa, double fb) { return 2.0 * fa * fb / (fa + fb) * ph.D; }
-__device__ inline double face_perm_edge(const Phys& ph, double K) { return 2.0 * K / ph.mu; }
-__device__ inline double face_disp_edge(const Phys& ph, double f) { return 2.0 * f * ph.D; }
+// Face coefficients between cells a and b: t = K_f / mu and w = phi_f D with
+// the harmonic means K_f = 2 Ka Kb / (Ka + Kb) and phi_f = 2 fa fb / (fa + fb),
+// both from one division.  At the seawater boundary (half a cell from the
+// centre) the coefficients are 2 K / mu and 2 phi D: twice the pair of the
+// cell with itself.  With the scale of a cell's residual in the norms, the
+// fields kernel stores them; the residual pass may form them again from K and
+// phi with the same operations.
+struct FacePair { double t, w; };
+__device__ inline FacePair face_pair(const Phys& ph, double Ka, double Kb, double fa, double fb) {
+    const double sK = (Ka + Kb) * ph.mu, sf = fa + fb;
+    const double r = 1.0 / (sK * sf);
+    return {2.0 * Ka * Kb * sf * r, 2.0 * fa * fb * ph.D * sK * r};
+}
 __device__ inline double res_scale(const Phys& ph, double tau, double h, double f) { return tau / (h * h * f * ph.rho0); }
 
 // Operands of one cell's residual, loaded from clamped indices before any
 // arithmetic (no loads under boundary branches).
 struct ResIn {
-    double cP, cnP, phiP, pP, cE, pE, cW, pW, cN, pN, cS, pS;
-    double txP, wxP, txW, wxW, tyP, wyP, tyS, wyS, sc;
+    double cP, cnP, phiP, pP, cE, pE, cW, pW, cN, pN;
+    double txP, wxP, txW, wxW, tyP, wyP, sc;
 };
 
 // The residual of one cell from its operands; both the interior and the
-// boundary flux of a face are formed and the applicable one selected.
+// boundary flux of a face are formed and the applicable one selected.  The
+// south face's flux fs comes in from the cell below (its north face, the same
+// operation on the same operands); the north face's goes out through fn.
 // Writes the level-0 inner arrays of `mode` and returns the scaled |R^p|,
 // |R^c| through mp, mc.
 template <typename T>
 __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, int j, const Nb& q, const ResIn& a,
-                                double& mp, double& mc) {
+                                const FaceFlux& fs, FaceFlux& fn_out, double& mp, double& mc) {
     const double h = S.h, h2t = h * h / S.tau;
     Level<T>& L0 = S.lv[0];
     const double rP = rho_of(ph, a.cP), rN = rho_of(ph, a.cnP);
     double Rp = h2t * a.phiP * (rP - rN);
     double Rc = h2t * a.phiP * (rP * a.cP - rN * a.cnP);
     // east face: interior, or the seawater boundary
-    const FaceFlux fe = flux_face(ph, h, a.pP, a.pE, a.cP, a.cE, a.txP, a.wxP, 0.0);
+    const FaceFlux fe = flux_face<false>(ph, h, a.pP, a.pE, a.cP, a.cE, a.txP, a.wxP);
     const FaceFlux fr = flux_right(ph, -1.0 + (j + 0.5) * h, a.pP, a.cP, a.txP, a.wxP);
     Rp += q.he ? fe.M : fr.M;
     Rc += q.he ? fe.F : fr.F;
     // west face: interior (flux out of the west neighbour), or recharge
-    const FaceFlux fw = flux_face(ph, h, a.pW, a.pP, a.cW, a.cP, a.txW, a.wxW, 0.0);
+    const FaceFlux fw = flux_face<false>(ph, h, a.pW, a.pP, a.cW, a.cP, a.txW, a.wxW);
     const FaceFlux fl = flux_left(ph, h, S.q, a.cP, a.phiP);
     Rp += q.hw ? -fw.M : fl.M;
     Rc += q.hw ? -fw.F : fl.F;
     // north face (the top is impermeable)
-    const FaceFlux fn = flux_face(ph, h, a.pP, a.pN, a.cP, a.cN, a.tyP, a.wyP, 1.0);
+    const FaceFlux fn = flux_face<true>(ph, h, a.pP, a.pN, a.cP, a.cN, a.tyP, a.wyP);
+    fn_out = fn;
     Rp += q.hn ? fn.M : 0.0;
     Rc += q.hn ? fn.F : 0.0;
     // south face (the bottom is impermeable)
-    const FaceFlux fs = flux_face(ph, h, a.pS, a.pP, a.cS, a.cP, a.tyS, a.wyS, 1.0);
     Rp -= q.hs ? fs.M : 0.0;
     Rc -= q.hs ? fs.F : 0.0;
     if (mode == 0) {
@@ -774,14 +782,18 @@ __device__ inline void residual_rows(const Phys& ph, Solve<T>& S, int mode, doub
             KP = S.K[jb * nx + i];
             fP = S.phi[jb * nx + i];
             if (jb > 0) {  // the first row's south face (none at j = 0)
-                const double Ks = S.K[js * nx + i], fs = S.phi[js * nx + i];
-                tyS = face_perm(ph, Ks, KP);
-                wyS = face_disp(ph, fs, fP);
+                const double Ks = S.K[js * nx + i], phs = S.phi[js * nx + i];
+                const FacePair fy = face_pair(ph, Ks, KP, phs, fP);
+                tyS = fy.t;
+                wyS = fy.w;
             }
         } else {
             tyS = S.ty[js * nx + i];
             wyS = S.wy[js * nx + i];
         }
+        // the flux through the south face of the band's first row; every
+        // later row takes it from the row below
+        FaceFlux fs = flux_face<true>(ph, S.h, pS, pP, cS, cP, tyS, wyS);
         for (int t = 0; t < band; ++t) {  // the same trip count in every lane (shuffles)
             const int j = j0 + t;
             const bool active = j < ny;
@@ -789,7 +801,7 @@ __device__ inline void residual_rows(const Phys& ph, Solve<T>& S, int mode, doub
             const Nb q(i, jc, nx, ny);
             const int idx = q.idx;
             ResIn a;
-            a.pP = pP; a.cP = cP; a.pS = pS; a.cS = cS; a.tyS = tyS; a.wyS = wyS;
+            a.pP = pP; a.cP = cP;
             a.pN = S.p[q.n]; a.cN = S.c[q.n];
             a.cnP = S.cn[idx];
             // neighbours in x: adjacent lanes, or memory at the wavefront's ends
@@ -798,18 +810,19 @@ __device__ inline void residual_rows(const Phys& ph, Solve<T>& S, int mode, doub
             if constexpr (kFields) {
                 KN = S.K[q.n];
                 fN = S.phi[q.n];
-                double KEm = 0.0, fEm = 0.0, KWm = 0.0, fWm = 0.0;
+                double KEm = 0.0, fEm = 0.0;
                 if (lane == kWave - 1) { pEm = S.p[q.e]; cEm = S.c[q.e]; KEm = S.K[q.e]; fEm = S.phi[q.e]; }
-                if (lane == 0) { pWm = S.p[q.w]; cWm = S.c[q.w]; KWm = S.K[q.w]; fWm = S.phi[q.w]; }
+                if (lane == 0) { pWm = S.p[q.w]; cWm = S.c[q.w]; txWm = S.tx[q.w]; wxWm = S.wx[q.w]; }
                 const double KEs = __shfl_down(KP, 1, kWave), fEs = __shfl_down(fP, 1, kWave);
                 const double KE = lane == kWave - 1 ? KEm : KEs, fE = lane == kWave - 1 ? fEm : fEs;
                 a.phiP = fP;
-                a.txP = q.he ? face_perm(ph, KP, KE) : face_perm_edge(ph, KP);
-                a.wxP = q.he ? face_disp(ph, fP, fE) : face_disp_edge(ph, fP);
-                a.tyP = q.hn ? face_perm(ph, KP, KN) : 0.0;
-                a.wyP = q.hn ? face_disp(ph, fP, fN) : 0.0;
+                const FacePair fx = face_pair(ph, KP, q.he ? KE : KP, fP, q.he ? fE : fP);
+                const FacePair fy = face_pair(ph, KP, KN, fP, fN);
+                a.txP = q.he ? fx.t : 2.0 * fx.t;
+                a.wxP = q.he ? fx.w : 2.0 * fx.w;
+                a.tyP = q.hn ? fy.t : 0.0;
+                a.wyP = q.hn ? fy.w : 0.0;
                 a.sc = res_scale(ph, S.tau, S.h, fP);
-                if (lane == 0) { txWm = face_perm(ph, KWm, KP); wxWm = face_disp(ph, fWm, fP); }
             } else {
                 a.phiP = S.phi[idx];
                 a.txP = S.tx[idx]; a.wxP = S.wx[idx]; a.tyP = S.ty[idx]; a.wyP = S.wy[idx];
@@ -826,9 +839,10 @@ __device__ inline void residual_rows(const Phys& ph, Solve<T>& S, int mode, doub
             a.cW = lane == 0 ? cWm : cWs;
             a.txW = lane == 0 ? txWm : txWs;
             a.wxW = lane == 0 ? wxWm : wxWs;
-            if (active) res_cell(ph, S, mode, idx, j, q, a, mp, mc);
+            FaceFlux fn = fs;
+            if (active) res_cell(ph, S, mode, idx, j, q, a, fs, fn, mp, mc);
             // carry up one row
-            pS = pP; cS = cP; tyS = a.tyP; wyS = a.wyP;
+            fs = fn;
             pP = a.pN; cP = a.cN;
             KP = KN; fP = fN;
         }
@@ -2259,17 +2273,18 @@ __global__ void henry_fields_kernel(Launch lp) {
         const int i = idx % nx, j = idx / nx;
         const double KP = K[idx], fP = phi[idx];
         if (i + 1 < nx) {
-            const double KE = K[idx + 1], fE = phi[idx + 1];
-            tx[idx] = face_perm(ph, KP, KE);
-            wx[idx] = face_disp(ph, fP, fE);
+            const FacePair fx = face_pair(ph, KP, K[idx + 1], fP, phi[idx + 1]);
+            tx[idx] = fx.t;
+            wx[idx] = fx.w;
         } else {
-            tx[idx] = face_perm_edge(ph, KP);
-            wx[idx] = face_disp_edge(ph, fP);
+            const FacePair fx = face_pair(ph, KP, KP, fP, fP);
+            tx[idx] = 2.0 * fx.t;
+            wx[idx] = 2.0 * fx.w;
         }
         if (j + 1 < ny) {
-            const double KN = K[idx + nx], fN = phi[idx + nx];
-            ty[idx] = face_perm(ph, KP, KN);
-            wy[idx] = face_disp(ph, fP, fN);
+            const FacePair fy = face_pair(ph, KP, K[idx + nx], fP, phi[idx + nx]);
+            ty[idx] = fy.t;
+            wy[idx] = fy.w;
         } else {
             ty[idx] = 0.0;
             wy[idx] = 0.0;
