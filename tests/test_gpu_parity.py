@@ -173,8 +173,12 @@ def test_cluster_sizes_are_bitwise_equal(torch_cuda, ctx, prec, predictor):
 def test_staged_line_solves_equal_the_register_path(torch_cuda, prec):
     """x-lines of 512 and 1024 cells on the cluster levels are formed from
     coalesced loads and staged through LDS; with one workgroup per solve the
-    same lines are solved from the lanes' own loads.  Both do the same
-    arithmetic: c, p, Q, status and iteration counts are bitwise equal
+    same lines are solved from the lanes' own loads.  The clusters also run
+    the 512-thread build, whose residual passes form the face coefficients
+    of these grids from K and phi and whose level transfers gather four
+    cells per thread, where the one-workgroup solves (1024-thread build)
+    load the stored coefficients and move one cell at a time.  Both do the
+    same arithmetic: c, p, Q, status and iteration counts are bitwise equal
     (512x256 and 1024x512, the first steps at the 1024x512 workload's time
     step, clusters of 2 and 8)."""
     torch = torch_cuda
