@@ -102,11 +102,19 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2302_07804_amd", "csrc", f)
 
 
 def kernel_hash() -> str:
+    """Hash of the solve kernel's sources with their comments and blank
+    lines removed: counters taken on a kernel stay valid while only its
+    comments change, and become stale with any change to its code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

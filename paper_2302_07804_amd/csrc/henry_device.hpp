@@ -55,7 +55,7 @@
 #endif
 // Grids of at least HENRY_RES_FIELDS_NX columns (0: none): the residual
 // pass forms the face coefficients and the norm scale from K and phi (5 FP64
-// loads per cell instead of 9, and seven FP64 divisions); smaller ones load
+// loads per cell instead of 9, and three FP64 divisions); smaller ones load
 // the stored ones.  Both give the same bits.
 #ifndef HENRY_RES_FIELDS_NX
 #define HENRY_RES_FIELDS_NX 0
@@ -758,7 +758,7 @@ __device__ inline void res_cell(const Phys& ph, Solve<T>& S, int mode, int idx, 
 
 // The rows of one residual pass (see residual_pass).  kFields: the face
 // coefficients and the norm scale formed from K and phi (5 FP64 loads per
-// cell instead of 9, and seven FP64 divisions), with the same operations as
+// cell instead of 9, and three FP64 divisions), with the same operations as
 // the fields kernel's stored ones, so both variants give the same bits.
 template <bool kFields, typename T>
 __device__ inline void residual_rows(const Phys& ph, Solve<T>& S, int mode, double& mp, double& mc) {
