@@ -53,6 +53,19 @@ def test_pmc_summary_round_trip(tmp_path):
     assert rec["bytes_per_launch"] == pytest.approx(((1000 + 3000) * 2.0 + (500 + 500)) * 1024 / 2)
 
 
+def test_kernel_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """The counter records' kernel hash is blind to comments and blank
+    lines, and changes with any change to the code."""
+    src = tmp_path / "k.hpp"
+    src.write_text("// note\nint f(int a) {\n    return a + 1;  /* one */\n}\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
+    h0 = bench.kernel_hash()
+    src.write_text("// another note\n\nint f(int a) {  // add one\n    return a + 1;\n}\n/* end\n */\n")
+    assert bench.kernel_hash() == h0
+    src.write_text("// note\nint f(int a) {\n    return a + 2;  /* one */\n}\n")
+    assert bench.kernel_hash() != h0
+
+
 def _fixture_record():
     """A record as main() builds it, from plausible measured values."""
     groups = [dict(nx=256, ny=128, nsolves=16, launches=1, cell_steps=16 * 32768 * 800, ms=452.1, threads=1024,
